@@ -1,0 +1,259 @@
+"""TEST INFRASTRUCTURE ONLY: the FP64 CPU oracle of the test-particle map.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``oracle.cpp`` (plain C++,
+``-O2 -ffp-contract=off``, no fast-math, OpenMP over particles) through ctypes
+and adds textbook element conversions used by the invariant tests.  It imports
+nothing from the HIP package and the HIP package imports nothing from it.
+
+Entry points (each cites the passage of Zhang & Gladman 2021 it follows):
+
+* :func:`ephemeris`  - planets by the Wisdom-Holman map in Jacobi coordinates
+  (sec. 2.2, planet integration; Jacobi definitions in sec. 2.2) writing the
+  table of heliocentric planet positions and the indirect term h0 (sec. 2.2).
+* :func:`particles`  - the test-particle leapfrog: half kick, Kepler drift by
+  the difference form of Kepler's equation with f and g functions, half kick,
+  and the encounter / escape / Kepler-failure deactivation (sec. 2.2).
+* :func:`run`        - both of the above.
+* :func:`tangent`, :func:`stm`, :func:`adjoint` - the exact derivative of the
+  discrete particle map by the complex-step method (Squire & Trapp 1998).
+* :func:`kepler_solve`, :func:`kepler_fixedk`, :func:`drift` - unit pieces.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ACTIVE, ENCOUNTER, ESCAPE, KEPLER = 0, 1, 2, 3
+KEPLER_FTOL = 1e-13
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` with g++ (strict IEEE doubles, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", _SRC, "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = C.CDLL(_LIB)
+        d, i, i64 = C.c_double, C.c_int, C.c_int64
+        P = C.c_void_p
+        lib.orc_kepler_solve.argtypes = [d, d, d, C.POINTER(i)]
+        lib.orc_kepler_solve.restype = d
+        lib.orc_kepler_fixedk.argtypes = [d, d, d, i, C.POINTER(d)]
+        lib.orc_kepler_fixedk.restype = d
+        lib.orc_drift.argtypes = [d, P, P, d, i, d, P]
+        lib.orc_drift.restype = i
+        lib.orc_ephemeris.argtypes = [d, i, P, P, P, i64, d, P, P, P]
+        lib.orc_ephemeris.restype = i64
+        lib.orc_particles.argtypes = [d, i, P, P, d, P, i64, d, i64, i, d, i64, P, P, P, P, P, i]
+        lib.orc_particles.restype = d
+        lib.orc_max_threads.argtypes = [i]
+        lib.orc_max_threads.restype = i
+        lib.orc_tangent.argtypes = [d, i, P, P, d, P, i64, d, i, d, i64, P, P, P, P, P, P, i]
+        lib.orc_tangent.restype = None
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+# ----------------------------------------------------------------- unit pieces
+def kepler_solve(ec: float, es: float, dM: float) -> tuple[float, int]:
+    """Converged root of x - ec sin x + es (1 - cos x) = dM (sec. 2.2)."""
+    it = C.c_int(0)
+    x = _load().orc_kepler_solve(float(ec), float(es), float(dM), C.byref(it))
+    return x, it.value
+
+
+def kepler_fixedk(ec: float, es: float, dM: float, k: int = 5) -> tuple[float, float]:
+    """Fixed-k Newton reference iteration; returns (x_k, F(x_k)) (sec. 2.2)."""
+    F = C.c_double(0.0)
+    x = _load().orc_kepler_fixedk(float(ec), float(es), float(dM), int(k), C.byref(F))
+    return x, F.value
+
+
+def drift(mu: float, r, v, dt: float, kfix: int = -1, ftol: float = KEPLER_FTOL):
+    """Two-body f-g drift; returns (ok, r, v, (f, g, fdot, gdot))."""
+    r = _f64(r, (3,)).copy()
+    v = _f64(v, (3,)).copy()
+    fg = np.zeros(4)
+    ok = _load().orc_drift(float(mu), _ptr(r), _ptr(v), float(dt), int(kfix), float(ftol), _ptr(fg))
+    return bool(ok), r, v, fg
+
+
+# ------------------------------------------------------------------- planets
+@dataclass
+class Ephemeris:
+    table: np.ndarray       # (nsteps+1, 3np+3): r_1..r_np, h0 (heliocentric)
+    r_final: np.ndarray     # (np, 3)
+    v_final: np.ndarray     # (np, 3)
+    flag: int               # -1 ok; >= 0 first step with a planet pair inside a mutual Hill radius; -2 drift failure
+
+
+def ephemeris(mu0: float, mu, rp, vp, nsteps: int, dt: float, keep_table: bool = True) -> Ephemeris:
+    """Planet table by the Jacobi Wisdom-Holman map (sec. 2.2)."""
+    mu = _f64(mu).reshape(-1)
+    npl = mu.shape[0]
+    rp = _f64(rp, (npl, 3))
+    vp = _f64(vp, (npl, 3))
+    table = np.zeros((nsteps + 1, 3 * npl + 3)) if keep_table else None
+    rf = np.zeros((npl, 3))
+    vf = np.zeros((npl, 3))
+    flag = _load().orc_ephemeris(float(mu0), npl, _ptr(mu), _ptr(rp), _ptr(vp), int(nsteps),
+                                 float(dt), _ptr(table) if table is not None else None,
+                                 _ptr(rf), _ptr(vf))
+    return Ephemeris(table, rf, vf, int(flag))
+
+
+# ------------------------------------------------------------------ particles
+@dataclass
+class Result:
+    r: np.ndarray
+    v: np.ndarray
+    deact_step: np.ndarray
+    reason: np.ndarray
+    planet: np.ndarray
+    seconds: float = 0.0
+
+
+def particles(mu0: float, mu, rcrit, rmax: float, table, dt: float, r, v, nsteps: int | None = None,
+              step0: int = 0, kepler_iters: int = 5, ftol: float = KEPLER_FTOL,
+              nthreads: int = 0) -> Result:
+    """Particles through the given planet table (sec. 2.2 leapfrog + deactivation)."""
+    mu = _f64(mu).reshape(-1)
+    npl = mu.shape[0]
+    rcrit = _f64(rcrit).reshape(-1)
+    table = _f64(table)
+    if nsteps is None:
+        nsteps = table.shape[0] - 1
+    assert table.shape == (nsteps + 1, 3 * npl + 3) or table.shape[0] >= nsteps + 1
+    r = _f64(r).reshape(-1, 3).copy()
+    v = _f64(v).reshape(-1, 3).copy()
+    n = r.shape[0]
+    ds = np.zeros(n, dtype=np.int64)
+    rs = np.zeros(n, dtype=np.int32)
+    pl = np.zeros(n, dtype=np.int32)
+    secs = _load().orc_particles(float(mu0), npl, _ptr(mu), _ptr(rcrit), float(rmax), _ptr(table),
+                                 int(nsteps), float(dt), int(step0), int(kepler_iters), float(ftol),
+                                 n, _ptr(r), _ptr(v), _ptr(ds), _ptr(rs), _ptr(pl), int(nthreads))
+    return Result(r, v, ds, rs, pl, secs)
+
+
+def run(w, nsteps: int | None = None, nthreads: int = 0):
+    """Ephemeris + particles for a workload object (see the package's workloads)."""
+    nsteps = w.nsteps if nsteps is None else nsteps
+    eph = ephemeris(w.mu0, w.mu, w.rp, w.vp, nsteps, w.dt)
+    res = particles(w.mu0, w.mu, w.rcrit, w.rmax, eph.table, w.dt, w.r, w.v, nsteps,
+                    kepler_iters=w.kepler_iters, nthreads=nthreads)
+    return eph, res
+
+
+def max_threads(nthreads: int = 0) -> int:
+    return int(_load().orc_max_threads(int(nthreads)))
+
+
+# ------------------------------------------------------------- derivatives
+def tangent(mu0, mu, rcrit, rmax, table, dt, r, v, dr, dv, nsteps=None, kepler_iters=5,
+            ftol=KEPLER_FTOL, nthreads=0):
+    """Directional derivative of the final (r, v) of each particle along (dr, dv),
+    exact to rounding by the complex step."""
+    mu = _f64(mu).reshape(-1)
+    npl = mu.shape[0]
+    rcrit = _f64(rcrit).reshape(-1)
+    table = _f64(table)
+    if nsteps is None:
+        nsteps = table.shape[0] - 1
+    r, v, dr, dv = (_f64(x).reshape(-1, 3) for x in (r, v, dr, dv))
+    n = r.shape[0]
+    dro = np.zeros((n, 3))
+    dvo = np.zeros((n, 3))
+    _load().orc_tangent(float(mu0), npl, _ptr(mu), _ptr(rcrit), float(rmax), _ptr(table),
+                        int(nsteps), float(dt), int(kepler_iters), float(ftol), n, _ptr(r),
+                        _ptr(v), _ptr(dr), _ptr(dv), _ptr(dro), _ptr(dvo), int(nthreads))
+    return dro, dvo
+
+
+def stm(mu0, mu, rcrit, rmax, table, dt, r, v, nsteps=None, kepler_iters=5, nthreads=0):
+    """6x6 state-transition matrix d(r_T, v_T)/d(r_0, v_0) per particle, (n, 6, 6)."""
+    r = _f64(r).reshape(-1, 3)
+    n = r.shape[0]
+    M = np.zeros((n, 6, 6))
+    for c in range(6):
+        w = np.zeros((n, 6))
+        w[:, c] = 1.0
+        dro, dvo = tangent(mu0, mu, rcrit, rmax, table, dt, r, v, w[:, :3], w[:, 3:], nsteps,
+                           kepler_iters, nthreads=nthreads)
+        M[:, :3, c] = dro
+        M[:, 3:, c] = dvo
+    return M
+
+
+def adjoint(mu0, mu, rcrit, rmax, table, dt, r, v, gr, gv, nsteps=None, kepler_iters=5, nthreads=0):
+    """Vector-Jacobian product: (dL/dr_0, dL/dv_0) = M^T (dL/dr_T, dL/dv_T)."""
+    M = stm(mu0, mu, rcrit, rmax, table, dt, r, v, nsteps, kepler_iters, nthreads)
+    lam = np.concatenate([_f64(gr).reshape(-1, 3), _f64(gv).reshape(-1, 3)], axis=1)
+    g = np.einsum("nij,ni->nj", M, lam)
+    return g[:, :3], g[:, 3:]
+
+
+# ----------------------------------------------------- textbook element helpers
+def cartesian_to_elements(mu, r, v):
+    """Heliocentric (r, v) -> (a, e, inc, node, peri, M), textbook relations."""
+    r = np.atleast_2d(_f64(r))
+    v = np.atleast_2d(_f64(v))
+    mu = np.broadcast_to(np.asarray(mu, dtype=np.float64), r.shape[:1])
+    rn = np.linalg.norm(r, axis=1)
+    v2 = np.sum(v * v, axis=1)
+    h = np.cross(r, v)
+    hn = np.linalg.norm(h, axis=1)
+    a = 1.0 / (2.0 / rn - v2 / mu)
+    evec = np.cross(v, h) / mu[:, None] - r / rn[:, None]
+    e = np.linalg.norm(evec, axis=1)
+    inc = np.arccos(np.clip(h[:, 2] / hn, -1.0, 1.0))
+    node = np.arctan2(h[:, 0], -h[:, 1])
+    nvec = np.stack([np.cos(node), np.sin(node), np.zeros_like(node)], axis=1)
+    # argument of pericentre, measured in the orbital plane from the node line
+    hz = h / hn[:, None]
+    mvec = np.cross(hz, nvec)
+    peri = np.arctan2(np.sum(evec * mvec, axis=1), np.sum(evec * nvec, axis=1))
+    # eccentric anomaly from e cos E = 1 - r/a, e sin E = r.v / sqrt(mu a)
+    ecE = 1.0 - rn / a
+    esE = np.sum(r * v, axis=1) / np.sqrt(mu * a)
+    E = np.arctan2(esE, ecE)
+    M = E - esE
+    return a, e, inc, node, peri, M
+
+
+def wrap_angle(x):
+    return (np.asarray(x) + math.pi) % (2 * math.pi) - math.pi

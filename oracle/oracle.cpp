@@ -1,0 +1,453 @@
+// TEST INFRASTRUCTURE ONLY -- the plain, slow FP64 CPU oracle.
+//
+// Only the tests, the package's smoke check and the benchmark's CPU-baseline
+// leg may load this library.  It shares no code, header, table or constant
+// generator with the HIP path; it is compiled by g++ with -ffp-contract=off and
+// without fast-math, so every operation is one IEEE-754 double rounding.
+//
+// What it computes (Zhang & Gladman, "GLISSE", New Astronomy 2021):
+//   * sec. 2.2, eq. (H = H_Kepler + H_int): each test particle is advanced by the
+//     Wisdom-Holman mixed-variable symplectic leapfrog -- half kick from H_int,
+//     Kepler drift about the central mass for a full step, half kick.
+//   * sec. 2.2, difference form of Kepler's equation: the drift solves
+//     x - ec sin x + es (1 - cos x) = dM for the change x of eccentric anomaly
+//     (ec = e cos E0, es = e sin E0) and applies the f and g functions.
+//   * sec. 2.2, kick equation: dv/dt = h0 - sum_j mu_j (r - r_j)/|r - r_j|^3 with
+//     the indirect term h0 = -sum_j mu_j r_j/|r_j|^3 (sec. 2.2, "common
+//     heliocentric force").
+//   * sec. 2.2: planets are integrated once with the standard Wisdom-Holman map
+//     in Jacobi coordinates; every particle shares their positions.
+//   * sec. 2.2, close-encounter paragraphs: a particle is frozen on close approach
+//     (fixed distance or Hill multiple), recording which planet removed it; a
+//     particle whose fixed-iteration Kepler solve does not converge is frozen too.
+//
+// Readings where the paper is silent (all listed in the design notes):
+//   kick-drift-kick with planet rows at t_n and t_{n+1}; checks at every step
+//   boundary on the synchronised state (r_n, v_n); precedence encounter > escape
+//   > Kepler failure; lowest planet index wins; strict < and >; unbound drift or
+//   |F(x_k)| > kepler_ftol after the fixed-k reference iteration -> Kepler
+//   failure; dM reduced to (-pi, pi].
+//
+// The particle map is a template over the scalar type so the same code, run on
+// std::complex<double>, yields the exact derivative of the discrete map by the
+// complex-step method (Squire & Trapp 1998): every branch decides on real parts.
+// The tangent, the state-transition matrix and the adjoint (its transpose) of
+// the oracle all come from that.
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <chrono>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+using cplx = std::complex<double>;
+
+inline double re(double x) { return x; }
+inline double re(const cplx& x) { return x.real(); }
+
+const double kTwoPi = 2.0 * M_PI;
+
+enum { ACTIVE = 0, ENCOUNTER = 1, ESCAPE = 2, KEPLER = 3 };
+
+// ---------------------------------------------------------------------------
+// Kepler's equation in difference form (sec. 2.2):
+//   F(x) = x - ec sin x + es (1 - cos x) - dM,  F'(x) = 1 - ec cos x + es sin x.
+// Since ec sin x - es (1 - cos x) = e [sin(E0 + x) - sin E0], the root obeys
+// |x - dM| <= 2e, and F' >= 1 - e > 0 makes it unique for e < 1.
+// ---------------------------------------------------------------------------
+template <class T>
+inline T kep_F(const T& x, const T& ec, const T& es, const T& dM) {
+  return x - ec * std::sin(x) + es * (1.0 - std::cos(x)) - dM;
+}
+template <class T>
+inline T kep_dF(const T& x, const T& ec, const T& es) {
+  return 1.0 - ec * std::cos(x) + es * std::sin(x);
+}
+
+// Fixed-k reference iteration (sec. 2.2: a fixed number of Newton iterations,
+// five by default, from a starting guess).  Starter: the second-order series
+// solution of F = 0 for small dM, clamped to the bracket dM +- 2(|ec| + |es|)
+// (a valid bracket since |ec| + |es| >= e).  Returns x_k.
+template <class T>
+T kep_fixedk(const T& ec, const T& es, const T& dM, int k) {
+  T om = 1.0 - ec;
+  T x = dM / om - es * dM * dM / (2.0 * om * om * om);
+  double w = 2.0 * (std::fabs(re(ec)) + std::fabs(re(es)));
+  if (re(x) > re(dM) + w) x = dM + w;
+  if (re(x) < re(dM) - w) x = dM - w;
+  for (int i = 0; i < k; ++i) x = x - kep_F(x, ec, es, dM) / kep_dF(x, ec, es);
+  return x;
+}
+
+// Converged solution: Newton safeguarded by bisection inside the bracket
+// [dM - 2e, dM + 2e], stopped when a Newton correction is within 2 ulp of x,
+// then one last Newton step (which also converges the imaginary part in the
+// complex-step instantiation).
+template <class T>
+T kep_solve(const T& ec, const T& es, const T& dM, int* iters) {
+  double e = std::sqrt(re(ec) * re(ec) + re(es) * re(es));
+  double lo = re(dM) - 2.0 * e, hi = re(dM) + 2.0 * e;
+  T x = kep_fixedk(ec, es, dM, 0);
+  int it = 0;
+  for (; it < 100; ++it) {
+    T F = kep_F(x, ec, es, dM);
+    if (re(F) == 0.0) break;
+    if (re(F) < 0.0) lo = std::fmax(lo, re(x)); else hi = std::fmin(hi, re(x));
+    T xn = x - F / kep_dF(x, ec, es);
+    if (!(re(xn) > lo && re(xn) < hi)) {
+      if (hi - lo <= 4.0 * std::ldexp(std::fabs(re(x)) + 1e-300, -52)) break;
+      xn = T(0.5 * (lo + hi));
+    }
+    double dx = std::fabs(re(xn) - re(x));
+    x = xn;
+    if (dx <= 2.0 * std::ldexp(std::fabs(re(x)), -52)) break;
+  }
+  x = x - kep_F(x, ec, es, dM) / kep_dF(x, ec, es);
+  if (iters) *iters = it;
+  return x;
+}
+
+struct KepOut {
+  int ok;
+  double f, g, fd, gd;
+};
+
+// Two-body drift of (r, v) about a mass mu for time dt with the f and g
+// functions (sec. 2.2, drift step; the element <-> Cartesian conversions of the
+// paper's steps 2 and 4 are carried by f, g).  Returns 0 (and leaves r, v
+// alone) when the orbit is unbound (alpha <= 0) or when the fixed-k reference
+// iteration leaves |F(x_k)| > ftol (kfix < 0 skips that test).
+template <class T>
+int drift(double mu, T r[3], T v[3], double dt, int kfix, double ftol, KepOut* dbg = nullptr) {
+  T r0 = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  T v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  T u = r[0] * v[0] + r[1] * v[1] + r[2] * v[2];
+  T alpha = 2.0 / r0 - v2 / mu;            // 1/a
+  if (!(re(alpha) > 0.0)) return 0;
+  T a = 1.0 / alpha;
+  T n = std::sqrt(mu * alpha) * alpha;     // sqrt(mu / a^3)
+  T ec = 1.0 - r0 * alpha;                 // e cos E0
+  T es = u * std::sqrt(alpha / mu);        // e sin E0
+  T dM = n * dt;
+  T dte = dt;
+  double q = std::rint(re(dM) / kTwoPi);
+  if (q != 0.0) {                          // reduce dM to (-pi, pi]
+    dM = dM - q * kTwoPi;
+    dte = dM / n;
+  }
+  if (kfix >= 0) {
+    T xk = kep_fixedk(ec, es, dM, kfix);
+    if (!(std::fabs(re(kep_F(xk, ec, es, dM))) <= ftol)) return 0;
+  }
+  T x = kep_solve(ec, es, dM, nullptr);
+  T s = std::sin(x), c = std::cos(x);
+  T r1 = a * (1.0 - ec * c + es * s);
+  T f = 1.0 + (a / r0) * (c - 1.0);
+  T g = dte + (s - x) / n;
+  T fd = -(a * a * n * s) / (r1 * r0);
+  T gd = 1.0 + (a / r1) * (c - 1.0);
+  T rn[3], vn[3];
+  for (int k = 0; k < 3; ++k) {
+    rn[k] = f * r[k] + g * v[k];
+    vn[k] = fd * r[k] + gd * v[k];
+  }
+  for (int k = 0; k < 3; ++k) { r[k] = rn[k]; v[k] = vn[k]; }
+  if (dbg) { dbg->ok = 1; dbg->f = re(f); dbg->g = re(g); dbg->fd = re(fd); dbg->gd = re(gd); }
+  return 1;
+}
+
+// ---------------------------------------------------------------------------
+// Particle kick acceleration from one planet-table row (sec. 2.2 kick equation):
+//   a = h0 - sum_j mu_j (r - r_j) / |r - r_j|^3.
+// Also returns the lowest planet index j with |r - r_j| < rcrit_j, or -1.
+// Row layout: r_1 (3), ..., r_np (3), h0 (3), heliocentric.
+// ---------------------------------------------------------------------------
+template <class T>
+int kick_accel(const double* row, int np, const double* mu, const double* rcrit,
+               const T r[3], T acc[3]) {
+  int hit = -1;
+  const double* h0 = row + 3 * np;
+  for (int k = 0; k < 3; ++k) acc[k] = T(h0[k]);
+  for (int j = 0; j < np; ++j) {
+    T d[3];
+    for (int k = 0; k < 3; ++k) d[k] = r[k] - row[3 * j + k];
+    T d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    T dist = std::sqrt(d2);
+    if (hit < 0 && re(dist) < rcrit[j]) hit = j;
+    T d3 = d2 * dist;
+    for (int k = 0; k < 3; ++k) acc[k] = acc[k] - mu[j] * d[k] / d3;
+  }
+  return hit;
+}
+
+struct Deact {
+  int64_t step;
+  int32_t reason;
+  int32_t planet;
+};
+
+// One particle through rows 0..nsteps of a table that starts at global step
+// step0.  Checks run at every boundary on the synchronised state; on a hit the
+// state of that boundary is kept.
+template <class T>
+Deact run_particle(double mu0, int np, const double* mu, const double* rcrit, double rmax,
+                   const double* table, int64_t nsteps, double dt, int64_t step0,
+                   int kfix, double ftol, T r[3], T v[3]) {
+  const int rowlen = 3 * np + 3;
+  const double h = 0.5 * dt;
+  T acc[3];
+  int hit = kick_accel(table, np, mu, rcrit, r, acc);
+  auto escaped = [&](const T* rr) {
+    T r2 = rr[0] * rr[0] + rr[1] * rr[1] + rr[2] * rr[2];
+    return rmax > 0.0 && re(std::sqrt(r2)) > rmax;
+  };
+  if (hit >= 0) return {step0, ENCOUNTER, hit};
+  if (escaped(r)) return {step0, ESCAPE, -1};
+  for (int64_t i = 0; i < nsteps; ++i) {
+    T rn[3], vn[3];
+    for (int k = 0; k < 3; ++k) { rn[k] = r[k]; vn[k] = v[k] + h * acc[k]; }
+    if (!drift(mu0, rn, vn, dt, kfix, ftol)) return {step0 + i, KEPLER, -1};
+    hit = kick_accel(table + (i + 1) * rowlen, np, mu, rcrit, rn, acc);
+    for (int k = 0; k < 3; ++k) { r[k] = rn[k]; v[k] = vn[k] + h * acc[k]; }
+    if (hit >= 0) return {step0 + i + 1, ENCOUNTER, hit};
+    if (escaped(r)) return {step0 + i + 1, ESCAPE, -1};
+  }
+  return {-1, ACTIVE, -1};
+}
+
+// ---------------------------------------------------------------------------
+// Planet ephemeris: Wisdom-Holman map in Jacobi coordinates (sec. 2.2; Jacobi
+// definitions as in sec. 2.2's coordinate list, with eta_i = sum_{j<=i} m_j).
+// Bodies are 0 (central mass, heliocentric origin) and 1..np (sorted by a).
+// ---------------------------------------------------------------------------
+struct Planets {
+  int np;
+  double mu0;
+  std::vector<double> mu;    // mu[0] = mu0, mu[j] = G m_j (j = 1..np)
+  std::vector<double> eta;   // eta[j] = sum_{k<=j} mu[k]
+  std::vector<double> rj, vj;  // Jacobi r', v' for j = 1..np at index 3(j-1)
+};
+
+// Heliocentric positions from Jacobi: r_j = r'_j + R_{j-1},
+// R_j = (eta_{j-1} R_{j-1} + mu_j r_j) / eta_j, R_0 = 0.
+void jacobi_to_helio(const Planets& P, const double* rj, double* rh) {
+  double R[3] = {0, 0, 0};
+  for (int j = 1; j <= P.np; ++j) {
+    for (int k = 0; k < 3; ++k) rh[3 * (j - 1) + k] = rj[3 * (j - 1) + k] + R[k];
+    for (int k = 0; k < 3; ++k)
+      R[k] = (P.eta[j - 1] * R[k] + P.mu[j] * rh[3 * (j - 1) + k]) / P.eta[j];
+  }
+}
+
+// Jacobi from heliocentric: r'_j = r_j - (sum_{k=1}^{j-1} mu_k r_k) / eta_{j-1}.
+void helio_to_jacobi(const Planets& P, const double* rh, double* rj) {
+  for (int j = 1; j <= P.np; ++j) {
+    double S[3] = {0, 0, 0};
+    for (int k = 1; k < j; ++k)
+      for (int c = 0; c < 3; ++c) S[c] += P.mu[k] * rh[3 * (k - 1) + c];
+    for (int c = 0; c < 3; ++c) rj[3 * (j - 1) + c] = rh[3 * (j - 1) + c] - S[c] / P.eta[j - 1];
+  }
+}
+
+// Interaction acceleration of each Jacobi body (the kick part of the map):
+//   a'_j = a_j - (sum_{k=0}^{j-1} mu_k a_k) / eta_{j-1} + mu'_j r'_j / |r'_j|^3,
+// with a_k the full Newtonian acceleration of body k (body 0 at the origin) and
+// mu'_j = mu0 eta_j / eta_{j-1} the Jacobi Kepler constant.
+void jacobi_int_accel(const Planets& P, const double* rj, double* aj) {
+  const int np = P.np;
+  std::vector<double> pos(3 * (np + 1), 0.0), a(3 * (np + 1), 0.0);
+  jacobi_to_helio(P, rj, pos.data() + 3);
+  for (int k = 0; k <= np; ++k)
+    for (int l = 0; l <= np; ++l) {
+      if (l == k) continue;
+      double d[3];
+      for (int c = 0; c < 3; ++c) d[c] = pos[3 * k + c] - pos[3 * l + c];
+      double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      double d3 = d2 * std::sqrt(d2);
+      for (int c = 0; c < 3; ++c) a[3 * k + c] -= P.mu[l] * d[c] / d3;
+    }
+  for (int j = 1; j <= np; ++j) {
+    double S[3] = {0, 0, 0};
+    for (int k = 0; k < j; ++k)
+      for (int c = 0; c < 3; ++c) S[c] += P.mu[k] * a[3 * k + c];
+    const double* r = rj + 3 * (j - 1);
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double r3 = r2 * std::sqrt(r2);
+    double mup = P.mu0 * P.eta[j] / P.eta[j - 1];
+    for (int c = 0; c < 3; ++c)
+      aj[3 * (j - 1) + c] = a[3 * j + c] - S[c] / P.eta[j - 1] + mup * r[c] / r3;
+  }
+}
+
+// Table row: heliocentric r_1..r_np and h0 = -sum_j mu_j r_j / |r_j|^3.
+void write_row(const Planets& P, double* row) {
+  jacobi_to_helio(P, P.rj.data(), row);
+  double h0[3] = {0, 0, 0};
+  for (int j = 1; j <= P.np; ++j) {
+    const double* r = row + 3 * (j - 1);
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double r3 = r2 * std::sqrt(r2);
+    for (int c = 0; c < 3; ++c) h0[c] -= P.mu[j] * r[c] / r3;
+  }
+  for (int c = 0; c < 3; ++c) row[3 * P.np + c] = h0[c];
+}
+
+// Any pair closer than one mutual Hill radius ((mu_i+mu_j)/(3 mu0))^(1/3) times
+// the mean of their heliocentric distances.
+bool planets_too_close(const Planets& P, const double* rh) {
+  for (int i = 1; i <= P.np; ++i)
+    for (int j = i + 1; j <= P.np; ++j) {
+      const double* a = rh + 3 * (i - 1);
+      const double* b = rh + 3 * (j - 1);
+      double d2 = 0, ra2 = 0, rb2 = 0;
+      for (int c = 0; c < 3; ++c) {
+        d2 += (a[c] - b[c]) * (a[c] - b[c]);
+        ra2 += a[c] * a[c];
+        rb2 += b[c] * b[c];
+      }
+      double rh_m = std::cbrt((P.mu[i] + P.mu[j]) / (3.0 * P.mu0)) * 0.5 *
+                    (std::sqrt(ra2) + std::sqrt(rb2));
+      if (std::sqrt(d2) < rh_m) return true;
+    }
+  return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+// ----------------------------- unit-level entry points ----------------------
+double orc_kepler_solve(double ec, double es, double dM, int* iters) {
+  return kep_solve<double>(ec, es, dM, iters);
+}
+double orc_kepler_fixedk(double ec, double es, double dM, int k, double* F) {
+  double x = kep_fixedk<double>(ec, es, dM, k);
+  if (F) *F = kep_F<double>(x, ec, es, dM);
+  return x;
+}
+// Drift of a single two-body orbit (kfix < 0: no fixed-k decision).  fg[4] gets
+// f, g, fdot, gdot when non-null.  Returns 1 on success, 0 on Kepler failure.
+int orc_drift(double mu, double* r, double* v, double dt, int kfix, double ftol, double* fg) {
+  KepOut o{};
+  int ok = drift<double>(mu, r, v, dt, kfix, ftol, &o);
+  if (fg && ok) { fg[0] = o.f; fg[1] = o.g; fg[2] = o.fd; fg[3] = o.gd; }
+  return ok;
+}
+
+// ----------------------------- planet ephemeris -----------------------------
+// mu0; np planets with mu[np], heliocentric r[np*3], v[np*3] (sorted by a).
+// Writes table[(nsteps+1) * (3np+3)] (row n = state at t_n) and the final
+// heliocentric r_out, v_out.  Returns the first step at which two planets were
+// within a mutual Hill radius, -2 if a planet's drift failed, else -1.
+int64_t orc_ephemeris(double mu0, int np, const double* mu, const double* r, const double* v,
+                      int64_t nsteps, double dt, double* table, double* r_out, double* v_out) {
+  Planets P;
+  P.np = np;
+  P.mu0 = mu0;
+  P.mu.assign(np + 1, 0.0);
+  P.eta.assign(np + 1, 0.0);
+  P.mu[0] = mu0;
+  P.eta[0] = mu0;
+  for (int j = 1; j <= np; ++j) { P.mu[j] = mu[j - 1]; P.eta[j] = P.eta[j - 1] + P.mu[j]; }
+  P.rj.assign(3 * np, 0.0);
+  P.vj.assign(3 * np, 0.0);
+  helio_to_jacobi(P, r, P.rj.data());
+  helio_to_jacobi(P, v, P.vj.data());
+  const int rowlen = 3 * np + 3;
+  int64_t flag = -1;
+  if (table) write_row(P, table);
+  {
+    std::vector<double> rh(3 * np);
+    jacobi_to_helio(P, P.rj.data(), rh.data());
+    if (np > 0 && planets_too_close(P, rh.data())) flag = 0;
+  }
+  std::vector<double> aj(3 * np), rh(3 * np);
+  const double h = 0.5 * dt;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    jacobi_int_accel(P, P.rj.data(), aj.data());
+    for (int i = 0; i < 3 * np; ++i) P.vj[i] = P.vj[i] + h * aj[i];
+    for (int j = 1; j <= np; ++j) {
+      double mup = mu0 * P.eta[j] / P.eta[j - 1];
+      if (!drift<double>(mup, &P.rj[3 * (j - 1)], &P.vj[3 * (j - 1)], dt, -1, 0.0) && flag == -1)
+        flag = -2;
+    }
+    jacobi_int_accel(P, P.rj.data(), aj.data());
+    for (int i = 0; i < 3 * np; ++i) P.vj[i] = P.vj[i] + h * aj[i];
+    if (table) write_row(P, table + (s + 1) * rowlen);
+    jacobi_to_helio(P, P.rj.data(), rh.data());
+    if (flag == -1 && np > 1 && planets_too_close(P, rh.data())) flag = s + 1;
+  }
+  if (r_out) jacobi_to_helio(P, P.rj.data(), r_out);
+  if (v_out) jacobi_to_helio(P, P.vj.data(), v_out);
+  return flag;
+}
+
+// ----------------------------- test particles -------------------------------
+// Advances n particles (AoS r[n*3], v[n*3], in/out) through the table rows
+// 0..nsteps (row 0 = global step step0).  Writes deact_step (-1 = survived),
+// reason and planet (-1 if none).  Returns wall seconds of the particle loop.
+double orc_particles(double mu0, int np, const double* mu, const double* rcrit, double rmax,
+                     const double* table, int64_t nsteps, double dt, int64_t step0,
+                     int kfix, double ftol, int64_t n, double* r, double* v,
+                     int64_t* deact_step, int32_t* reason, int32_t* planet, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  auto t0 = std::chrono::steady_clock::now();
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; ++i) {
+    Deact d = run_particle<double>(mu0, np, mu, rcrit, rmax, table, nsteps, dt, step0, kfix,
+                                   ftol, r + 3 * i, v + 3 * i);
+    deact_step[i] = d.step;
+    reason[i] = d.reason;
+    planet[i] = d.planet;
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  return std::chrono::duration<double>(t1 - t0).count();
+}
+
+// Number of OpenMP threads a parallel region would use.
+int orc_max_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  return omp_get_max_threads();
+#else
+  (void)nthreads;
+  return 1;
+#endif
+}
+
+// Tangent of the particle map by the complex step: for each particle i the
+// directional derivative of its final (r, v) along (dr[i], dv[i]) is written to
+// dr_out, dv_out.  r, v are the initial states (not modified).  A particle
+// deactivated at step n has the derivative of its frozen state (r_n, v_n).
+void orc_tangent(double mu0, int np, const double* mu, const double* rcrit, double rmax,
+                 const double* table, int64_t nsteps, double dt, int kfix, double ftol,
+                 int64_t n, const double* r, const double* v, const double* dr, const double* dv,
+                 double* dr_out, double* dv_out, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  const double hstep = 1e-100;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n; ++i) {
+    cplx rc[3], vc[3];
+    for (int k = 0; k < 3; ++k) {
+      rc[k] = cplx(r[3 * i + k], hstep * dr[3 * i + k]);
+      vc[k] = cplx(v[3 * i + k], hstep * dv[3 * i + k]);
+    }
+    run_particle<cplx>(mu0, np, mu, rcrit, rmax, table, nsteps, dt, 0, kfix, ftol, rc, vc);
+    for (int k = 0; k < 3; ++k) {
+      dr_out[3 * i + k] = rc[k].imag() / hstep;
+      dv_out[3 * i + k] = vc[k].imag() / hstep;
+    }
+  }
+}
+
+}  // extern "C"
