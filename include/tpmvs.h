@@ -1,0 +1,155 @@
+/* tpmvs -- FP64 test-particle mixed-variable symplectic integrator for AMD
+ * MI355X (gfx950).
+ *
+ * The method is that of Zhang & Gladman 2021 ("GLISSE", New Astronomy), sec. 2:
+ * N massless test particles move in the field of a central mass m0 and Np
+ * planets.  The planets are integrated once by the Wisdom-Holman map in Jacobi
+ * coordinates (sec. 2.2, planet integration) and their heliocentric positions
+ * plus the indirect term h0 = -sum_j mu_j r_j/|r_j|^3 are shared by every
+ * particle (sec. 2.2).  Each particle step is a half kick
+ *   dv/dt = h0 - sum_j mu_j (r - r_j)/|r - r_j|^3   (sec. 2.2, kick equation),
+ * a Kepler drift about m0 for the full step solved by a fixed number of Newton
+ * iterations of the difference form of Kepler's equation with f and g
+ * functions (sec. 2.2), and a second half kick.  A particle is removed on close
+ * approach to a planet (sec. 2.2, encounter criterion), on escape beyond
+ * r_escape, or when its fixed-count Kepler solve does not converge (sec. 2.2),
+ * and its state at that step boundary is kept.
+ *
+ * Conventions for every call:
+ *  - Units are the caller's: mu = G m and dt must be consistent.
+ *  - Vectors are row-major [n][3] float64 arrays (x, y, z), heliocentric.
+ *  - The caller owns every buffer.  Inputs are copied before the call returns;
+ *    outputs are written into caller buffers; no pointer is kept.
+ *  - Return value: TPM_OK (0) or a negative TPM_E* code; tpm_last_error()
+ *    then describes the failure.  Nothing is thrown or aborted across the ABI.
+ *  - A tpm_sim is used by one host thread at a time.
+ */
+#ifndef TPMVS_H
+#define TPMVS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tpm_sim tpm_sim;
+
+enum {
+  TPM_OK = 0,
+  TPM_EINVAL = -1,   /* bad argument: NaN/Inf, size out of range, np > 8 ... */
+  TPM_ENOMEM = -2,   /* device or host allocation failed                    */
+  TPM_EDEVICE = -3,  /* HIP runtime error or no usable gfx950 device         */
+  TPM_ESTATE = -4,   /* call out of order (e.g. integrate before set_*)      */
+  TPM_EPLANET = -5   /* planets approached within a mutual Hill radius, or a
+                        planet orbit became unbound: the planet map assumes no
+                        planet-planet encounters (sec. 2.2).  The integration
+                        was still carried out; results are returned.         */
+};
+
+/* Removal reasons (sec. 2.2, close-encounter and non-convergence paragraphs). */
+enum {
+  TPM_ACTIVE = 0,     /* still integrated                                   */
+  TPM_ENCOUNTER = 1,  /* |r - r_j| < r_crit_j at a step boundary            */
+  TPM_ESCAPE = 2,     /* |r| > r_escape at a step boundary                  */
+  TPM_KEPLER = 3      /* unbound orbit, or |F(x_k)| > kepler_ftol after the
+                         fixed kepler_iters Newton steps                      */
+};
+
+typedef struct {
+  int32_t kepler_iters;   /* fixed Newton iterations per drift (sec. 2.2: five); default 5 */
+  int32_t chunk_steps;    /* steps per particle launch ("planetary chunk", sec. 2.2); 0 = 1024 */
+  int32_t resync_chunks;  /* chunks between compactions ("resync interval", sec. 2.2); 0 = 4 */
+  int32_t block_threads;  /* particle-kernel workgroup size (64..256, multiple of 64); 0 = 64 */
+  double r_escape;        /* remove when |r| > r_escape; <= 0 disables                */
+  double kepler_ftol;     /* Kepler-failure threshold on |F(x_k)|; 0 = 1e-13         */
+  int32_t device;         /* HIP device ordinal                                      */
+  int32_t time_kernels;   /* 1: bracket every particle launch with HIP events        */
+} tpm_options;
+
+typedef struct {
+  int64_t step;                   /* global step reached                          */
+  int64_t n_particles;
+  int64_t n_active;               /* particles still active                       */
+  int64_t active_particle_steps;  /* particle-steps done while active, last integrate */
+  double wall_ms;                 /* last integrate, host wall clock incl. sync   */
+  double particle_ms;             /* last integrate, HIP events on the particle stream */
+  double ephemeris_ms;            /* last integrate, HIP events on the ephemeris stream */
+  int64_t chunks;                 /* particle launches in the last integrate      */
+  double particle_kernel_ms;      /* last integrate, sum of HIP-event durations of the
+                                     particle launches alone (only with time_kernels) */
+  int64_t compactions;            /* compactions in the last integrate            */
+  int64_t count_by_reason[4];     /* over all particles                           */
+} tpm_stats;
+
+/* Fill *opt with the defaults listed above. */
+void tpm_default_options(tpm_options* opt);
+
+/* Create a simulation on opt->device (opt may be NULL for defaults).
+ * TPM_EDEVICE if the device cannot be used. */
+int tpm_create(const tpm_options* opt, tpm_sim** out);
+void tpm_destroy(tpm_sim* sim);
+
+/* Central mass mu0 = G m0 > 0.  Must precede tpm_set_planets. */
+int tpm_set_central(tpm_sim* sim, double mu0);
+
+/* np (0..8) planets: mu[np] = G m_j > 0, heliocentric r[np][3], v[np][3], and
+ * the encounter radius r_crit[np] >= 0 of each (a fixed distance or a Hill
+ * multiple, sec. 2.2; see tpm_hill_radius).  Planets may be given in any order;
+ * they are integrated sorted by osculating semi-major axis (the Jacobi order of
+ * sec. 2.2) but every output uses the caller's order.  Resets the step count. */
+int tpm_set_planets(tpm_sim* sim, int32_t np, const double* mu, const double* r,
+                    const double* v, const double* r_crit);
+
+/* n particles, heliocentric r[n][3], v[n][3]; all active.  0 <= n < 2^31. */
+int tpm_set_particles(tpm_sim* sim, int64_t n, const double* r, const double* v);
+
+/* Advance planets and particles by nsteps steps of dt (dt < 0 integrates
+ * backwards).  Checks run at every step boundary, including the first and last.
+ * Calling it twice with T1 and T2 steps gives bit-identical results to one call
+ * with T1 + T2 steps. */
+int tpm_integrate(tpm_sim* sim, int64_t nsteps, double dt);
+
+/* Particle results in the caller's order (any pointer may be NULL): r, v [n][3]
+ * (removed particles keep the state of their removal step), deact_step[n]
+ * (-1 while active), reason[n] (TPM_ACTIVE...), planet[n] (caller index of the
+ * planet for TPM_ENCOUNTER, else -1). */
+int tpm_get_particles(tpm_sim* sim, double* r, double* v, int64_t* deact_step,
+                      int32_t* reason, int32_t* planet);
+
+/* Current heliocentric planet state, caller order, r[np][3], v[np][3]. */
+int tpm_get_planets(tpm_sim* sim, double* r, double* v);
+
+int tpm_get_stats(tpm_sim* sim, tpm_stats* out);
+
+/* Hill radius a_p (mu_p / (3 mu0))^(1/3) (sec. 2.2, encounter criterion). */
+double tpm_hill_radius(double mu0, double mu_p, double a_p);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* tpm_last_error(void);
+
+/* ---- planet table ---------------------------------------------------------
+ * Run the planet map from the current planet state for nsteps steps of dt and
+ * write the table rows [nsteps+1][3np+3] (r_1..r_np heliocentric in the
+ * caller's planet order, then h0) to host memory.  The simulation state is not
+ * advanced.  Returns TPM_EPLANET under the same condition as tpm_integrate. */
+int tpm_planet_table(tpm_sim* sim, int64_t nsteps, double dt, double* table);
+
+/* Use a caller-supplied planet table (rows [nrows][3np+3], same layout, row n =
+ * global step n) instead of the on-device planet map, from now on; nrows <= 0
+ * returns to the planet map.  Meant for checking the particle kernel alone. */
+int tpm_set_planet_table(tpm_sim* sim, const double* table, int64_t nrows);
+
+/* ---- unit entry points of the device math (host arrays) -------------------- */
+/* sin and cos of x[n] by the library's branch-free FP64 routine. */
+int tpm_debug_sincos(int64_t n, const double* x, double* s, double* c);
+/* One fixed-iteration Kepler drift about mu of each rv[n][6] (x, y, z, vx, vy,
+ * vz) by dt; ok[n] = 0 where the drift was refused (TPM_KEPLER rule). */
+int tpm_debug_drift(double mu, int64_t n, const double* rv_in, double* rv_out, int32_t* ok,
+                    double dt, int32_t kepler_iters, double kepler_ftol);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPMVS_H */

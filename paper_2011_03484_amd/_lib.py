@@ -1,0 +1,238 @@
+"""ctypes binding of ``libtpmvs.so`` (argument marshalling only).
+
+Every computation happens in the library's HIP kernels; this module converts
+numpy arrays to pointers and error codes to exceptions.  The library is loaded
+from the package directory; if it is missing, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtpmvs.so")
+
+TPM_OK, TPM_EINVAL, TPM_ENOMEM, TPM_EDEVICE, TPM_ESTATE, TPM_EPLANET = 0, -1, -2, -3, -4, -5
+ACTIVE, ENCOUNTER, ESCAPE, KEPLER = 0, 1, 2, 3
+ERROR_NAMES = {TPM_EINVAL: "EINVAL", TPM_ENOMEM: "ENOMEM", TPM_EDEVICE: "EDEVICE",
+               TPM_ESTATE: "ESTATE", TPM_EPLANET: "EPLANET"}
+
+
+class TpmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tpm error {ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class PlanetEncounterError(TpmError):
+    """Planets came within a mutual Hill radius (results are still valid to read)."""
+
+
+class Options(C.Structure):
+    _fields_ = [("kepler_iters", C.c_int32), ("chunk_steps", C.c_int32),
+                ("resync_chunks", C.c_int32), ("block_threads", C.c_int32),
+                ("r_escape", C.c_double), ("kepler_ftol", C.c_double), ("device", C.c_int32),
+                ("time_kernels", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("step", C.c_int64), ("n_particles", C.c_int64), ("n_active", C.c_int64),
+                ("active_particle_steps", C.c_int64), ("wall_ms", C.c_double),
+                ("particle_ms", C.c_double), ("ephemeris_ms", C.c_double), ("chunks", C.c_int64),
+                ("particle_kernel_ms", C.c_double), ("compactions", C.c_int64),
+                ("count_by_reason", C.c_int64 * 4)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "count_by_reason"}
+        d["count_by_reason"] = list(self.count_by_reason)
+        return d
+
+
+# Exported symbols and their signatures; the tests check the library against this list
+# and include/tpmvs.h.
+_P = C.c_void_p
+SIGNATURES = {
+    "tpm_default_options": (None, [_P]),
+    "tpm_create": (C.c_int, [_P, _P]),
+    "tpm_destroy": (None, [_P]),
+    "tpm_set_central": (C.c_int, [_P, C.c_double]),
+    "tpm_set_planets": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P]),
+    "tpm_set_particles": (C.c_int, [_P, C.c_int64, _P, _P]),
+    "tpm_integrate": (C.c_int, [_P, C.c_int64, C.c_double]),
+    "tpm_get_particles": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "tpm_get_planets": (C.c_int, [_P, _P, _P]),
+    "tpm_get_stats": (C.c_int, [_P, _P]),
+    "tpm_hill_radius": (C.c_double, [C.c_double, C.c_double, C.c_double]),
+    "tpm_last_error": (C.c_char_p, []),
+    "tpm_planet_table": (C.c_int, [_P, C.c_int64, C.c_double, _P]),
+    "tpm_set_planet_table": (C.c_int, [_P, _P, C.c_int64]),
+    "tpm_debug_sincos": (C.c_int, [C.c_int64, _P, _P, _P]),
+    "tpm_debug_drift": (C.c_int, [C.c_double, C.c_int64, _P, _P, _P, C.c_double, C.c_int32,
+                                  C.c_double]),
+}
+
+_lib = None
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2011_03484_amd.build` (no CPU fallback exists)")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != TPM_OK:
+        msg = load().tpm_last_error().decode()
+        if rc == TPM_EPLANET:
+            raise PlanetEncounterError(rc, msg)
+        raise TpmError(rc, msg)
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a, shape):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64)).reshape(shape)
+    return a
+
+
+def default_options() -> Options:
+    o = Options()
+    load().tpm_default_options(C.byref(o))
+    return o
+
+
+def hill_radius(mu0: float, mu_p: float, a_p: float) -> float:
+    return load().tpm_hill_radius(float(mu0), float(mu_p), float(a_p))
+
+
+class Simulation:
+    """One integrator instance on one GPU (see include/tpmvs.h)."""
+
+    def __init__(self, kepler_iters: int = 5, chunk_steps: int = 0, resync_chunks: int = 0,
+                 block_threads: int = 0, r_escape: float = 0.0, kepler_ftol: float = 0.0,
+                 device: int = 0, time_kernels: bool = False):
+        lib = load()
+        o = default_options()
+        o.kepler_iters, o.chunk_steps, o.resync_chunks = kepler_iters, chunk_steps, resync_chunks
+        o.block_threads, o.r_escape, o.kepler_ftol, o.device = (block_threads, r_escape,
+                                                                kepler_ftol, device)
+        o.time_kernels = int(bool(time_kernels))
+        h = C.c_void_p()
+        _check(lib.tpm_create(C.byref(o), C.byref(h)))
+        self._h = h
+        self.np = 0
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().tpm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_central(self, mu0: float):
+        _check(load().tpm_set_central(self._h, float(mu0)))
+
+    def set_planets(self, mu, r, v, r_crit):
+        mu = _f64(mu, (-1,))
+        npl = mu.shape[0]
+        r, v = _f64(r, (npl, 3)), _f64(v, (npl, 3))
+        rc = _f64(r_crit, (npl,))
+        _check(load().tpm_set_planets(self._h, npl, _p(mu), _p(r), _p(v), _p(rc)))
+        self.np = npl
+
+    def set_particles(self, r, v):
+        r = _f64(r, (-1, 3))
+        v = _f64(v, (r.shape[0], 3))
+        _check(load().tpm_set_particles(self._h, r.shape[0], _p(r), _p(v)))
+        self.n = r.shape[0]
+
+    def integrate(self, nsteps: int, dt: float):
+        _check(load().tpm_integrate(self._h, int(nsteps), float(dt)))
+
+    def particles(self):
+        n = self.n
+        r, v = np.zeros((n, 3)), np.zeros((n, 3))
+        st = np.zeros(n, np.int64)
+        rs = np.zeros(n, np.int32)
+        pl = np.zeros(n, np.int32)
+        _check(load().tpm_get_particles(self._h, _p(r), _p(v), _p(st), _p(rs), _p(pl)))
+        return {"r": r, "v": v, "deact_step": st, "reason": rs, "planet": pl}
+
+    def planets(self):
+        r, v = np.zeros((self.np, 3)), np.zeros((self.np, 3))
+        _check(load().tpm_get_planets(self._h, _p(r), _p(v)))
+        return r, v
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(load().tpm_get_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def planet_table(self, nsteps: int, dt: float):
+        t = np.zeros((nsteps + 1, 3 * self.np + 3))
+        _check(load().tpm_planet_table(self._h, int(nsteps), float(dt), _p(t)))
+        return t
+
+    def set_planet_table(self, table):
+        if table is None:
+            _check(load().tpm_set_planet_table(self._h, None, 0))
+            return
+        t = _f64(table, (-1, 3 * self.np + 3))
+        _check(load().tpm_set_planet_table(self._h, _p(t), t.shape[0]))
+
+
+def debug_sincos(x):
+    x = _f64(x, (-1,))
+    s, c = np.zeros_like(x), np.zeros_like(x)
+    _check(load().tpm_debug_sincos(x.shape[0], _p(x), _p(s), _p(c)))
+    return s, c
+
+
+def debug_drift(mu, r, v, dt, kepler_iters=5, kepler_ftol=0.0):
+    r = _f64(r, (-1, 3))
+    v = _f64(v, (r.shape[0], 3))
+    rv = np.ascontiguousarray(np.concatenate([r, v], axis=1))
+    out = np.zeros_like(rv)
+    ok = np.zeros(r.shape[0], np.int32)
+    _check(load().tpm_debug_drift(float(mu), r.shape[0], _p(rv), _p(out), _p(ok), float(dt),
+                                  int(kepler_iters), float(kepler_ftol)))
+    return out[:, :3], out[:, 3:], ok.astype(bool)
+
+
+def run_workload(w, nsteps=None, **opts):
+    """Integrate a workload object (see the workloads module) and return results."""
+    sim = Simulation(r_escape=w.rmax, kepler_iters=w.kepler_iters, **opts)
+    sim.set_central(w.mu0)
+    sim.set_planets(w.mu, w.rp, w.vp, w.rcrit)
+    sim.set_particles(w.r, w.v)
+    sim.integrate(w.nsteps if nsteps is None else nsteps, w.dt)
+    out = sim.particles()
+    out["planets"] = sim.planets()
+    out["stats"] = sim.stats()
+    sim.close()
+    return out

@@ -1,0 +1,89 @@
+// Internal interface between the host runtime and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tpm {
+
+constexpr int MAX_NP = 8;
+
+// Working set of active particles, structure of arrays (coalesced per lane).
+struct Work {
+  double* x;
+  double* y;
+  double* z;
+  double* vx;
+  double* vy;
+  double* vz;
+  int32_t* slot;    // index of the particle in the caller's arrays
+  int32_t* status;  // 0 while active, else the removal reason
+};
+
+// Per-particle results, indexed by slot (caller order).
+struct Out {
+  double* r;        // [n][3]
+  double* v;        // [n][3]
+  int64_t* step;    // removal step, -1 while active
+  int32_t* reason;
+  int32_t* planet;
+};
+
+struct SysConst {
+  int np;
+  double mu0, inv_mu0, sqrt_mu0, inv_sqrt_mu0;
+  double mu[MAX_NP];
+  double rcrit2[MAX_NP];
+  double rmax2;          // +inf when escape is off
+  int kiters;
+  double ftol;
+};
+
+// Ephemeris constants (bodies 0..np, body 0 = central mass).
+struct EphConst {
+  int np;
+  double mu[MAX_NP + 1];
+  double eta[MAX_NP + 1];       // eta_b = sum_{k<=b} mu_k
+  double inv_eta[MAX_NP + 1];   // 1/eta_b
+  double mup[MAX_NP + 1];       // Jacobi Kepler constant mu0 eta_b / eta_{b-1}
+  double hill[MAX_NP + 1][MAX_NP + 1];  // ((mu_i+mu_j)/(3 mu0))^(1/3) / 2
+};
+
+// Particle chunk: nsteps steps through rows[0..nsteps] (row 0 = step0).
+hipError_t launch_particle_chunk(const SysConst& S, Work w, const int32_t* d_nactive, int grid_n,
+                                 Out out, const double* rows, int nsteps, double dt, int64_t step0,
+                                 int block, hipStream_t st);
+
+// Ephemeris chunk: advances the Jacobi state (rj, vj: [np][3]) by nsteps and
+// writes rows[0..nsteps]; flag receives the first step of a planet close
+// approach (or -2 for an unbound planet) if it is still -1.
+hipError_t launch_ephemeris_chunk(const EphConst& E, double* rj, double* vj, double* rows,
+                                  int nsteps, double dt, int64_t step0, int64_t* flag,
+                                  hipStream_t st);
+
+// Stable partition of the working set: active entries of src (in order) go to
+// dst; d_nactive is updated in place.  scratch holds >= 2 * nblocks + 1 ints.
+hipError_t launch_compact(Work src, Work dst, int32_t* d_nactive, int n_upper, int32_t* scratch,
+                          hipStream_t st);
+int compact_scratch_ints(int n_upper);
+
+// Write the still-active particles of the working set into out (by slot).
+hipError_t launch_finalize(Work w, const int32_t* d_nactive, int n_upper, Out out, hipStream_t st);
+
+// Helio -> Jacobi on the host-side arrays is done in the runtime; conversion of
+// the device Jacobi state back to heliocentric r, v:
+hipError_t launch_jacobi_to_helio(const EphConst& E, const double* rj, const double* vj,
+                                  double* rh, double* vh, hipStream_t st);
+
+hipError_t launch_helio_to_jacobi(const EphConst& E, const double* h, double* j, hipStream_t st);
+
+// Steps spent active in [step_begin, step_end) summed over particles (for a
+// backward run the range is taken in absolute order).
+hipError_t launch_active_steps(const int64_t* dstep, int n, int64_t step_begin, int64_t step_end,
+                               unsigned long long* acc, hipStream_t st);
+
+// Unit checks of the device math (test entry points).
+hipError_t launch_sincos_test(const double* x, double* s, double* c, int n, hipStream_t st);
+hipError_t launch_drift_test(const SysConst& S, const double* rv_in, double* rv_out, int32_t* ok,
+                             int n, double dt, hipStream_t st);
+
+}  // namespace tpm

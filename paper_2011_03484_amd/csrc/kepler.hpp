@@ -1,0 +1,159 @@
+// Kepler drift with the f and g functions (Zhang & Gladman 2021, sec. 2.2,
+// drift step and the difference form of Kepler's equation), FP64, gfx950.
+//
+// With r0 = |r|, u = r.v and alpha = 2/r0 - v^2/mu = 1/a, the mean motion is
+// n = sqrt(mu alpha) alpha, ec = 1 - r0 alpha = e cos E0 and
+// es = u sqrt(alpha/mu) = e sin E0.  The change x of eccentric anomaly over a
+// step dt solves F(x) = x - ec sin x + es (1 - cos x) - n dt = 0, and
+//   f = 1 + (a/r0)(cos x - 1),      g = dt + (sin x - x)/n,
+//   fdot = -a^2 n sin x / (r1 r0),  gdot = 1 + (a/r1)(cos x - 1),
+// with r1 = a F'(x), give r' = f r + g v and v' = fdot r + gdot v.
+//
+// Particle version (drift_fixed): a fixed number k of Newton steps from a
+// fixed starting guess and no early exit, so every lane of a wavefront runs
+// the same instruction stream (sec. 2.2: the slowest lane of a group sets the
+// group's time, hence a fixed iteration count).  The starter is the
+// second-order series root x0 = dM/(1-ec) - es dM^2 / (2 (1-ec)^3), clamped to
+// dM +- 2(|ec|+|es|) (a bracket of the root).  The drift is refused (returns
+// false) when the orbit is unbound or |F(x_k)| > ftol; mean anomaly steps
+// beyond pi are reduced by whole periods.
+#pragma once
+#include "dmath.hpp"
+
+namespace tpm {
+
+constexpr double TWO_PI_HI = 0x1.921fb54442d18p+2;
+constexpr double TWO_PI_LO = 0x1.1a62633145c07p-52;
+constexpr double INV_TWO_PI = 0x1.45f306dc9c883p-3;
+
+struct KepConst {
+  double mu, inv_mu, sqrt_mu, inv_sqrt_mu;
+};
+
+// Drift (x, v) by dt about mass mu with k fixed Newton iterations.  Writes the
+// drifted state into (x, v) only where the return value is true.
+TPM_DEV bool drift_fixed(const KepConst& K, double dt, int kiters, double ftol,
+                         double& x, double& y, double& z,
+                         double& vx, double& vy, double& vz) {
+  double r2 = fma_(x, x, fma_(y, y, z * z));
+  double v2 = fma_(vx, vx, fma_(vy, vy, vz * vz));
+  double u = fma_(x, vx, fma_(y, vy, z * vz));
+  double r0, rinv;
+  sqrt_rsqrt(r2, r0, rinv);
+  double alpha = fma_(-v2, K.inv_mu, 2.0 * rinv);
+  bool bound = alpha > 0.0;
+  double sa, rsa;
+  sqrt_rsqrt(alpha, sa, rsa);            // NaN for unbound lanes, never selected
+  double a = rsa * rsa;                  // 1/alpha
+  a = fma_(a, fma_(-alpha, a, 1.0), a);  // one correction to ~1 ulp
+  double n = K.sqrt_mu * sa * alpha;
+  double ninv = K.inv_sqrt_mu * rsa * a; // 1/n
+  double ec = fma_(-r0, alpha, 1.0);
+  double es = u * sa * K.inv_sqrt_mu;
+  double dM = n * dt;
+  // reduce dM to (-pi, pi]; keep dt itself when no whole period is removed
+  double q = __builtin_rint(dM * INV_TWO_PI);
+  double dMr = fma_(-q, TWO_PI_HI, dM);
+  dMr = fma_(-q, TWO_PI_LO, dMr);
+  double dte = (q == 0.0) ? dt : dMr * ninv;
+  dM = dMr;
+  // starter
+  double om = 1.0 - ec;
+  double oinv = rcp(om);
+  double t = dM * oinv;
+  double xk = t * fma_(-0.5 * es * t, oinv, 1.0);
+  double w = 2.0 * (__builtin_fabs(ec) + __builtin_fabs(es));
+  xk = __builtin_fmin(__builtin_fmax(xk, dM - w), dM + w);
+  double s, c;
+  for (int it = 0; it < kiters; ++it) {
+    sincos(xk, s, c);
+    double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
+    double Fp = fma_(-ec, c, fma_(es, s, 1.0));
+    xk = fma_(-F, rcp_newton(Fp), xk);
+  }
+  sincos(xk, s, c);
+  double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
+  double Fp = fma_(-ec, c, fma_(es, s, 1.0));
+  bool ok = bound && (__builtin_fabs(F) <= ftol);
+  double cm1 = c - 1.0;
+  double r1 = a * Fp;
+  double r1inv = rcp(r1);
+  double f = fma_(a * rinv, cm1, 1.0);
+  double g = fma_(s - xk, ninv, dte);
+  double fd = -(a * a) * n * s * rinv * r1inv;
+  double gd = fma_(a * r1inv, cm1, 1.0);
+  if (ok) {
+    double nx = fma_(f, x, g * vx), ny = fma_(f, y, g * vy), nz = fma_(f, z, g * vz);
+    double nvx = fma_(fd, x, gd * vx), nvy = fma_(fd, y, gd * vy), nvz = fma_(fd, z, gd * vz);
+    x = nx; y = ny; z = nz;
+    vx = nvx; vy = nvy; vz = nvz;
+  }
+  return ok;
+}
+
+// Converged drift for the planets (a handful of lanes in one wavefront):
+// Newton until the correction is below 4 ulp of x on every lane, at most 40
+// steps; the loop condition is taken over the whole wavefront.
+TPM_DEV bool drift_converged(double mu, double dt, bool lane_on,
+                             double& x, double& y, double& z,
+                             double& vx, double& vy, double& vz) {
+  double r2 = fma_(x, x, fma_(y, y, z * z));
+  double v2 = fma_(vx, vx, fma_(vy, vy, vz * vz));
+  double u = fma_(x, vx, fma_(y, vy, z * vz));
+  double r0, rinv;
+  sqrt_rsqrt(r2, r0, rinv);
+  double inv_mu = rcp(mu);
+  double alpha = fma_(-v2, inv_mu, 2.0 * rinv);
+  bool bound = alpha > 0.0;
+  double sa, rsa;
+  sqrt_rsqrt(alpha, sa, rsa);
+  double a = rsa * rsa;
+  a = fma_(a, fma_(-alpha, a, 1.0), a);
+  double smu, rsmu;
+  sqrt_rsqrt(mu, smu, rsmu);
+  double n = smu * sa * alpha;
+  double ninv = rsmu * rsa * a;
+  double ec = fma_(-r0, alpha, 1.0);
+  double es = u * sa * rsmu;
+  double dM = n * dt;
+  double q = __builtin_rint(dM * INV_TWO_PI);
+  double dMr = fma_(-q, TWO_PI_HI, dM);
+  dMr = fma_(-q, TWO_PI_LO, dMr);
+  double dte = (q == 0.0) ? dt : dMr * ninv;
+  dM = dMr;
+  double om = 1.0 - ec;
+  double oinv = rcp(om);
+  double t = dM * oinv;
+  double xk = t * fma_(-0.5 * es * t, oinv, 1.0);
+  double w = 2.0 * (__builtin_fabs(ec) + __builtin_fabs(es));
+  xk = __builtin_fmin(__builtin_fmax(xk, dM - w), dM + w);
+  double s, c;
+  bool done = !(lane_on && bound);
+  for (int it = 0; it < 40; ++it) {
+    if (__all(done)) break;
+    sincos(xk, s, c);
+    double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
+    double Fp = fma_(-ec, c, fma_(es, s, 1.0));
+    double dx = F * rcp(Fp);
+    if (!done) xk = xk - dx;
+    done = done || (__builtin_fabs(dx) <= 0x1p-50 * __builtin_fabs(xk));
+  }
+  sincos(xk, s, c);
+  double Fp = fma_(-ec, c, fma_(es, s, 1.0));
+  double cm1 = c - 1.0;
+  double r1 = a * Fp;
+  double r1inv = rcp(r1);
+  double f = fma_(a * rinv, cm1, 1.0);
+  double g = fma_(s - xk, ninv, dte);
+  double fd = -(a * a) * n * s * rinv * r1inv;
+  double gd = fma_(a * r1inv, cm1, 1.0);
+  if (lane_on && bound) {
+    double nx = fma_(f, x, g * vx), ny = fma_(f, y, g * vy), nz = fma_(f, z, g * vz);
+    double nvx = fma_(fd, x, gd * vx), nvy = fma_(fd, y, gd * vy), nvz = fma_(fd, z, gd * vz);
+    x = nx; y = ny; z = nz;
+    vx = nvx; vy = nvy; vz = nvz;
+  }
+  return bound;
+}
+
+}  // namespace tpm

@@ -1,0 +1,43 @@
+// Per-particle pieces of the test-particle map (Zhang & Gladman 2021, sec. 2.2).
+#pragma once
+#include "kepler.hpp"
+
+namespace tpm {
+
+enum : int32_t { ST_ACTIVE = 0, ST_ENCOUNTER = 1, ST_ESCAPE = 2, ST_KEPLER = 3 };
+
+// Planet constants of one system, passed by value so they land in SGPRs.
+template <int NP>
+struct PlanetConst {
+  double mu[NP > 0 ? NP : 1];
+  double rcrit2[NP > 0 ? NP : 1];
+};
+
+// Kick acceleration from one table row (sec. 2.2, kick equation):
+//   a = h0 - sum_j mu_j d_j / |d_j|^3,   d_j = r - r_j,
+// and the encounter test |d_j| < rcrit_j (lowest j wins; -1 if none).
+// The row (3 NP + 3 doubles: r_1..r_NP, h0) is the same for every lane.
+template <int NP>
+TPM_DEV int accel(const double* __restrict__ row, const PlanetConst<NP>& P,
+                  double x, double y, double z, double& ax, double& ay, double& az) {
+  ax = row[3 * NP + 0];
+  ay = row[3 * NP + 1];
+  az = row[3 * NP + 2];
+  int hit = -1;
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    double dx = x - row[3 * j + 0];
+    double dy = y - row[3 * j + 1];
+    double dz = z - row[3 * j + 2];
+    double d2 = fma_(dx, dx, fma_(dy, dy, dz * dz));
+    hit = (hit < 0 && d2 < P.rcrit2[j]) ? j : hit;
+    double inv = rsqrt(d2);
+    double k = P.mu[j] * (inv * inv) * inv;
+    ax = fma_(-k, dx, ax);
+    ay = fma_(-k, dy, ay);
+    az = fma_(-k, dz, az);
+  }
+  return hit;
+}
+
+}  // namespace tpm

@@ -1,0 +1,673 @@
+// Host runtime behind the C ABI of include/tpmvs.h.
+//
+// One simulation = one device, two HIP streams at default priority:
+//   stream E runs the planet map chunk by chunk into a ring of planet-table
+//   slots in HBM; stream P runs the particle kernel over each slot once its
+//   rows are written.  The planet map for chunk c+1 thus overlaps the particle
+//   work of chunk c (sec. 2.2: the next planetary chunk is prepared while the
+//   particles are advanced), with events guarding slot reuse.  Every
+//   resync_chunks chunks the working set is compacted (sec. 2.2, resync
+//   interval) and its new size read back to shrink the next launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/tpmvs.h"
+#include "internal.h"
+
+using namespace tpm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define TPM_HIP(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? TPM_ENOMEM : TPM_EDEVICE,                 \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+  } while (0)
+
+constexpr int NSLOT = 8;
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+bool finite_all(const double* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+struct tpm_sim {
+  tpm_options opt{};
+  hipStream_t sP = nullptr, sE = nullptr;
+  hipEvent_t ev_eph[NSLOT]{}, ev_done[NSLOT]{};
+  hipEvent_t t0P = nullptr, t1P = nullptr, t0E = nullptr, t1E = nullptr;
+  bool central_set = false, planets_set = false, particles_set = false;
+  double mu0 = 0.0;
+  int np = 0;
+  std::vector<int> perm;                 // internal planet index -> caller index
+  std::vector<double> mu_s, rcrit_s;     // internal (sorted) order
+  double* d_rj = nullptr;                // Jacobi planet state [np][3]
+  double* d_vj = nullptr;
+  double* d_tmp = nullptr;               // [4][np][3] scratch for conversions
+  int64_t* d_flag = nullptr;
+  int64_t n = 0;
+  Work work[2]{};
+  int cur = 0;
+  int32_t* d_nactive = nullptr;
+  int32_t* d_scratch = nullptr;
+  Out out{};
+  int32_t* h_pin = nullptr;
+  unsigned long long* d_acc = nullptr;
+  int n_active = 0;                      // host copy (upper bound between compactions)
+  double* d_ring = nullptr;
+  int64_t ring_rows = 0;                 // rows per slot allocated
+  double* d_table = nullptr;             // caller-supplied table (optional)
+  int64_t table_rows = 0;
+  int64_t step = 0;
+  tpm_stats stats{};
+  std::vector<hipEvent_t> kev;           // per-launch timing events (time_kernels)
+
+  ~tpm_sim() { release_particles(); release_planets(); release_ring(); release_base(); }
+
+  void release_particles() {
+    for (auto& w : work) {
+      dfree(w.x); dfree(w.y); dfree(w.z); dfree(w.vx); dfree(w.vy); dfree(w.vz);
+      dfree(w.slot); dfree(w.status);
+      w = Work{};
+    }
+    dfree(out.r); dfree(out.v); dfree(out.step); dfree(out.reason); dfree(out.planet);
+    out = Out{};
+    dfree(d_scratch); d_scratch = nullptr;
+    n = 0;
+    particles_set = false;
+  }
+  void release_planets() {
+    dfree(d_rj); dfree(d_vj); dfree(d_tmp); dfree(d_table);
+    d_rj = d_vj = d_tmp = d_table = nullptr;
+    table_rows = 0;
+  }
+  void release_ring() { dfree(d_ring); d_ring = nullptr; ring_rows = 0; }
+  void release_base() {
+    if (sP) { (void)hipStreamSynchronize(sP); (void)hipStreamDestroy(sP); }
+    if (sE) { (void)hipStreamSynchronize(sE); (void)hipStreamDestroy(sE); }
+    for (int i = 0; i < NSLOT; ++i) {
+      if (ev_eph[i]) (void)hipEventDestroy(ev_eph[i]);
+      if (ev_done[i]) (void)hipEventDestroy(ev_done[i]);
+    }
+    for (auto e : {t0P, t1P, t0E, t1E}) if (e) (void)hipEventDestroy(e);
+    for (auto e : kev) (void)hipEventDestroy(e);
+    dfree(d_flag); dfree(d_nactive); dfree(d_acc);
+    if (h_pin) (void)hipHostFree(h_pin);
+  }
+
+  SysConst sys() const {
+    SysConst S{};
+    S.np = np;
+    S.mu0 = mu0;
+    S.inv_mu0 = 1.0 / mu0;
+    S.sqrt_mu0 = std::sqrt(mu0);
+    S.inv_sqrt_mu0 = 1.0 / std::sqrt(mu0);
+    for (int j = 0; j < np; ++j) {
+      S.mu[j] = mu_s[j];
+      S.rcrit2[j] = rcrit_s[j] * rcrit_s[j];
+    }
+    S.rmax2 = opt.r_escape > 0 ? opt.r_escape * opt.r_escape : INFINITY;
+    S.kiters = opt.kepler_iters;
+    S.ftol = opt.kepler_ftol;
+    return S;
+  }
+
+  EphConst eph() const {
+    EphConst E{};
+    E.np = np;
+    E.mu[0] = mu0;
+    E.eta[0] = mu0;
+    E.inv_eta[0] = 1.0 / mu0;
+    for (int b = 1; b <= np; ++b) {
+      E.mu[b] = mu_s[b - 1];
+      E.eta[b] = E.eta[b - 1] + E.mu[b];
+      E.inv_eta[b] = 1.0 / E.eta[b];
+      E.mup[b] = mu0 * E.eta[b] / E.eta[b - 1];
+    }
+    for (int i = 1; i <= np; ++i)
+      for (int j = 1; j <= np; ++j)
+        E.hill[i][j] = 0.5 * std::cbrt((E.mu[i] + E.mu[j]) / (3.0 * mu0));
+    return E;
+  }
+};
+
+namespace {
+
+int ensure_ring(tpm_sim* s, int64_t rows) {
+  if (s->ring_rows >= rows && s->d_ring) return TPM_OK;
+  TPM_HIP(hipStreamSynchronize(s->sE));
+  TPM_HIP(hipStreamSynchronize(s->sP));
+  s->release_ring();
+  size_t bytes = sizeof(double) * (size_t)NSLOT * rows * (3 * s->np + 3);
+  TPM_HIP(hipMalloc(&s->d_ring, bytes));
+  s->ring_rows = rows;
+  return TPM_OK;
+}
+
+// Reorder table columns between caller planet order and internal order.
+void permute_table(const tpm_sim* s, const double* src, double* dst, int64_t rows, bool to_caller) {
+  const int np = s->np, rl = 3 * np + 3;
+  for (int64_t r = 0; r < rows; ++r) {
+    const double* a = src + r * rl;
+    double* b = dst + r * rl;
+    for (int j = 0; j < np; ++j) {
+      int c = s->perm[j];
+      for (int k = 0; k < 3; ++k) {
+        if (to_caller) b[3 * c + k] = a[3 * j + k];
+        else b[3 * j + k] = a[3 * c + k];
+      }
+    }
+    for (int k = 0; k < 3; ++k) b[3 * np + k] = a[3 * np + k];
+  }
+}
+
+int check_eplanet(tpm_sim* s, int rc) {
+  if (rc != TPM_OK) return rc;
+  int64_t flag = -1;
+  TPM_HIP(hipMemcpy(&flag, s->d_flag, sizeof(flag), hipMemcpyDeviceToHost));
+  if (flag == -2) return fail(TPM_EPLANET, "a planet orbit became unbound");
+  if (flag >= 0)
+    return fail(TPM_EPLANET, "two planets came within a mutual Hill radius at step " +
+                                 std::to_string(flag));
+  return TPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tpm_default_options(tpm_options* o) {
+  if (!o) return;
+  o->kepler_iters = 5;
+  o->chunk_steps = 0;
+  o->resync_chunks = 0;
+  o->block_threads = 0;
+  o->r_escape = 0.0;
+  o->kepler_ftol = 0.0;
+  o->device = 0;
+  o->time_kernels = 0;
+}
+
+const char* tpm_last_error(void) { return g_err.c_str(); }
+
+double tpm_hill_radius(double mu0, double mu_p, double a_p) {
+  return a_p * std::cbrt(mu_p / (3.0 * mu0));
+}
+
+int tpm_create(const tpm_options* opt, tpm_sim** out) {
+  if (!out) return fail(TPM_EINVAL, "out is NULL");
+  *out = nullptr;
+  tpm_options o;
+  tpm_default_options(&o);
+  if (opt) o = *opt;
+  if (o.kepler_iters <= 0) o.kepler_iters = 5;
+  if (o.kepler_iters > 64) return fail(TPM_EINVAL, "kepler_iters > 64");
+  if (o.chunk_steps < 0 || o.resync_chunks < 0 || o.block_threads < 0)
+    return fail(TPM_EINVAL, "negative option");
+  if (o.chunk_steps == 0) o.chunk_steps = 1024;
+  if (o.resync_chunks == 0) o.resync_chunks = 4;
+  if (o.block_threads == 0) o.block_threads = 64;
+  if (o.block_threads % 64 || o.block_threads > 256)
+    return fail(TPM_EINVAL, "block_threads must be 64, 128, 192 or 256");
+  if (!(o.kepler_ftol > 0.0)) o.kepler_ftol = 1e-13;
+  if (!std::isfinite(o.r_escape)) return fail(TPM_EINVAL, "r_escape not finite");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(TPM_EDEVICE, "no HIP device");
+  if (o.device < 0 || o.device >= ndev) return fail(TPM_EINVAL, "device ordinal out of range");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, o.device) != hipSuccess)
+    return fail(TPM_EDEVICE, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(TPM_EDEVICE, std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
+  TPM_HIP(hipSetDevice(o.device));
+  tpm_sim* s = new tpm_sim();
+  s->opt = o;
+  auto bad = [&](hipError_t e, const char* what) {
+    if (e == hipSuccess) return false;
+    fail(TPM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return true;
+  };
+  if (bad(hipStreamCreateWithFlags(&s->sP, hipStreamNonBlocking), "stream") ||
+      bad(hipStreamCreateWithFlags(&s->sE, hipStreamNonBlocking), "stream")) {
+    delete s;
+    return TPM_EDEVICE;
+  }
+  for (int i = 0; i < NSLOT; ++i)
+    if (bad(hipEventCreateWithFlags(&s->ev_eph[i], hipEventDisableTiming), "event") ||
+        bad(hipEventCreateWithFlags(&s->ev_done[i], hipEventDisableTiming), "event")) {
+      delete s;
+      return TPM_EDEVICE;
+    }
+  if (bad(hipEventCreate(&s->t0P), "event") || bad(hipEventCreate(&s->t1P), "event") ||
+      bad(hipEventCreate(&s->t0E), "event") || bad(hipEventCreate(&s->t1E), "event") ||
+      bad(hipMalloc(&s->d_flag, sizeof(int64_t)), "alloc") ||
+      bad(hipMalloc(&s->d_nactive, sizeof(int32_t)), "alloc") ||
+      bad(hipMalloc(&s->d_acc, sizeof(unsigned long long)), "alloc") ||
+      bad(hipHostMalloc(&s->h_pin, 64, hipHostMallocDefault), "pinned alloc")) {
+    delete s;
+    return TPM_EDEVICE;
+  }
+  int64_t m1 = -1;
+  if (bad(hipMemcpy(s->d_flag, &m1, sizeof(m1), hipMemcpyHostToDevice), "memcpy")) {
+    delete s;
+    return TPM_EDEVICE;
+  }
+  *out = s;
+  return TPM_OK;
+}
+
+void tpm_destroy(tpm_sim* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->opt.device);
+  delete s;
+}
+
+int tpm_set_central(tpm_sim* s, double mu0) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  if (!(std::isfinite(mu0) && mu0 > 0.0)) return fail(TPM_EINVAL, "mu0 must be finite and > 0");
+  s->mu0 = mu0;
+  s->central_set = true;
+  s->planets_set = false;
+  return TPM_OK;
+}
+
+int tpm_set_planets(tpm_sim* s, int32_t np, const double* mu, const double* r, const double* v,
+                    const double* r_crit) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  if (!s->central_set) return fail(TPM_ESTATE, "tpm_set_central must come first");
+  if (np < 0 || np > MAX_NP) return fail(TPM_EINVAL, "np must be in 0..8");
+  if (np > 0 && (!mu || !r || !v || !r_crit)) return fail(TPM_EINVAL, "NULL planet array");
+  if (np > 0 && !(finite_all(mu, np) && finite_all(r, 3 * np) && finite_all(v, 3 * np) &&
+                  finite_all(r_crit, np)))
+    return fail(TPM_EINVAL, "planet input not finite");
+  std::vector<double> a(np);
+  for (int j = 0; j < np; ++j) {
+    if (!(mu[j] > 0.0)) return fail(TPM_EINVAL, "planet mu must be > 0");
+    if (r_crit[j] < 0.0) return fail(TPM_EINVAL, "r_crit must be >= 0");
+    double rr = std::sqrt(r[3 * j] * r[3 * j] + r[3 * j + 1] * r[3 * j + 1] + r[3 * j + 2] * r[3 * j + 2]);
+    double vv = v[3 * j] * v[3 * j] + v[3 * j + 1] * v[3 * j + 1] + v[3 * j + 2] * v[3 * j + 2];
+    double alpha = 2.0 / rr - vv / (s->mu0 + mu[j]);
+    if (!(rr > 0.0) || !(alpha > 0.0)) return fail(TPM_EINVAL, "planet orbit not bound");
+    a[j] = 1.0 / alpha;
+  }
+  TPM_HIP(hipSetDevice(s->opt.device));
+  TPM_HIP(hipStreamSynchronize(s->sP));
+  TPM_HIP(hipStreamSynchronize(s->sE));
+  s->release_planets();
+  s->release_ring();
+  s->np = np;
+  s->perm.resize(np);
+  std::iota(s->perm.begin(), s->perm.end(), 0);
+  std::stable_sort(s->perm.begin(), s->perm.end(), [&](int x, int y) { return a[x] < a[y]; });
+  s->mu_s.resize(np);
+  s->rcrit_s.resize(np);
+  std::vector<double> rs(3 * np), vs(3 * np);
+  for (int j = 0; j < np; ++j) {
+    int c = s->perm[j];
+    s->mu_s[j] = mu[c];
+    s->rcrit_s[j] = r_crit[c];
+    for (int k = 0; k < 3; ++k) { rs[3 * j + k] = r[3 * c + k]; vs[3 * j + k] = v[3 * c + k]; }
+  }
+  size_t b = sizeof(double) * 3 * std::max(np, 1);
+  TPM_HIP(hipMalloc(&s->d_rj, b));
+  TPM_HIP(hipMalloc(&s->d_vj, b));
+  TPM_HIP(hipMalloc(&s->d_tmp, 4 * b));
+  if (np > 0) {
+    TPM_HIP(hipMemcpy(s->d_tmp, rs.data(), b, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(s->d_tmp + 3 * np, vs.data(), b, hipMemcpyHostToDevice));
+    EphConst E = s->eph();
+    TPM_HIP(launch_helio_to_jacobi(E, s->d_tmp, s->d_rj, s->sE));
+    TPM_HIP(launch_helio_to_jacobi(E, s->d_tmp + 3 * np, s->d_vj, s->sE));
+    TPM_HIP(hipStreamSynchronize(s->sE));
+  }
+  int64_t m1 = -1;
+  TPM_HIP(hipMemcpy(s->d_flag, &m1, sizeof(m1), hipMemcpyHostToDevice));
+  s->step = 0;
+  s->planets_set = true;
+  return TPM_OK;
+}
+
+int tpm_set_particles(tpm_sim* s, int64_t n, const double* r, const double* v) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(TPM_EINVAL, "n out of range");
+  if (n > 0 && (!r || !v)) return fail(TPM_EINVAL, "NULL particle array");
+  if (n > 0 && !(finite_all(r, 3 * n) && finite_all(v, 3 * n)))
+    return fail(TPM_EINVAL, "particle input not finite");
+  TPM_HIP(hipSetDevice(s->opt.device));
+  TPM_HIP(hipStreamSynchronize(s->sP));
+  s->release_particles();
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  for (auto& w : s->work) {
+    TPM_HIP(hipMalloc(&w.x, nn * 8)); TPM_HIP(hipMalloc(&w.y, nn * 8)); TPM_HIP(hipMalloc(&w.z, nn * 8));
+    TPM_HIP(hipMalloc(&w.vx, nn * 8)); TPM_HIP(hipMalloc(&w.vy, nn * 8)); TPM_HIP(hipMalloc(&w.vz, nn * 8));
+    TPM_HIP(hipMalloc(&w.slot, nn * 4)); TPM_HIP(hipMalloc(&w.status, nn * 4));
+  }
+  TPM_HIP(hipMalloc(&s->out.r, nn * 24)); TPM_HIP(hipMalloc(&s->out.v, nn * 24));
+  TPM_HIP(hipMalloc(&s->out.step, nn * 8)); TPM_HIP(hipMalloc(&s->out.reason, nn * 4));
+  TPM_HIP(hipMalloc(&s->out.planet, nn * 4));
+  TPM_HIP(hipMalloc(&s->d_scratch, sizeof(int32_t) * compact_scratch_ints((int)nn)));
+  // structure-of-arrays layout for the kernels
+  std::vector<double> col(n);
+  Work& w = s->work[0];
+  double* dst[6] = {w.x, w.y, w.z, w.vx, w.vy, w.vz};
+  for (int c = 0; c < 6; ++c) {
+    const double* src = c < 3 ? r : v;
+    for (int64_t i = 0; i < n; ++i) col[i] = src[3 * i + (c % 3)];
+    if (n) TPM_HIP(hipMemcpy(dst[c], col.data(), n * 8, hipMemcpyHostToDevice));
+  }
+  std::vector<int32_t> idx(n), zero(n, 0), m1(n, -1);
+  std::vector<int64_t> m1l(n, -1);
+  std::iota(idx.begin(), idx.end(), 0);
+  if (n) {
+    TPM_HIP(hipMemcpy(w.slot, idx.data(), n * 4, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(w.status, zero.data(), n * 4, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(s->out.step, m1l.data(), n * 8, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(s->out.reason, zero.data(), n * 4, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(s->out.planet, m1.data(), n * 4, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(s->out.r, r, n * 24, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(s->out.v, v, n * 24, hipMemcpyHostToDevice));
+  }
+  int32_t nn32 = (int32_t)n;
+  TPM_HIP(hipMemcpy(s->d_nactive, &nn32, 4, hipMemcpyHostToDevice));
+  s->cur = 0;
+  s->n = n;
+  s->n_active = (int)n;
+  s->particles_set = true;
+  return TPM_OK;
+}
+
+int tpm_set_planet_table(tpm_sim* s, const double* table, int64_t nrows) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  if (!s->planets_set) return fail(TPM_ESTATE, "tpm_set_planets must come first");
+  TPM_HIP(hipSetDevice(s->opt.device));
+  TPM_HIP(hipStreamSynchronize(s->sP));
+  dfree(s->d_table);
+  s->d_table = nullptr;
+  s->table_rows = 0;
+  if (nrows <= 0) return TPM_OK;
+  if (!table) return fail(TPM_EINVAL, "table is NULL");
+  const int rl = 3 * s->np + 3;
+  if (!finite_all(table, nrows * rl)) return fail(TPM_EINVAL, "table not finite");
+  std::vector<double> t(nrows * rl);
+  permute_table(s, table, t.data(), nrows, false);
+  TPM_HIP(hipMalloc(&s->d_table, sizeof(double) * t.size()));
+  TPM_HIP(hipMemcpy(s->d_table, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
+  s->table_rows = nrows;
+  return TPM_OK;
+}
+
+int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  if (!s->planets_set || !s->particles_set)
+    return fail(TPM_ESTATE, "set central mass, planets and particles first");
+  if (nsteps < 0) return fail(TPM_EINVAL, "nsteps < 0");
+  if (!std::isfinite(dt) || dt == 0.0) return fail(TPM_EINVAL, "dt must be finite and non-zero");
+  if (s->d_table && s->step + nsteps > s->table_rows - 1)
+    return fail(TPM_EINVAL, "supplied planet table too short");
+  TPM_HIP(hipSetDevice(s->opt.device));
+  auto w0 = std::chrono::steady_clock::now();
+  const int K = s->opt.chunk_steps;
+  const int R = s->opt.resync_chunks;
+  const int rl = 3 * s->np + 3;
+  const int64_t nchunks = (nsteps + K - 1) / K;
+  if (!s->d_table) {
+    int rc = ensure_ring(s, (int64_t)K + 1);
+    if (rc) return rc;
+  }
+  const SysConst S = s->sys();
+  const EphConst E = s->eph();
+  const int64_t step_begin = s->step;
+  const bool timed = s->opt.time_kernels != 0;
+  if (timed) {
+    while ((int64_t)s->kev.size() < 2 * nchunks) {
+      hipEvent_t e;
+      TPM_HIP(hipEventCreate(&e));
+      s->kev.push_back(e);
+    }
+  }
+  s->stats.chunks = 0;
+  s->stats.compactions = 0;
+  TPM_HIP(hipEventRecord(s->t0P, s->sP));
+  TPM_HIP(hipEventRecord(s->t0E, s->sE));
+  for (int64_t c = 0; c < nchunks; ++c) {
+    const int ks = (int)std::min<int64_t>(K, nsteps - c * K);
+    const int slot = (int)(c % NSLOT);
+    const int64_t step0 = s->step + c * K;
+    const double* rows;
+    if (s->d_table) {
+      rows = s->d_table + (size_t)step0 * rl;
+    } else {
+      double* srow = s->d_ring + (size_t)slot * s->ring_rows * rl;
+      TPM_HIP(hipStreamWaitEvent(s->sE, s->ev_done[slot], 0));
+      TPM_HIP(launch_ephemeris_chunk(E, s->d_rj, s->d_vj, srow, ks, dt, step0, s->d_flag, s->sE));
+      TPM_HIP(hipEventRecord(s->ev_eph[slot], s->sE));
+      TPM_HIP(hipStreamWaitEvent(s->sP, s->ev_eph[slot], 0));
+      rows = srow;
+    }
+    if (s->n_active > 0) {
+      Work& w = s->work[s->cur];
+      if (timed) TPM_HIP(hipEventRecord(s->kev[2 * s->stats.chunks], s->sP));
+      TPM_HIP(launch_particle_chunk(S, w, s->d_nactive, s->n_active, s->out, rows, ks, dt, step0,
+                                    s->opt.block_threads, s->sP));
+      if (timed) TPM_HIP(hipEventRecord(s->kev[2 * s->stats.chunks + 1], s->sP));
+      s->stats.chunks++;
+    }
+    TPM_HIP(hipEventRecord(s->ev_done[slot], s->sP));
+    const bool last = (c == nchunks - 1);
+    if (s->n_active > 0 && (((c + 1) % R == 0) || last)) {
+      Work& src = s->work[s->cur];
+      Work& dst = s->work[1 - s->cur];
+      TPM_HIP(launch_compact(src, dst, s->d_nactive, s->n_active, s->d_scratch, s->sP));
+      TPM_HIP(hipMemcpyAsync(s->h_pin, s->d_nactive, 4, hipMemcpyDeviceToHost, s->sP));
+      TPM_HIP(hipStreamSynchronize(s->sP));
+      s->n_active = s->h_pin[0];
+      s->cur = 1 - s->cur;
+      s->stats.compactions++;
+    }
+  }
+  TPM_HIP(hipEventRecord(s->t1P, s->sP));
+  TPM_HIP(hipEventRecord(s->t1E, s->sE));
+  TPM_HIP(hipStreamSynchronize(s->sE));
+  TPM_HIP(hipStreamSynchronize(s->sP));
+  s->step += nsteps;
+  float msP = 0.f, msE = 0.f;
+  TPM_HIP(hipEventElapsedTime(&msP, s->t0P, s->t1P));
+  TPM_HIP(hipEventElapsedTime(&msE, s->t0E, s->t1E));
+  // active particle-steps of this call
+  TPM_HIP(hipMemsetAsync(s->d_acc, 0, sizeof(unsigned long long), s->sP));
+  TPM_HIP(launch_active_steps(s->out.step, (int)s->n, step_begin, s->step, s->d_acc, s->sP));
+  unsigned long long acc = 0;
+  TPM_HIP(hipMemcpyAsync(s->h_pin, s->d_acc, sizeof(acc), hipMemcpyDeviceToHost, s->sP));
+  TPM_HIP(hipStreamSynchronize(s->sP));
+  std::memcpy(&acc, s->h_pin, sizeof(acc));
+  auto w1 = std::chrono::steady_clock::now();
+  double kms = 0.0;
+  if (timed)
+    for (int64_t c = 0; c < s->stats.chunks; ++c) {
+      float m = 0.f;
+      TPM_HIP(hipEventElapsedTime(&m, s->kev[2 * c], s->kev[2 * c + 1]));
+      kms += m;
+    }
+  s->stats.particle_kernel_ms = kms;
+  s->stats.particle_ms = msP;
+  s->stats.ephemeris_ms = msE;
+  s->stats.wall_ms = std::chrono::duration<double, std::milli>(w1 - w0).count();
+  s->stats.active_particle_steps = (int64_t)acc;
+  return check_eplanet(s, TPM_OK);
+}
+
+int tpm_get_particles(tpm_sim* s, double* r, double* v, int64_t* deact_step, int32_t* reason,
+                      int32_t* planet) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  if (!s->particles_set) return fail(TPM_ESTATE, "no particles");
+  TPM_HIP(hipSetDevice(s->opt.device));
+  const int64_t n = s->n;
+  if (n == 0) return TPM_OK;
+  TPM_HIP(launch_finalize(s->work[s->cur], s->d_nactive, s->n_active, s->out, s->sP));
+  TPM_HIP(hipStreamSynchronize(s->sP));
+  if (r) TPM_HIP(hipMemcpy(r, s->out.r, n * 24, hipMemcpyDeviceToHost));
+  if (v) TPM_HIP(hipMemcpy(v, s->out.v, n * 24, hipMemcpyDeviceToHost));
+  if (deact_step) TPM_HIP(hipMemcpy(deact_step, s->out.step, n * 8, hipMemcpyDeviceToHost));
+  if (reason) TPM_HIP(hipMemcpy(reason, s->out.reason, n * 4, hipMemcpyDeviceToHost));
+  if (planet) {
+    TPM_HIP(hipMemcpy(planet, s->out.planet, n * 4, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i)
+      if (planet[i] >= 0) planet[i] = s->perm[planet[i]];
+  }
+  return TPM_OK;
+}
+
+int tpm_get_planets(tpm_sim* s, double* r, double* v) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  if (!s->planets_set) return fail(TPM_ESTATE, "no planets");
+  const int np = s->np;
+  if (np == 0) return TPM_OK;
+  TPM_HIP(hipSetDevice(s->opt.device));
+  TPM_HIP(hipStreamSynchronize(s->sE));
+  TPM_HIP(launch_jacobi_to_helio(s->eph(), s->d_rj, s->d_vj, s->d_tmp, s->d_tmp + 3 * np, s->sE));
+  std::vector<double> h(6 * np);
+  TPM_HIP(hipMemcpyAsync(h.data(), s->d_tmp, sizeof(double) * 6 * np, hipMemcpyDeviceToHost, s->sE));
+  TPM_HIP(hipStreamSynchronize(s->sE));
+  for (int j = 0; j < np; ++j) {
+    int c = s->perm[j];
+    for (int k = 0; k < 3; ++k) {
+      if (r) r[3 * c + k] = h[3 * j + k];
+      if (v) v[3 * c + k] = h[3 * np + 3 * j + k];
+    }
+  }
+  return TPM_OK;
+}
+
+int tpm_get_stats(tpm_sim* s, tpm_stats* o) {
+  if (!s || !o) return fail(TPM_EINVAL, "NULL argument");
+  tpm_stats st = s->stats;
+  st.step = s->step;
+  st.n_particles = s->n;
+  st.n_active = 0;
+  for (int k = 0; k < 4; ++k) st.count_by_reason[k] = 0;
+  if (s->particles_set && s->n > 0) {
+    TPM_HIP(hipSetDevice(s->opt.device));
+    TPM_HIP(hipStreamSynchronize(s->sP));
+    std::vector<int32_t> reason(s->n);
+    TPM_HIP(launch_finalize(s->work[s->cur], s->d_nactive, s->n_active, s->out, s->sP));
+    TPM_HIP(hipStreamSynchronize(s->sP));
+    TPM_HIP(hipMemcpy(reason.data(), s->out.reason, s->n * 4, hipMemcpyDeviceToHost));
+    for (auto x : reason)
+      if (x >= 0 && x < 4) st.count_by_reason[x]++;
+    st.n_active = st.count_by_reason[TPM_ACTIVE];
+  }
+  *o = st;
+  return TPM_OK;
+}
+
+int tpm_planet_table(tpm_sim* s, int64_t nsteps, double dt, double* table) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  if (!s->planets_set) return fail(TPM_ESTATE, "no planets");
+  if (nsteps < 0 || !table) return fail(TPM_EINVAL, "bad arguments");
+  if (!std::isfinite(dt) || dt == 0.0) return fail(TPM_EINVAL, "dt must be finite and non-zero");
+  TPM_HIP(hipSetDevice(s->opt.device));
+  const int np = s->np, rl = 3 * np + 3;
+  double *rj = nullptr, *vj = nullptr, *rows = nullptr;
+  int64_t* flag = nullptr;
+  size_t b = sizeof(double) * 3 * std::max(np, 1);
+  TPM_HIP(hipStreamSynchronize(s->sE));
+  TPM_HIP(hipMalloc(&rj, b));
+  TPM_HIP(hipMalloc(&vj, b));
+  TPM_HIP(hipMalloc(&flag, sizeof(int64_t)));
+  TPM_HIP(hipMalloc(&rows, sizeof(double) * (nsteps + 1) * rl));
+  TPM_HIP(hipMemcpy(rj, s->d_rj, b, hipMemcpyDeviceToDevice));
+  TPM_HIP(hipMemcpy(vj, s->d_vj, b, hipMemcpyDeviceToDevice));
+  int64_t m1 = -1;
+  TPM_HIP(hipMemcpy(flag, &m1, sizeof(m1), hipMemcpyHostToDevice));
+  const EphConst E = s->eph();
+  const int K = s->opt.chunk_steps;
+  for (int64_t c = 0; c * K < nsteps || c == 0; ++c) {
+    int ks = (int)std::min<int64_t>(K, nsteps - c * K);
+    TPM_HIP(launch_ephemeris_chunk(E, rj, vj, rows + (size_t)c * K * rl, ks, dt, s->step + c * K,
+                                   flag, s->sE));
+    if (nsteps == 0) break;
+  }
+  std::vector<double> t((nsteps + 1) * rl);
+  TPM_HIP(hipStreamSynchronize(s->sE));
+  TPM_HIP(hipMemcpy(t.data(), rows, sizeof(double) * t.size(), hipMemcpyDeviceToHost));
+  int64_t f = -1;
+  TPM_HIP(hipMemcpy(&f, flag, sizeof(f), hipMemcpyDeviceToHost));
+  dfree(rj); dfree(vj); dfree(rows); dfree(flag);
+  permute_table(s, t.data(), table, nsteps + 1, true);
+  if (f == -2) return fail(TPM_EPLANET, "a planet orbit became unbound");
+  if (f >= 0) return fail(TPM_EPLANET, "two planets came within a mutual Hill radius");
+  return TPM_OK;
+}
+
+int tpm_debug_sincos(int64_t n, const double* x, double* s_out, double* c_out) {
+  if (n < 0 || n >= (int64_t(1) << 31) || (n && (!x || !s_out || !c_out)))
+    return fail(TPM_EINVAL, "bad arguments");
+  if (n == 0) return TPM_OK;
+  double *dx, *ds, *dc;
+  TPM_HIP(hipMalloc(&dx, n * 8));
+  TPM_HIP(hipMalloc(&ds, n * 8));
+  TPM_HIP(hipMalloc(&dc, n * 8));
+  TPM_HIP(hipMemcpy(dx, x, n * 8, hipMemcpyHostToDevice));
+  TPM_HIP(launch_sincos_test(dx, ds, dc, (int)n, nullptr));
+  TPM_HIP(hipDeviceSynchronize());
+  TPM_HIP(hipMemcpy(s_out, ds, n * 8, hipMemcpyDeviceToHost));
+  TPM_HIP(hipMemcpy(c_out, dc, n * 8, hipMemcpyDeviceToHost));
+  dfree(dx); dfree(ds); dfree(dc);
+  return TPM_OK;
+}
+
+int tpm_debug_drift(double mu, int64_t n, const double* rv_in, double* rv_out, int32_t* ok,
+                    double dt, int32_t kepler_iters, double kepler_ftol) {
+  if (n < 0 || n >= (int64_t(1) << 31) || (n && (!rv_in || !rv_out || !ok)))
+    return fail(TPM_EINVAL, "bad arguments");
+  if (!(mu > 0.0) || !std::isfinite(dt) || kepler_iters < 0 || kepler_iters > 64)
+    return fail(TPM_EINVAL, "bad arguments");
+  if (n == 0) return TPM_OK;
+  SysConst S{};
+  S.mu0 = mu;
+  S.inv_mu0 = 1.0 / mu;
+  S.sqrt_mu0 = std::sqrt(mu);
+  S.inv_sqrt_mu0 = 1.0 / std::sqrt(mu);
+  S.kiters = kepler_iters;
+  S.ftol = kepler_ftol > 0 ? kepler_ftol : 1e-13;
+  double *di, *dout;
+  int32_t* dok;
+  TPM_HIP(hipMalloc(&di, n * 48));
+  TPM_HIP(hipMalloc(&dout, n * 48));
+  TPM_HIP(hipMalloc(&dok, n * 4));
+  TPM_HIP(hipMemcpy(di, rv_in, n * 48, hipMemcpyHostToDevice));
+  TPM_HIP(launch_drift_test(S, di, dout, dok, (int)n, dt, nullptr));
+  TPM_HIP(hipDeviceSynchronize());
+  TPM_HIP(hipMemcpy(rv_out, dout, n * 48, hipMemcpyDeviceToHost));
+  TPM_HIP(hipMemcpy(ok, dok, n * 4, hipMemcpyDeviceToHost));
+  dfree(di); dfree(dout); dfree(dok);
+  return TPM_OK;
+}
+
+}  // extern "C"
