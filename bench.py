@@ -61,6 +61,9 @@ def main():
     ap.add_argument("--cpu-particles", type=int, default=16384)
     ap.add_argument("--cpu-steps", type=int, default=10000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="after the run, copy this many MiB device-to-device with a plain copy "
+                         "kernel (the reference for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
@@ -123,7 +126,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS if achieved else None,
                      "traffic": None},
-        "kernel": {"name": "particle_chunk<4,5>", "launches": launches,
+        "kernel": {"name": "particle_queue<4,5>", "launches": launches,
                    "avg_launch_ms": kern_ms / max(launches, 1),
                    "flops_per_particle_step": fpps,
                    "particle_steps_per_s_kernels_only": aps / (kern_ms / 1e3) if kern_ms else None,
@@ -133,6 +136,14 @@ def main():
     }
     for s in sims:
         s.close()
+    if args.copy_calibration_mb > 0:
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = nbytes
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_particles, args.cpu_steps)
     print(json.dumps(line))

@@ -232,6 +232,7 @@ struct Planets {
   std::vector<double> mu;    // mu[0] = mu0, mu[j] = G m_j (j = 1..np)
   std::vector<double> eta;   // eta[j] = sum_{k<=j} mu[k]
   std::vector<double> rj, vj;  // Jacobi r', v' for j = 1..np at index 3(j-1)
+  std::vector<double> a0;      // initial osculating semi-major axis (mu0 + mu_j), j = 1..np
 };
 
 // Heliocentric positions from Jacobi: r_j = r'_j + R_{j-1},
@@ -299,20 +300,15 @@ void write_row(const Planets& P, double* row) {
 }
 
 // Any pair closer than one mutual Hill radius ((mu_i+mu_j)/(3 mu0))^(1/3) times
-// the mean of their heliocentric distances.
+// the mean of their initial osculating semi-major axes.
 bool planets_too_close(const Planets& P, const double* rh) {
   for (int i = 1; i <= P.np; ++i)
     for (int j = i + 1; j <= P.np; ++j) {
       const double* a = rh + 3 * (i - 1);
       const double* b = rh + 3 * (j - 1);
-      double d2 = 0, ra2 = 0, rb2 = 0;
-      for (int c = 0; c < 3; ++c) {
-        d2 += (a[c] - b[c]) * (a[c] - b[c]);
-        ra2 += a[c] * a[c];
-        rb2 += b[c] * b[c];
-      }
-      double rh_m = std::cbrt((P.mu[i] + P.mu[j]) / (3.0 * P.mu0)) * 0.5 *
-                    (std::sqrt(ra2) + std::sqrt(rb2));
+      double d2 = 0;
+      for (int c = 0; c < 3; ++c) d2 += (a[c] - b[c]) * (a[c] - b[c]);
+      double rh_m = std::cbrt((P.mu[i] + P.mu[j]) / (3.0 * P.mu0)) * 0.5 * (P.a0[i] + P.a0[j]);
       if (std::sqrt(d2) < rh_m) return true;
     }
   return false;
@@ -357,6 +353,14 @@ int64_t orc_ephemeris(double mu0, int np, const double* mu, const double* r, con
   for (int j = 1; j <= np; ++j) { P.mu[j] = mu[j - 1]; P.eta[j] = P.eta[j - 1] + P.mu[j]; }
   P.rj.assign(3 * np, 0.0);
   P.vj.assign(3 * np, 0.0);
+  P.a0.assign(np + 1, 0.0);
+  for (int j = 1; j <= np; ++j) {
+    const double* rr = r + 3 * (j - 1);
+    const double* vv = v + 3 * (j - 1);
+    double rn = std::sqrt(rr[0] * rr[0] + rr[1] * rr[1] + rr[2] * rr[2]);
+    double v2 = vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2];
+    P.a0[j] = 1.0 / (2.0 / rn - v2 / (mu0 + P.mu[j]));
+  }
   helio_to_jacobi(P, r, P.rj.data());
   helio_to_jacobi(P, v, P.vj.data());
   const int rowlen = 3 * np + 3;

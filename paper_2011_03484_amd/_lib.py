@@ -33,6 +33,7 @@ class PlanetEncounterError(TpmError):
 class Options(C.Structure):
     _fields_ = [("kepler_iters", C.c_int32), ("chunk_steps", C.c_int32),
                 ("resync_chunks", C.c_int32), ("block_threads", C.c_int32),
+                ("sub_chunks", C.c_int32), ("waves_per_simd", C.c_int32),
                 ("r_escape", C.c_double), ("kepler_ftol", C.c_double), ("device", C.c_int32),
                 ("time_kernels", C.c_int32)]
 
@@ -124,13 +125,15 @@ class Simulation:
 
     def __init__(self, kepler_iters: int = 5, chunk_steps: int = 0, resync_chunks: int = 0,
                  block_threads: int = 0, r_escape: float = 0.0, kepler_ftol: float = 0.0,
-                 device: int = 0, time_kernels: bool = False):
+                 device: int = 0, time_kernels: bool = False, sub_chunks: int = 0,
+                 waves_per_simd: int = 0):
         lib = load()
         o = default_options()
         o.kepler_iters, o.chunk_steps, o.resync_chunks = kepler_iters, chunk_steps, resync_chunks
         o.block_threads, o.r_escape, o.kepler_ftol, o.device = (block_threads, r_escape,
                                                                 kepler_ftol, device)
         o.time_kernels = int(bool(time_kernels))
+        o.sub_chunks, o.waves_per_simd = sub_chunks, waves_per_simd
         h = C.c_void_p()
         _check(lib.tpm_create(C.byref(o), C.byref(h)))
         self._h = h

@@ -45,13 +45,28 @@ struct EphConst {
   double eta[MAX_NP + 1];       // eta_b = sum_{k<=b} mu_k
   double inv_eta[MAX_NP + 1];   // 1/eta_b
   double mup[MAX_NP + 1];       // Jacobi Kepler constant mu0 eta_b / eta_{b-1}
-  double hill[MAX_NP + 1][MAX_NP + 1];  // ((mu_i+mu_j)/(3 mu0))^(1/3) / 2
+  // squared mutual Hill radius ((mu_i+mu_j)/(3 mu0))^(1/3) (a_i + a_j)/2 with
+  // the planets' osculating semi-major axes when they were set
+  double hill2[MAX_NP + 1][MAX_NP + 1];
 };
 
-// Particle chunk: nsteps steps through rows[0..nsteps] (row 0 = step0).
+// Work-queue bookkeeping of one particle launch (see particle_queue).
+struct QueueLaunch {
+  unsigned long long* ctr;     // device item counter
+  unsigned long long base;     // its value when this launch starts
+  uint32_t* progress;          // device per-tile progress counters
+  uint32_t epoch;              // their value when this launch starts
+  int nsub;                    // sub-chunks per chunk
+  int workers;                 // wavefronts launched
+  int block;                   // threads per workgroup (multiple of 64)
+  int32_t* error;              // device flag set on an over-long wait
+};
+
+// Particle chunk: nsteps steps through rows[0..nsteps] (row 0 = step0) over
+// the first grid_n (>= active count) working-set entries.
 hipError_t launch_particle_chunk(const SysConst& S, Work w, const int32_t* d_nactive, int grid_n,
                                  Out out, const double* rows, int nsteps, double dt, int64_t step0,
-                                 int block, hipStream_t st);
+                                 const QueueLaunch& QL, hipStream_t st);
 
 // Ephemeris chunk: advances the Jacobi state (rj, vj: [np][3]) by nsteps and
 // writes rows[0..nsteps]; flag receives the first step of a planet close

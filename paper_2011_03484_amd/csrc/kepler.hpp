@@ -94,27 +94,24 @@ TPM_DEV bool drift_fixed(const KepConst& K, double dt, int kiters, double ftol,
 // Converged drift for the planets (a handful of lanes in one wavefront):
 // Newton until the correction is below 4 ulp of x on every lane, at most 40
 // steps; the loop condition is taken over the whole wavefront.
-TPM_DEV bool drift_converged(double mu, double dt, bool lane_on,
+TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
                              double& x, double& y, double& z,
                              double& vx, double& vy, double& vz) {
   double r2 = fma_(x, x, fma_(y, y, z * z));
   double v2 = fma_(vx, vx, fma_(vy, vy, vz * vz));
   double u = fma_(x, vx, fma_(y, vy, z * vz));
   double r0, rinv;
-  sqrt_rsqrt(r2, r0, rinv);
-  double inv_mu = rcp(mu);
-  double alpha = fma_(-v2, inv_mu, 2.0 * rinv);
+  sqrt_rsqrt(lane_on ? r2 : 1.0, r0, rinv);
+  double alpha = fma_(-v2, K.inv_mu, 2.0 * rinv);
   bool bound = alpha > 0.0;
   double sa, rsa;
-  sqrt_rsqrt(alpha, sa, rsa);
+  sqrt_rsqrt(bound ? alpha : 1.0, sa, rsa);
   double a = rsa * rsa;
   a = fma_(a, fma_(-alpha, a, 1.0), a);
-  double smu, rsmu;
-  sqrt_rsqrt(mu, smu, rsmu);
-  double n = smu * sa * alpha;
-  double ninv = rsmu * rsa * a;
+  double n = K.sqrt_mu * sa * alpha;
+  double ninv = K.inv_sqrt_mu * rsa * a;
   double ec = fma_(-r0, alpha, 1.0);
-  double es = u * sa * rsmu;
+  double es = u * sa * K.inv_sqrt_mu;
   double dM = n * dt;
   double q = __builtin_rint(dM * INV_TWO_PI);
   double dMr = fma_(-q, TWO_PI_HI, dM);
@@ -135,7 +132,7 @@ TPM_DEV bool drift_converged(double mu, double dt, bool lane_on,
     double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
     double Fp = fma_(-ec, c, fma_(es, s, 1.0));
     double dx = F * rcp(Fp);
-    if (!done) xk = xk - dx;
+    xk = done ? xk : xk - dx;
     done = done || (__builtin_fabs(dx) <= 0x1p-50 * __builtin_fabs(xk));
   }
   sincos(xk, s, c);
@@ -147,12 +144,11 @@ TPM_DEV bool drift_converged(double mu, double dt, bool lane_on,
   double g = fma_(s - xk, ninv, dte);
   double fd = -(a * a) * n * s * rinv * r1inv;
   double gd = fma_(a * r1inv, cm1, 1.0);
-  if (lane_on && bound) {
-    double nx = fma_(f, x, g * vx), ny = fma_(f, y, g * vy), nz = fma_(f, z, g * vz);
-    double nvx = fma_(fd, x, gd * vx), nvy = fma_(fd, y, gd * vy), nvz = fma_(fd, z, gd * vz);
-    x = nx; y = ny; z = nz;
-    vx = nvx; vy = nvy; vz = nvz;
-  }
+  bool upd = lane_on && bound;
+  double nx = fma_(f, x, g * vx), ny = fma_(f, y, g * vy), nz = fma_(f, z, g * vz);
+  double nvx = fma_(fd, x, gd * vx), nvy = fma_(fd, y, gd * vy), nvz = fma_(fd, z, gd * vz);
+  x = upd ? nx : x; y = upd ? ny : y; z = upd ? nz : z;
+  vx = upd ? nvx : vx; vy = upd ? nvy : vy; vz = upd ? nvz : vz;
   return bound;
 }
 

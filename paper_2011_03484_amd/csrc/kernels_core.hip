@@ -1,10 +1,11 @@
 // Core kernels of the test-particle map on gfx950 (FP64 throughout).
 //
-//  * particle_chunk  - one lane per particle; the particle stays in registers
-//    for a whole chunk of steps (sec. 2.2: a single kernel loops over the
-//    planet chunk so each particle is read and written once per chunk).  Every
-//    lane reads the same planet-table row, so the row is fetched with scalar
-//    loads (wave-uniform address) into SGPRs.
+//  * particle_queue  - one lane per particle; the particle stays in registers
+//    for hundreds of steps (sec. 2.2: a single kernel loops over the planet
+//    chunk so each particle is read and written once per chunk), with the
+//    chunk's (tile, sub-chunk) items handed out dynamically to wavefronts.
+//    Every lane reads the same planet-table row, so the row is fetched with
+//    scalar loads (wave-uniform address) into SGPRs.
 //  * ephemeris_chunk - one wavefront; lane b holds Jacobi body b.  Wisdom-Holman
 //    kick-drift-kick of the planets (sec. 2.2, planet integration) writing the
 //    heliocentric positions and the indirect term h0 per step.
@@ -27,33 +28,36 @@ struct ChunkArgs {
   int64_t step0;
 };
 
-// KIT > 0 fixes the Newton count at compile time (fully unrolled); KIT == 0
-// reads it from the arguments.
+// Advance particle i of the working set through steps [s_begin, s_end) of a
+// chunk whose rows start at `rows` (row k = step step0 + k).  The step loop
+// is uniform across the wavefront (s_begin, s_end are wave-uniform), so row
+// addresses stay wave-uniform and are read with scalar loads; removed lanes
+// are masked off and the wavefront leaves early once none is active.
+// KIT > 0 fixes the Newton count at compile time.
 template <int NP, int KIT>
-__global__ void __launch_bounds__(256)
-particle_chunk(Work w, const int32_t* __restrict__ d_nactive, Out out,
-               const double* __restrict__ rows, ChunkArgs<NP> A) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= *d_nactive) return;
-  if (w.status[i] != ST_ACTIVE) return;
+TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const ChunkArgs<NP>& A,
+                     int i, bool valid, int s_begin, int s_end) {
   constexpr int ROW = 3 * NP + 3;
   const int kiters = KIT > 0 ? KIT : A.kiters;
-  double x = w.x[i], y = w.y[i], z = w.z[i];
-  double vx = w.vx[i], vy = w.vy[i], vz = w.vz[i];
+  valid = valid && w.status[i] == ST_ACTIVE;
+  double x = 0, y = 0, z = 0, vx = 0, vy = 0, vz = 0;
+  if (valid) {
+    x = w.x[i]; y = w.y[i]; z = w.z[i];
+    vx = w.vx[i]; vy = w.vy[i]; vz = w.vz[i];
+  }
   double ax, ay, az;
-  int hit = accel<NP>(rows, A.P, x, y, z, ax, ay, az);
-  int32_t reason = ST_ACTIVE, planet = -1;
+  int hit = accel<NP>(rows + (size_t)s_begin * ROW, A.P, x, y, z, ax, ay, az);
+  int32_t reason = valid ? ST_ACTIVE : -1, planet = -1;
   int64_t dstep = -1;
-  if (hit >= 0) {
-    reason = ST_ENCOUNTER; planet = hit; dstep = A.step0;
-  } else if (fma_(x, x, fma_(y, y, z * z)) > A.rmax2) {
-    reason = ST_ESCAPE; dstep = A.step0;
+  if (valid) {
+    if (hit >= 0) {
+      reason = ST_ENCOUNTER; planet = hit; dstep = A.step0 + s_begin;
+    } else if (fma_(x, x, fma_(y, y, z * z)) > A.rmax2) {
+      reason = ST_ESCAPE; dstep = A.step0 + s_begin;
+    }
   }
   const double h = 0.5 * A.dt;
-  // The step loop is uniform across the wavefront (so the row address stays
-  // wave-uniform and is read by scalar loads); removed lanes are masked off
-  // and the wavefront leaves early once none of its lanes is active.
-  for (int s = 0; s < A.nsteps; ++s) {
+  for (int s = s_begin; s < s_end; ++s) {
     if (__all(reason != ST_ACTIVE)) break;
     const double* row = rows + (size_t)(s + 1) * ROW;
     if (reason == ST_ACTIVE) {
@@ -77,6 +81,7 @@ particle_chunk(Work w, const int32_t* __restrict__ d_nactive, Out out,
       }
     }
   }
+  if (!valid) return;
   if (reason != ST_ACTIVE) {
     const int k = w.slot[i];
     out.r[3 * k + 0] = x; out.r[3 * k + 1] = y; out.r[3 * k + 2] = z;
@@ -91,10 +96,79 @@ particle_chunk(Work w, const int32_t* __restrict__ d_nactive, Out out,
   }
 }
 
+// Work queue of one chunk: item = (sub-chunk s, tile t) in s-major order,
+// tile = 64 consecutive working-set entries (one wavefront).  Wavefronts take
+// items from a monotonic counter, so a wavefront that shares its SIMD with
+// other work (or sits alone on one) simply takes fewer items.  Item (s, t)
+// waits for item (s-1, t) through a per-tile progress counter; that item was
+// taken earlier by a running wavefront, so the wait always ends.  A wait
+// longer than the spin limit flags an error and drops the item.
+struct QueueArgs {
+  unsigned long long* ctr;     // monotonic item counter
+  unsigned long long base;     // counter value at this launch's start
+  uint32_t* progress;          // per tile: sub-chunks completed (monotonic over launches)
+  uint32_t epoch;              // progress value of every tile at this launch's start
+  int ntiles, nsub, sub_steps, nsteps;
+  int32_t* error;
+};
+
+constexpr uint32_t SPIN_LIMIT = 1u << 22;   // about 4 s of polling
+
+TPM_DEV unsigned long long wave_uniform(unsigned long long v) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// No part of the item loop runs on a subset of the lanes: the grab, the wait
+// and the publish are executed by the whole wavefront (lane 0 alone adds 1 to
+// the counter), so the readfirstlane that makes their results wave-uniform
+// always sees the full wavefront and the loop's branches stay scalar.
+template <int NP, int KIT>
+__global__ void __launch_bounds__(256)
+particle_queue(Work w, const int32_t* __restrict__ d_nactive, Out out,
+               const double* __restrict__ rows, ChunkArgs<NP> A, QueueArgs Q) {
+  const int lane = threadIdx.x & 63;
+  const int n = *d_nactive;
+  const unsigned long long total = (unsigned long long)Q.ntiles * Q.nsub;
+  const unsigned long long one = lane == 0 ? 1ull : 0ull;
+  for (;;) {
+    const unsigned long long item = wave_uniform(atomicAdd(Q.ctr, one) - Q.base);
+    if (item >= total) break;
+    const int s = (int)(item / Q.ntiles);
+    const int t = (int)(item % Q.ntiles);
+    bool go = true;
+    if (s > 0) {
+      const uint32_t target = Q.epoch + (uint32_t)s;
+      uint32_t spins = 0;
+      for (;;) {
+        const uint32_t p = (uint32_t)__builtin_amdgcn_readfirstlane(
+            (int)__hip_atomic_load(Q.progress + t, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+        if ((int32_t)(p - target) >= 0) break;
+        if (++spins > SPIN_LIMIT) {
+          atomicOr(Q.error, 1);
+          go = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    const int s_begin = s * Q.sub_steps;
+    const int s_end = min(Q.nsteps, s_begin + Q.sub_steps);
+    if (go && s_begin < s_end) {       // the last sub-chunks of a short chunk may be empty
+      const int i = t * 64 + lane;
+      advance<NP, KIT>(w, out, rows, A, i, i < n, s_begin, s_end);
+    }
+    // publish completion; the release orders every store of this item
+    __hip_atomic_store(Q.progress + t, Q.epoch + (uint32_t)s + 1u, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 template <int NP>
 static hipError_t launch_np(const SysConst& S, Work w, const int32_t* d_nactive, int grid_n,
                             Out out, const double* rows, int nsteps, double dt, int64_t step0,
-                            int block, hipStream_t st) {
+                            const QueueLaunch& QL, hipStream_t st) {
   ChunkArgs<NP> A;
   for (int j = 0; j < NP; ++j) { A.P.mu[j] = S.mu[j]; A.P.rcrit2[j] = S.rcrit2[j]; }
   if (NP == 0) { A.P.mu[0] = 0.0; A.P.rcrit2[0] = 0.0; }
@@ -105,39 +179,64 @@ static hipError_t launch_np(const SysConst& S, Work w, const int32_t* d_nactive,
   A.kiters = S.kiters;
   A.nsteps = nsteps;
   A.step0 = step0;
-  int grid = (grid_n + block - 1) / block;
-  if (grid <= 0) return hipSuccess;
+  QueueArgs Q;
+  Q.ctr = QL.ctr;
+  Q.base = QL.base;
+  Q.progress = QL.progress;
+  Q.epoch = QL.epoch;
+  Q.ntiles = (grid_n + 63) / 64;
+  Q.nsub = QL.nsub;
+  Q.sub_steps = (nsteps + QL.nsub - 1) / QL.nsub;
+  Q.nsteps = nsteps;
+  Q.error = QL.error;
+  if (Q.ntiles <= 0) return hipSuccess;
+  const int waves_per_block = QL.block / 64;
+  const int nblocks = (QL.workers + waves_per_block - 1) / waves_per_block;
   if (S.kiters == 5)
-    hipLaunchKernelGGL((particle_chunk<NP, 5>), dim3(grid), dim3(block), 0, st, w, d_nactive, out, rows, A);
+    hipLaunchKernelGGL((particle_queue<NP, 5>), dim3(nblocks), dim3(QL.block), 0, st, w, d_nactive,
+                       out, rows, A, Q);
   else
-    hipLaunchKernelGGL((particle_chunk<NP, 0>), dim3(grid), dim3(block), 0, st, w, d_nactive, out, rows, A);
+    hipLaunchKernelGGL((particle_queue<NP, 0>), dim3(nblocks), dim3(QL.block), 0, st, w, d_nactive,
+                       out, rows, A, Q);
   return hipGetLastError();
 }
 
 hipError_t launch_particle_chunk(const SysConst& S, Work w, const int32_t* d_nactive, int grid_n,
                                  Out out, const double* rows, int nsteps, double dt, int64_t step0,
-                                 int block, hipStream_t st) {
+                                 const QueueLaunch& QL, hipStream_t st) {
   switch (S.np) {
-    case 0: return launch_np<0>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, block, st);
-    case 1: return launch_np<1>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, block, st);
-    case 2: return launch_np<2>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, block, st);
-    case 3: return launch_np<3>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, block, st);
-    case 4: return launch_np<4>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, block, st);
-    case 5: return launch_np<5>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, block, st);
-    case 6: return launch_np<6>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, block, st);
-    case 7: return launch_np<7>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, block, st);
-    case 8: return launch_np<8>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, block, st);
+    case 0: return launch_np<0>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, QL, st);
+    case 1: return launch_np<1>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, QL, st);
+    case 2: return launch_np<2>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, QL, st);
+    case 3: return launch_np<3>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, QL, st);
+    case 4: return launch_np<4>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, QL, st);
+    case 5: return launch_np<5>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, QL, st);
+    case 6: return launch_np<6>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, QL, st);
+    case 7: return launch_np<7>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, QL, st);
+    case 8: return launch_np<8>(S, w, d_nactive, grid_n, out, rows, nsteps, dt, step0, QL, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 // ---------------------------------------------------------------- ephemeris
-// Value of v held by lane src (wave64 cross-lane read).
-TPM_DEV double lane_read(double v, int src) { return __shfl(v, src, 64); }
+// The planet map is a serial chain in time, so this kernel is written for
+// latency: one wavefront, lane b (1..NP) holds Jacobi body b, lane 0 the
+// central body.  Values every lane needs are broadcast with v_readlane into
+// scalar registers (no LDS round trip), and everything per step is branch-free
+// except the wave-uniform Newton loop of the planets' Kepler drifts.
 
-// Heliocentric positions of bodies 1..NP from the Jacobi positions held by
-// lanes 1..NP: r_b = r'_b + R_{b-1}, R_b = (eta_{b-1} R_{b-1} + mu_b r_b)/eta_b.
-// Every lane computes the whole chain and keeps all positions.
+// Value of v on lane `src` (a compile-time constant), returned wave-uniform.
+TPM_DEV double bcast(double v, int src) {
+  uint64_t u = __builtin_bit_cast(uint64_t, v);
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Heliocentric positions of bodies 0..NP (body 0 at the origin) from the
+// Jacobi positions held by lanes 1..NP:
+//   r_b = r'_b + R_{b-1},  R_b = (eta_{b-1} R_{b-1} + mu_b r_b) / eta_b.
+// The results are wave-uniform.
 template <int NP>
 TPM_DEV void helio_all(const EphConst& E, double jx, double jy, double jz,
                        double (&hx)[NP + 1], double (&hy)[NP + 1], double (&hz)[NP + 1]) {
@@ -145,87 +244,87 @@ TPM_DEV void helio_all(const EphConst& E, double jx, double jy, double jz,
   hx[0] = 0.0; hy[0] = 0.0; hz[0] = 0.0;
 #pragma unroll
   for (int b = 1; b <= NP; ++b) {
-    double px = lane_read(jx, b) + Rx;
-    double py = lane_read(jy, b) + Ry;
-    double pz = lane_read(jz, b) + Rz;
+    double px = bcast(jx, b) + Rx;
+    double py = bcast(jy, b) + Ry;
+    double pz = bcast(jz, b) + Rz;
     hx[b] = px; hy[b] = py; hz[b] = pz;
-    // (eta_{b-1} R + mu_b r_b) / eta_b
     Rx = fma_(E.eta[b - 1], Rx, E.mu[b] * px) * E.inv_eta[b];
     Ry = fma_(E.eta[b - 1], Ry, E.mu[b] * py) * E.inv_eta[b];
     Rz = fma_(E.eta[b - 1], Rz, E.mu[b] * pz) * E.inv_eta[b];
   }
 }
 
-// Interaction acceleration of Jacobi body `lane` (lanes 1..NP) and, on lane 0,
-// the central body's acceleration a_0 (h0 = -a_0).
-//   a'_b = a_b - (sum_{k<b} mu_k a_k)/eta_{b-1} + mu'_b r'_b/|r'_b|^3
+// Per-lane constants of the planet map.
+struct EphLane {
+  int lane;
+  bool body;
+  double mu_self, mup, ie_prev;   // mu_b, mu'_b, 1/eta_{b-1}
+  KepConst K;                     // Kepler constant mu'_b for the drift
+};
+
+// Interaction acceleration of the lane's Jacobi body (lanes 1..NP):
+//   a'_b = a_b - (sum_{k<b} mu_k a_k)/eta_{b-1} + mu'_b r'_b/|r'_b|^3,
+// with a_k the Newtonian acceleration of body k; lane 0 gets a_0 (h0 = -a_0).
 template <int NP>
-TPM_DEV void eph_accel(const EphConst& E, int lane, double jx, double jy, double jz,
+TPM_DEV void eph_accel(const EphConst& E, const EphLane& L, double jx, double jy, double jz,
                        const double (&hx)[NP + 1], const double (&hy)[NP + 1],
                        const double (&hz)[NP + 1], double& ax, double& ay, double& az) {
-  // own heliocentric position
-  double ox = 0.0, oy = 0.0, oz = 0.0;
+  double ox = hx[0], oy = hy[0], oz = hz[0];
 #pragma unroll
-  for (int b = 0; b <= NP; ++b)
-    if (lane == b) { ox = hx[b]; oy = hy[b]; oz = hz[b]; }
-  // Newtonian acceleration of body `lane`
+  for (int b = 1; b <= NP; ++b) {
+    ox = (L.lane == b) ? hx[b] : ox;
+    oy = (L.lane == b) ? hy[b] : oy;
+    oz = (L.lane == b) ? hz[b] : oz;
+  }
   double nx = 0.0, ny = 0.0, nz = 0.0;
 #pragma unroll
   for (int l = 0; l <= NP; ++l) {
     double dx = ox - hx[l], dy = oy - hy[l], dz = oz - hz[l];
     double d2 = fma_(dx, dx, fma_(dy, dy, dz * dz));
-    bool self = (l == lane);
+    bool self = (l == L.lane);
     double inv = rsqrt(self ? 1.0 : d2);
     double k = self ? 0.0 : E.mu[l] * (inv * inv) * inv;
     nx = fma_(-k, dx, nx);
     ny = fma_(-k, dy, ny);
     nz = fma_(-k, dz, nz);
   }
-  // S = sum_{k<lane} mu_k a_k
+  // sum_{k<b} mu_k a_k from the broadcast Newtonian accelerations
   double sx = 0.0, sy = 0.0, sz = 0.0;
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    double kx = lane_read(nx, k), ky = lane_read(ny, k), kz = lane_read(nz, k);
-    if (k < lane) {
-      sx = fma_(E.mu[k], kx, sx);
-      sy = fma_(E.mu[k], ky, sy);
-      sz = fma_(E.mu[k], kz, sz);
-    }
+    double kx = bcast(nx, k), ky = bcast(ny, k), kz = bcast(nz, k);
+    bool use = k < L.lane;
+    sx = use ? fma_(E.mu[k], kx, sx) : sx;
+    sy = use ? fma_(E.mu[k], ky, sy) : sy;
+    sz = use ? fma_(E.mu[k], kz, sz) : sz;
   }
-  if (lane >= 1 && lane <= NP) {
-    double ie = 0.0, mup = 0.0;
-#pragma unroll
-    for (int b = 1; b <= NP; ++b)
-      if (lane == b) { ie = E.inv_eta[b - 1]; mup = E.mup[b]; }
-    double r2 = fma_(jx, jx, fma_(jy, jy, jz * jz));
-    double inv = rsqrt(r2);
-    double k = mup * (inv * inv) * inv;
-    ax = fma_(k, jx, fma_(-sx, ie, nx));
-    ay = fma_(k, jy, fma_(-sy, ie, ny));
-    az = fma_(k, jz, fma_(-sz, ie, nz));
-  } else {
-    ax = nx; ay = ny; az = nz;
-  }
+  double r2 = fma_(jx, jx, fma_(jy, jy, jz * jz));
+  double inv = rsqrt(L.body ? r2 : 1.0);
+  double kk = L.mup * (inv * inv) * inv;
+  ax = L.body ? fma_(kk, jx, fma_(-sx, L.ie_prev, nx)) : nx;
+  ay = L.body ? fma_(kk, jy, fma_(-sy, L.ie_prev, ny)) : ny;
+  az = L.body ? fma_(kk, jz, fma_(-sz, L.ie_prev, nz)) : nz;
 }
 
+// Any pair (lane, j > lane) closer than their mutual Hill radius.
 template <int NP>
-TPM_DEV bool hill_violation(const EphConst& E, int lane, const double (&hx)[NP + 1],
-                            const double (&hy)[NP + 1], const double (&hz)[NP + 1]) {
+TPM_DEV bool hill_violation(const EphLane& L, const double (&hill2row)[NP + 1],
+                            const double (&hx)[NP + 1], const double (&hy)[NP + 1],
+                            const double (&hz)[NP + 1]) {
+  double ox = hx[0], oy = hy[0], oz = hz[0];
+#pragma unroll
+  for (int b = 1; b <= NP; ++b) {
+    ox = (L.lane == b) ? hx[b] : ox;
+    oy = (L.lane == b) ? hy[b] : oy;
+    oz = (L.lane == b) ? hz[b] : oz;
+  }
   bool bad = false;
 #pragma unroll
-  for (int i = 1; i <= NP; ++i)
-#pragma unroll
-    for (int j = i + 1; j <= NP; ++j) {
-      if (lane != i) continue;
-      double dx = hx[i] - hx[j], dy = hy[i] - hy[j], dz = hz[i] - hz[j];
-      double d2 = fma_(dx, dx, fma_(dy, dy, dz * dz));
-      double ri = rsqrt(fma_(hx[i], hx[i], fma_(hy[i], hy[i], hz[i] * hz[i])));
-      double rj = rsqrt(fma_(hx[j], hx[j], fma_(hy[j], hy[j], hz[j] * hz[j])));
-      double ri_ = fma_(hx[i], hx[i], fma_(hy[i], hy[i], hz[i] * hz[i])) * ri;
-      double rj_ = fma_(hx[j], hx[j], fma_(hy[j], hy[j], hz[j] * hz[j])) * rj;
-      double lim = E.hill[i][j] * (ri_ + rj_);
-      bad = bad || (d2 < lim * lim);
-    }
+  for (int j = 2; j <= NP; ++j) {
+    double dx = ox - hx[j], dy = oy - hy[j], dz = oz - hz[j];
+    double d2 = fma_(dx, dx, fma_(dy, dy, dz * dz));
+    bad = bad || (L.body && j > L.lane && d2 < hill2row[j]);
+  }
   return bad;
 }
 
@@ -235,54 +334,100 @@ ephemeris_chunk(EphConst E, double* __restrict__ rj, double* __restrict__ vj,
                 double* __restrict__ rows, int nsteps, double dt, int64_t step0,
                 int64_t* __restrict__ flag) {
   constexpr int ROW = 3 * NP + 3;
-  const int lane = threadIdx.x;
-  const bool body = lane >= 1 && lane <= NP;
-  double jx = 0, jy = 0, jz = 0, wx = 0, wy = 0, wz = 0;
-  if (body) {
-    jx = rj[3 * (lane - 1) + 0]; jy = rj[3 * (lane - 1) + 1]; jz = rj[3 * (lane - 1) + 2];
-    wx = vj[3 * (lane - 1) + 0]; wy = vj[3 * (lane - 1) + 1]; wz = vj[3 * (lane - 1) + 2];
-  }
-  double mup = 0.0;
+  // This wave is a serial chain that shares its SIMD with particle waves:
+  // let it issue first.
+  __builtin_amdgcn_s_setprio(3);
+  EphLane L;
+  L.lane = threadIdx.x;
+  L.body = L.lane >= 1 && L.lane <= NP;
+  L.mu_self = 0.0; L.mup = 1.0; L.ie_prev = 0.0;
+  double hill2row[NP + 1];
 #pragma unroll
-  for (int b = 1; b <= NP; ++b)
-    if (lane == b) mup = E.mup[b];
+  for (int j = 0; j <= NP; ++j) hill2row[j] = 0.0;
+#pragma unroll
+  for (int b = 1; b <= NP; ++b) {
+    if (L.lane == b) {
+      L.mu_self = E.mu[b]; L.mup = E.mup[b]; L.ie_prev = E.inv_eta[b - 1];
+#pragma unroll
+      for (int j = 0; j <= NP; ++j) hill2row[j] = E.hill2[b][j];
+    }
+  }
+  {
+    double smu, rsmu;
+    sqrt_rsqrt(L.mup, smu, rsmu);
+    L.K = KepConst{L.mup, rcp(L.mup), smu, rsmu};
+  }
+  double jx = 0, jy = 0, jz = 0, wx = 0, wy = 0, wz = 0;
+  if (L.body) {
+    jx = rj[3 * (L.lane - 1) + 0]; jy = rj[3 * (L.lane - 1) + 1]; jz = rj[3 * (L.lane - 1) + 2];
+    wx = vj[3 * (L.lane - 1) + 0]; wy = vj[3 * (L.lane - 1) + 1]; wz = vj[3 * (L.lane - 1) + 2];
+  }
   double hx[NP + 1], hy[NP + 1], hz[NP + 1];
   double ax, ay, az;
   helio_all<NP>(E, jx, jy, jz, hx, hy, hz);
-  eph_accel<NP>(E, lane, jx, jy, jz, hx, hy, hz, ax, ay, az);
-  // row 0: current state
-  if (body) {
-    rows[3 * (lane - 1) + 0] = hx[lane];
-    rows[3 * (lane - 1) + 1] = hy[lane];
-    rows[3 * (lane - 1) + 2] = hz[lane];
-  } else if (lane == 0) {
+  eph_accel<NP>(E, L, jx, jy, jz, hx, hy, hz, ax, ay, az);
+  // row 0: current state; lane b writes planet b, lane 0 writes h0 = -a_0
+  double ownx = hx[0], owny = hy[0], ownz = hz[0];
+#pragma unroll
+  for (int b = 1; b <= NP; ++b) {
+    ownx = (L.lane == b) ? hx[b] : ownx;
+    owny = (L.lane == b) ? hy[b] : owny;
+    ownz = (L.lane == b) ? hz[b] : ownz;
+  }
+  if (L.body) {
+    rows[3 * (L.lane - 1) + 0] = ownx;
+    rows[3 * (L.lane - 1) + 1] = owny;
+    rows[3 * (L.lane - 1) + 2] = ownz;
+  } else if (L.lane == 0) {
     rows[3 * NP + 0] = -ax; rows[3 * NP + 1] = -ay; rows[3 * NP + 2] = -az;
   }
   const double h = 0.5 * dt;
-  int64_t bad_step = -1;
+  int64_t first_bad = -1;      // per lane: first step with a close pair
+  if (NP > 1 && hill_violation<NP>(L, hill2row, hx, hy, hz)) first_bad = step0;
+  bool unbound = false;
   for (int s = 0; s < nsteps; ++s) {
     wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
-    bool bound = drift_converged(body ? mup : 1.0, dt, body, jx, jy, jz, wx, wy, wz);
-    if (bad_step == -1 && __any(body && !bound)) bad_step = -2;
+    bool bound = drift_converged(L.K, dt, L.body, jx, jy, jz, wx, wy, wz);
+    unbound = unbound || (L.body && !bound);
     helio_all<NP>(E, jx, jy, jz, hx, hy, hz);
-    eph_accel<NP>(E, lane, jx, jy, jz, hx, hy, hz, ax, ay, az);
+    eph_accel<NP>(E, L, jx, jy, jz, hx, hy, hz, ax, ay, az);
     wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
     double* row = rows + (size_t)(s + 1) * ROW;
-    if (body) {
-      row[3 * (lane - 1) + 0] = hx[lane];
-      row[3 * (lane - 1) + 1] = hy[lane];
-      row[3 * (lane - 1) + 2] = hz[lane];
-    } else if (lane == 0) {
+    ownx = hx[0]; owny = hy[0]; ownz = hz[0];
+#pragma unroll
+    for (int b = 1; b <= NP; ++b) {
+      ownx = (L.lane == b) ? hx[b] : ownx;
+      owny = (L.lane == b) ? hy[b] : owny;
+      ownz = (L.lane == b) ? hz[b] : ownz;
+    }
+    if (L.body) {
+      row[3 * (L.lane - 1) + 0] = ownx;
+      row[3 * (L.lane - 1) + 1] = owny;
+      row[3 * (L.lane - 1) + 2] = ownz;
+    } else if (L.lane == 0) {
       row[3 * NP + 0] = -ax; row[3 * NP + 1] = -ay; row[3 * NP + 2] = -az;
     }
-    if (bad_step == -1 && NP > 1 && __any(hill_violation<NP>(E, lane, hx, hy, hz)))
-      bad_step = step0 + s + 1;
+    if (NP > 1) {
+      bool bad = hill_violation<NP>(L, hill2row, hx, hy, hz);
+      first_bad = (first_bad < 0 && bad) ? step0 + s + 1 : first_bad;
+    }
   }
-  if (body) {
-    rj[3 * (lane - 1) + 0] = jx; rj[3 * (lane - 1) + 1] = jy; rj[3 * (lane - 1) + 2] = jz;
-    vj[3 * (lane - 1) + 0] = wx; vj[3 * (lane - 1) + 1] = wy; vj[3 * (lane - 1) + 2] = wz;
+  if (L.body) {
+    rj[3 * (L.lane - 1) + 0] = jx; rj[3 * (L.lane - 1) + 1] = jy; rj[3 * (L.lane - 1) + 2] = jz;
+    vj[3 * (L.lane - 1) + 0] = wx; vj[3 * (L.lane - 1) + 1] = wy; vj[3 * (L.lane - 1) + 2] = wz;
   }
-  if (lane == 0 && bad_step != -1 && *flag == -1) *flag = bad_step;
+  // reduce the flags over the wavefront: unbound -> -2, else the earliest step
+  bool any_unbound = __any(unbound);
+  int64_t fb = first_bad < 0 ? INT64_MAX : first_bad;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    int64_t o = __shfl_xor(fb, off, 64);
+    fb = o < fb ? o : fb;
+  }
+  if (L.lane == 0 && *flag == -1) {
+    if (any_unbound) *flag = -2;
+    else if (fb != INT64_MAX) *flag = fb;
+  }
 }
 
 template <int NP>

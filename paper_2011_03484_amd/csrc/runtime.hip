@@ -40,7 +40,8 @@ int fail(int code, const std::string& msg) {
                   std::string(#expr) + ": " + hipGetErrorString(e_));                   \
   } while (0)
 
-constexpr int NSLOT = 8;
+constexpr int NSLOT = 8;   // planet-table ring slots
+constexpr int NCNT = 8;    // in-flight active-count readbacks
 
 template <class T>
 void dfree(T*& p) {
@@ -66,6 +67,7 @@ struct tpm_sim {
   int np = 0;
   std::vector<int> perm;                 // internal planet index -> caller index
   std::vector<double> mu_s, rcrit_s;     // internal (sorted) order
+  std::vector<double> a_s;               // initial osculating semi-major axes, sorted
   double* d_rj = nullptr;                // Jacobi planet state [np][3]
   double* d_vj = nullptr;
   double* d_tmp = nullptr;               // [4][np][3] scratch for conversions
@@ -76,7 +78,9 @@ struct tpm_sim {
   int32_t* d_nactive = nullptr;
   int32_t* d_scratch = nullptr;
   Out out{};
-  int32_t* h_pin = nullptr;
+  int32_t* h_pin = nullptr;             // [0..NCNT) active counts, [16..] scratch
+  hipEvent_t ev_cnt[NCNT]{};             // one per in-flight count readback
+  int64_t cnt_issued = 0, cnt_seen = 0;  // readbacks issued / consumed
   unsigned long long* d_acc = nullptr;
   int n_active = 0;                      // host copy (upper bound between compactions)
   double* d_ring = nullptr;
@@ -84,6 +88,12 @@ struct tpm_sim {
   double* d_table = nullptr;             // caller-supplied table (optional)
   int64_t table_rows = 0;
   int64_t step = 0;
+  int ncu = 0;                           // compute units of the device
+  unsigned long long* d_qctr = nullptr;  // work-queue item counter
+  uint32_t* d_progress = nullptr;        // per-tile progress counters
+  int32_t* d_qerr = nullptr;             // work-queue error flag
+  unsigned long long q_base = 0;         // host copy of the item counter
+  uint32_t q_epoch = 0;                  // host copy of the tiles' progress
   tpm_stats stats{};
   std::vector<hipEvent_t> kev;           // per-launch timing events (time_kernels)
 
@@ -98,6 +108,9 @@ struct tpm_sim {
     dfree(out.r); dfree(out.v); dfree(out.step); dfree(out.reason); dfree(out.planet);
     out = Out{};
     dfree(d_scratch); d_scratch = nullptr;
+    dfree(d_qctr); dfree(d_progress); dfree(d_qerr);
+    q_base = 0;
+    q_epoch = 0;
     n = 0;
     particles_set = false;
   }
@@ -116,6 +129,7 @@ struct tpm_sim {
     }
     for (auto e : {t0P, t1P, t0E, t1E}) if (e) (void)hipEventDestroy(e);
     for (auto e : kev) (void)hipEventDestroy(e);
+    for (auto e : ev_cnt) if (e) (void)hipEventDestroy(e);
     dfree(d_flag); dfree(d_nactive); dfree(d_acc);
     if (h_pin) (void)hipHostFree(h_pin);
   }
@@ -150,8 +164,10 @@ struct tpm_sim {
       E.mup[b] = mu0 * E.eta[b] / E.eta[b - 1];
     }
     for (int i = 1; i <= np; ++i)
-      for (int j = 1; j <= np; ++j)
-        E.hill[i][j] = 0.5 * std::cbrt((E.mu[i] + E.mu[j]) / (3.0 * mu0));
+      for (int j = 1; j <= np; ++j) {
+        double rh = std::cbrt((E.mu[i] + E.mu[j]) / (3.0 * mu0)) * 0.5 * (a_s[i - 1] + a_s[j - 1]);
+        E.hill2[i][j] = rh * rh;
+      }
     return E;
   }
 };
@@ -207,6 +223,8 @@ void tpm_default_options(tpm_options* o) {
   o->chunk_steps = 0;
   o->resync_chunks = 0;
   o->block_threads = 0;
+  o->sub_chunks = 0;
+  o->waves_per_simd = 0;
   o->r_escape = 0.0;
   o->kepler_ftol = 0.0;
   o->device = 0;
@@ -227,8 +245,12 @@ int tpm_create(const tpm_options* opt, tpm_sim** out) {
   if (opt) o = *opt;
   if (o.kepler_iters <= 0) o.kepler_iters = 5;
   if (o.kepler_iters > 64) return fail(TPM_EINVAL, "kepler_iters > 64");
-  if (o.chunk_steps < 0 || o.resync_chunks < 0 || o.block_threads < 0)
+  if (o.chunk_steps < 0 || o.resync_chunks < 0 || o.block_threads < 0 || o.sub_chunks < 0 ||
+      o.waves_per_simd < 0)
     return fail(TPM_EINVAL, "negative option");
+  if (o.sub_chunks == 0) o.sub_chunks = 4;
+  if (o.waves_per_simd == 0) o.waves_per_simd = 2;
+  if (o.waves_per_simd > 8) return fail(TPM_EINVAL, "waves_per_simd > 8");
   if (o.chunk_steps == 0) o.chunk_steps = 1024;
   if (o.resync_chunks == 0) o.resync_chunks = 4;
   if (o.block_threads == 0) o.block_threads = 64;
@@ -248,6 +270,7 @@ int tpm_create(const tpm_options* opt, tpm_sim** out) {
   TPM_HIP(hipSetDevice(o.device));
   tpm_sim* s = new tpm_sim();
   s->opt = o;
+  s->ncu = prop.multiProcessorCount;
   auto bad = [&](hipError_t e, const char* what) {
     if (e == hipSuccess) return false;
     fail(TPM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -269,7 +292,12 @@ int tpm_create(const tpm_options* opt, tpm_sim** out) {
       bad(hipMalloc(&s->d_flag, sizeof(int64_t)), "alloc") ||
       bad(hipMalloc(&s->d_nactive, sizeof(int32_t)), "alloc") ||
       bad(hipMalloc(&s->d_acc, sizeof(unsigned long long)), "alloc") ||
-      bad(hipHostMalloc(&s->h_pin, 64, hipHostMallocDefault), "pinned alloc")) {
+      bad(hipHostMalloc(&s->h_pin, 256, hipHostMallocDefault), "pinned alloc")) {
+    delete s;
+    return TPM_EDEVICE;
+  }
+  for (int i = 0; i < NCNT; ++i)
+    if (bad(hipEventCreateWithFlags(&s->ev_cnt[i], hipEventDisableTiming), "event")) {
     delete s;
     return TPM_EDEVICE;
   }
@@ -327,11 +355,13 @@ int tpm_set_planets(tpm_sim* s, int32_t np, const double* mu, const double* r, c
   std::stable_sort(s->perm.begin(), s->perm.end(), [&](int x, int y) { return a[x] < a[y]; });
   s->mu_s.resize(np);
   s->rcrit_s.resize(np);
+  s->a_s.resize(np);
   std::vector<double> rs(3 * np), vs(3 * np);
   for (int j = 0; j < np; ++j) {
     int c = s->perm[j];
     s->mu_s[j] = mu[c];
     s->rcrit_s[j] = r_crit[c];
+    s->a_s[j] = a[c];
     for (int k = 0; k < 3; ++k) { rs[3 * j + k] = r[3 * c + k]; vs[3 * j + k] = v[3 * c + k]; }
   }
   size_t b = sizeof(double) * 3 * std::max(np, 1);
@@ -372,6 +402,13 @@ int tpm_set_particles(tpm_sim* s, int64_t n, const double* r, const double* v) {
   TPM_HIP(hipMalloc(&s->out.step, nn * 8)); TPM_HIP(hipMalloc(&s->out.reason, nn * 4));
   TPM_HIP(hipMalloc(&s->out.planet, nn * 4));
   TPM_HIP(hipMalloc(&s->d_scratch, sizeof(int32_t) * compact_scratch_ints((int)nn)));
+  const size_t ntiles = (nn + 63) / 64;
+  TPM_HIP(hipMalloc(&s->d_qctr, sizeof(unsigned long long)));
+  TPM_HIP(hipMalloc(&s->d_progress, sizeof(uint32_t) * ntiles));
+  TPM_HIP(hipMalloc(&s->d_qerr, sizeof(int32_t)));
+  TPM_HIP(hipMemset(s->d_qctr, 0, sizeof(unsigned long long)));
+  TPM_HIP(hipMemset(s->d_progress, 0, sizeof(uint32_t) * ntiles));
+  TPM_HIP(hipMemset(s->d_qerr, 0, sizeof(int32_t)));
   // structure-of-arrays layout for the kernels
   std::vector<double> col(n);
   Work& w = s->work[0];
@@ -455,6 +492,37 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   s->stats.compactions = 0;
   TPM_HIP(hipEventRecord(s->t0P, s->sP));
   TPM_HIP(hipEventRecord(s->t0E, s->sE));
+  // The planet map is enqueued up to NSLOT-1 chunks ahead of the particles so
+  // that it keeps running while the host waits on anything else.
+  int64_t eph_next = 0;
+  auto enqueue_eph = [&](int64_t upto) -> int {
+    for (; eph_next <= upto && eph_next < nchunks; ++eph_next) {
+      const int64_t c = eph_next;
+      const int ks = (int)std::min<int64_t>(K, nsteps - c * K);
+      const int slot = (int)(c % NSLOT);
+      double* srow = s->d_ring + (size_t)slot * s->ring_rows * rl;
+      TPM_HIP(hipStreamWaitEvent(s->sE, s->ev_done[slot], 0));
+      TPM_HIP(launch_ephemeris_chunk(E, s->d_rj, s->d_vj, srow, ks, dt, s->step + c * K,
+                                     s->d_flag, s->sE));
+      TPM_HIP(hipEventRecord(s->ev_eph[slot], s->sE));
+    }
+    return TPM_OK;
+  };
+  // Newest active count whose readback has completed (never blocks); the
+  // count is only an upper bound for the grid, the kernels read the exact
+  // value on the device.
+  auto poll_counts = [&]() -> int {
+    while (s->cnt_seen < s->cnt_issued) {
+      hipEvent_t e = s->ev_cnt[s->cnt_seen % NCNT];
+      hipError_t q = hipEventQuery(e);
+      if (q == hipErrorNotReady) break;
+      TPM_HIP(q);
+      s->n_active = std::min(s->n_active, (int)s->h_pin[s->cnt_seen % NCNT]);
+      s->cnt_seen++;
+    }
+    return TPM_OK;
+  };
+  int n_grid = s->n_active;
   for (int64_t c = 0; c < nchunks; ++c) {
     const int ks = (int)std::min<int64_t>(K, nsteps - c * K);
     const int slot = (int)(c % NSLOT);
@@ -463,38 +531,72 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
     if (s->d_table) {
       rows = s->d_table + (size_t)step0 * rl;
     } else {
-      double* srow = s->d_ring + (size_t)slot * s->ring_rows * rl;
-      TPM_HIP(hipStreamWaitEvent(s->sE, s->ev_done[slot], 0));
-      TPM_HIP(launch_ephemeris_chunk(E, s->d_rj, s->d_vj, srow, ks, dt, step0, s->d_flag, s->sE));
-      TPM_HIP(hipEventRecord(s->ev_eph[slot], s->sE));
+      int rc = enqueue_eph(c + NSLOT - 1);
+      if (rc) return rc;
       TPM_HIP(hipStreamWaitEvent(s->sP, s->ev_eph[slot], 0));
-      rows = srow;
+      rows = s->d_ring + (size_t)slot * s->ring_rows * rl;
     }
-    if (s->n_active > 0) {
+    {
+      int rc = poll_counts();
+      if (rc) return rc;
+      n_grid = std::min(n_grid, s->n_active);
+    }
+    if (n_grid > 0) {
       Work& w = s->work[s->cur];
       if (timed) TPM_HIP(hipEventRecord(s->kev[2 * s->stats.chunks], s->sP));
-      TPM_HIP(launch_particle_chunk(S, w, s->d_nactive, s->n_active, s->out, rows, ks, dt, step0,
-                                    s->opt.block_threads, s->sP));
+      QueueLaunch QL;
+      QL.ctr = s->d_qctr;
+      QL.base = s->q_base;
+      QL.progress = s->d_progress;
+      QL.epoch = s->q_epoch;
+      QL.nsub = std::max(1, std::min(s->opt.sub_chunks, ks));
+      const int ntiles = (n_grid + 63) / 64;
+      QL.workers = std::max(1, std::min(ntiles * QL.nsub, 4 * s->ncu * s->opt.waves_per_simd));
+      QL.workers = std::min(QL.workers, ntiles);
+      QL.block = s->opt.block_threads;
+      QL.error = s->d_qerr;
+      TPM_HIP(launch_particle_chunk(S, w, s->d_nactive, n_grid, s->out, rows, ks, dt, step0, QL,
+                                    s->sP));
+      // every wavefront takes exactly one failing item at the end
+      const int wpb = QL.block / 64;
+      const unsigned long long waves = (unsigned long long)((QL.workers + wpb - 1) / wpb) * wpb;
+      s->q_base += (unsigned long long)ntiles * QL.nsub + waves;
+      s->q_epoch += (uint32_t)QL.nsub;
       if (timed) TPM_HIP(hipEventRecord(s->kev[2 * s->stats.chunks + 1], s->sP));
       s->stats.chunks++;
     }
     TPM_HIP(hipEventRecord(s->ev_done[slot], s->sP));
     const bool last = (c == nchunks - 1);
-    if (s->n_active > 0 && (((c + 1) % R == 0) || last)) {
+    if (n_grid > 0 && (((c + 1) % R == 0) || last)) {
       Work& src = s->work[s->cur];
       Work& dst = s->work[1 - s->cur];
-      TPM_HIP(launch_compact(src, dst, s->d_nactive, s->n_active, s->d_scratch, s->sP));
-      TPM_HIP(hipMemcpyAsync(s->h_pin, s->d_nactive, 4, hipMemcpyDeviceToHost, s->sP));
-      TPM_HIP(hipStreamSynchronize(s->sP));
-      s->n_active = s->h_pin[0];
+      TPM_HIP(launch_compact(src, dst, s->d_nactive, n_grid, s->d_scratch, s->sP));
       s->cur = 1 - s->cur;
       s->stats.compactions++;
+      if (s->cnt_issued - s->cnt_seen >= NCNT) {       // ring full: wait for the oldest
+        TPM_HIP(hipEventSynchronize(s->ev_cnt[s->cnt_seen % NCNT]));
+        int rc = poll_counts();
+        if (rc) return rc;
+      }
+      const int k = (int)(s->cnt_issued % NCNT);
+      TPM_HIP(hipMemcpyAsync(s->h_pin + k, s->d_nactive, 4, hipMemcpyDeviceToHost, s->sP));
+      TPM_HIP(hipEventRecord(s->ev_cnt[k], s->sP));
+      s->cnt_issued++;
     }
   }
   TPM_HIP(hipEventRecord(s->t1P, s->sP));
   TPM_HIP(hipEventRecord(s->t1E, s->sE));
   TPM_HIP(hipStreamSynchronize(s->sE));
   TPM_HIP(hipStreamSynchronize(s->sP));
+  {
+    int rc = poll_counts();
+    if (rc) return rc;
+  }
+  {
+    int32_t qerr = 0;
+    TPM_HIP(hipMemcpy(&qerr, s->d_qerr, sizeof(qerr), hipMemcpyDeviceToHost));
+    if (qerr) return fail(TPM_EDEVICE, "particle work queue: a wait exceeded its limit");
+  }
   s->step += nsteps;
   float msP = 0.f, msE = 0.f;
   TPM_HIP(hipEventElapsedTime(&msP, s->t0P, s->t1P));
@@ -503,9 +605,9 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   TPM_HIP(hipMemsetAsync(s->d_acc, 0, sizeof(unsigned long long), s->sP));
   TPM_HIP(launch_active_steps(s->out.step, (int)s->n, step_begin, s->step, s->d_acc, s->sP));
   unsigned long long acc = 0;
-  TPM_HIP(hipMemcpyAsync(s->h_pin, s->d_acc, sizeof(acc), hipMemcpyDeviceToHost, s->sP));
+  TPM_HIP(hipMemcpyAsync(s->h_pin + 16, s->d_acc, sizeof(acc), hipMemcpyDeviceToHost, s->sP));
   TPM_HIP(hipStreamSynchronize(s->sP));
-  std::memcpy(&acc, s->h_pin, sizeof(acc));
+  std::memcpy(&acc, s->h_pin + 16, sizeof(acc));
   auto w1 = std::chrono::steady_clock::now();
   double kms = 0.0;
   if (timed)

@@ -262,6 +262,23 @@ def test_kepler_failure_removal(tpm, orc):
     assert g["reason"][0] == tpm.KEPLER and g["deact_step"][0] == 0
 
 
+def test_planet_close_pair_reported(tpm, orc):
+    """Planets inside a mutual Hill radius: both sides flag it (the planet map
+    assumes no planet-planet encounters)."""
+    mu0 = W.MU_SUN
+    mu = np.array([1e-3, 1e-3]) * mu0
+    rp, vp = W.elements_to_cartesian(mu0 + mu, np.array([5.0, 5.05]), np.zeros(2), np.zeros(2),
+                                     np.zeros(2), np.zeros(2), np.array([0.0, 0.01]))
+    assert orc.ephemeris(mu0, mu, rp, vp, 10, 0.1).flag == 0
+    s = tpm.Simulation()
+    s.set_central(mu0)
+    s.set_planets(mu, rp, vp, np.zeros(2))
+    s.set_particles([[20.0, 0, 0]], [[0, math.sqrt(mu0 / 20.0), 0]])
+    with pytest.raises(tpm.PlanetEncounterError):
+        s.integrate(10, 0.1)
+    assert s.particles()["reason"][0] == tpm.ACTIVE
+
+
 # ------------------------------------------------------- invariance and resume
 def _run(tpm, w, T, **opts):
     s = _sim(tpm, w, **opts)
@@ -278,7 +295,10 @@ def test_results_do_not_depend_on_tuning(tpm):
     assert np.sum(base["reason"] != 0) > 10
     for opts in ({"chunk_steps": 64, "resync_chunks": 1}, {"chunk_steps": 333, "resync_chunks": 3},
                  {"chunk_steps": 1000, "block_threads": 256}, {"chunk_steps": 7, "resync_chunks": 50,
-                                                               "block_threads": 128}):
+                                                               "block_threads": 128},
+                 {"chunk_steps": 5, "sub_chunks": 4}, {"chunk_steps": 512, "sub_chunks": 16,
+                                                        "waves_per_simd": 1},
+                 {"chunk_steps": 256, "sub_chunks": 1, "waves_per_simd": 8}):
         o = _run(tpm, w, T, **opts)
         for k in ("r", "v", "deact_step", "reason", "planet"):
             assert np.array_equal(o[k], base[k]), (opts, k)
