@@ -48,6 +48,37 @@ def cpu_baseline(w, n_sample: int, steps_sample: int):
                       f"{active} active particle-steps)"}
 
 
+def adjoint_ratio(P, W, torch, nsteps: int, n: int, ckpt: int):
+    """Forward (with checkpoints) and backward of loss = sum |r_T|^2 on the
+    16,384-particle four-planet workload; returns times and their ratio."""
+    from paper_2011_03484_amd import autograd as AG
+    w = W.adjoint_16k(n=n)
+    s = P.Simulation(r_escape=w.rmax, kepler_iters=w.kepler_iters)
+    s.set_central(w.mu0)
+    s.set_planets(w.mu, w.rp, w.vp, w.rcrit)
+    r0 = torch.tensor(w.r, dtype=torch.float64, device="cuda").requires_grad_(True)
+    v0 = torch.tensor(w.v, dtype=torch.float64, device="cuda").requires_grad_(True)
+    # warm-up on a short run
+    rT, vT, _, _ = AG.integrate(s, r0, v0, 2 * ckpt, w.dt, ckpt)
+    (rT ** 2).sum().backward()
+    r0.grad = v0.grad = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rT, vT, step, reason = AG.integrate(s, r0, v0, nsteps, w.dt, ckpt)
+    loss = (rT ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    survivors = int((reason == 0).sum().item())
+    s.close()
+    return {"workload": f"adjoint_16k: {n} particles, 4 planets, {nsteps} steps, checkpoint every "
+                        f"{ckpt}, loss = sum |r_T|^2",
+            "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
+            "survivors": survivors}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +92,8 @@ def main():
     ap.add_argument("--cpu-particles", type=int, default=16384)
     ap.add_argument("--cpu-steps", type=int, default=10000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=100_000)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device with a plain copy "
                          "kernel (the reference for scaling HBM byte counters)")
@@ -144,6 +177,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = nbytes
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_ratio(P, W, torch, args.adjoint_steps, 16_384, 1000)
+        print("adjoint done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_particles, args.cpu_steps)
     print(json.dumps(line))

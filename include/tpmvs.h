@@ -142,6 +142,36 @@ int tpm_planet_table(tpm_sim* sim, int64_t nsteps, double dt, double* table);
  * returns to the planet map.  Meant for checking the particle kernel alone. */
 int tpm_set_planet_table(tpm_sim* sim, const double* table, int64_t nrows);
 
+/* ---- derivatives of the particle map ---------------------------------------
+ * Device-pointer calls for autograd frameworks: every array is caller-owned
+ * device memory, [n][3] row-major float64 unless stated; work is enqueued on
+ * the caller's HIP stream `stream` (NULL = null stream) without synchronising,
+ * so outputs are ready when that stream reaches them.  The planets are not
+ * differentiated.  A removed particle keeps the state of its removal step, so
+ * its derivative is that of the map up to that step.
+ *
+ * tpm_ad_forward: integrates n particles from (d_r0, d_v0) for nsteps steps of
+ * dt through the planets set on sim (their state is not advanced) and writes
+ * d_rT, d_vT, d_step[n] (int64, removal step or -1) and d_reason[n] (int32)
+ * (those two may be NULL).  It keeps, inside sim, the planet table of the run
+ * and the particle states every ckpt_every steps; they are the context of the
+ * next tpm_ad_backward / tpm_ad_tangent (one context per sim: a new forward
+ * replaces it).
+ * tpm_ad_backward: vector-Jacobian product (dL/dr_0, dL/dv_0) from
+ * (dL/dr_T, dL/dv_T): each segment of ckpt_every steps is recomputed from its
+ * checkpoint, its states written to a tape of ckpt_every x 48 n bytes, and swept
+ * backwards.
+ * tpm_ad_tangent: Jacobian-vector product (d r_T, d v_T) from (d r_0, d v_0)
+ * for the run of the last forward.
+ * TPM_ESTATE if no forward has been run. */
+int tpm_ad_forward(tpm_sim* sim, int64_t n, const double* d_r0, const double* d_v0,
+                   int64_t nsteps, double dt, int32_t ckpt_every, double* d_rT, double* d_vT,
+                   int64_t* d_step, int32_t* d_reason, void* stream);
+int tpm_ad_backward(tpm_sim* sim, const double* d_gRT, const double* d_gVT, double* d_gR0,
+                    double* d_gV0, void* stream);
+int tpm_ad_tangent(tpm_sim* sim, const double* d_dR0, const double* d_dV0, double* d_dRT,
+                   double* d_dVT, void* stream);
+
 /* ---- unit entry points of the device math (host arrays) -------------------- */
 /* sin and cos of x[n] by the library's branch-free FP64 routine. */
 int tpm_debug_sincos(int64_t n, const double* x, double* s, double* c);

@@ -72,6 +72,10 @@ SIGNATURES = {
     "tpm_debug_sincos": (C.c_int, [C.c_int64, _P, _P, _P]),
     "tpm_debug_drift": (C.c_int, [C.c_double, C.c_int64, _P, _P, _P, C.c_double, C.c_int32,
                                   C.c_double]),
+    "tpm_ad_forward": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int64, C.c_double, C.c_int32, _P, _P,
+                                 _P, _P, _P]),
+    "tpm_ad_backward": (C.c_int, [_P] * 6),
+    "tpm_ad_tangent": (C.c_int, [_P] * 6),
 }
 
 _lib = None

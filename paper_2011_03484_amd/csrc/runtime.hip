@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/tpmvs.h"
+#include "ad_internal.h"
 #include "internal.h"
 
 using namespace tpm;
@@ -95,9 +96,36 @@ struct tpm_sim {
   unsigned long long q_base = 0;         // host copy of the item counter
   uint32_t q_epoch = 0;                  // host copy of the tiles' progress
   tpm_stats stats{};
+  // automatic-differentiation context of the last tpm_ad_forward
+  struct AD {
+    int64_t n = 0, nsteps = 0;
+    int ckpt = 0, nseg = 0;
+    double dt = 0.0;
+    double* table = nullptr;      // [nsteps+1][3np+3]
+    double* ckpts = nullptr;      // [nseg+1][6][n]
+    double* tape = nullptr;       // [ckpt][6][n]
+    double* work = nullptr;       // [2][6][n]
+    int64_t* dstep = nullptr;
+    int32_t* reason = nullptr;
+    int32_t* planet = nullptr;
+    int32_t* treason = nullptr;   // tangent's own removal flags
+    size_t cap_table = 0, cap_ckpts = 0, cap_tape = 0, cap_n = 0;
+    bool valid = false;
+  } ad;
   std::vector<hipEvent_t> kev;           // per-launch timing events (time_kernels)
 
-  ~tpm_sim() { release_particles(); release_planets(); release_ring(); release_base(); }
+  ~tpm_sim() {
+    release_ad();
+    release_particles();
+    release_planets();
+    release_ring();
+    release_base();
+  }
+  void release_ad() {
+    dfree(ad.table); dfree(ad.ckpts); dfree(ad.tape); dfree(ad.work);
+    dfree(ad.dstep); dfree(ad.reason); dfree(ad.planet); dfree(ad.treason);
+    ad = AD{};
+  }
 
   void release_particles() {
     for (auto& w : work) {
@@ -769,6 +797,151 @@ int tpm_debug_drift(double mu, int64_t n, const double* rv_in, double* rv_out, i
   TPM_HIP(hipMemcpy(rv_out, dout, n * 48, hipMemcpyDeviceToHost));
   TPM_HIP(hipMemcpy(ok, dok, n * 4, hipMemcpyDeviceToHost));
   dfree(di); dfree(dout); dfree(dok);
+  return TPM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ derivatives
+namespace {
+
+template <class T>
+int grow(T*& p, size_t& cap, size_t want) {
+  if (cap >= want && p) return TPM_OK;
+  dfree(p);
+  TPM_HIP(hipMalloc(&p, sizeof(T) * std::max<size_t>(want, 1)));
+  cap = want;
+  return TPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tpm_ad_forward(tpm_sim* s, int64_t n, const double* d_r0, const double* d_v0, int64_t nsteps,
+                   double dt, int32_t ckpt_every, double* d_rT, double* d_vT, int64_t* d_step,
+                   int32_t* d_reason, void* stream) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  if (!s->planets_set) return fail(TPM_ESTATE, "set central mass and planets first");
+  if (n < 0 || n >= (int64_t(1) << 31) || nsteps < 0 || nsteps >= (int64_t(1) << 31) ||
+      ckpt_every <= 0)
+    return fail(TPM_EINVAL, "bad sizes");
+  if (n > 0 && (!d_r0 || !d_v0 || !d_rT || !d_vT)) return fail(TPM_EINVAL, "NULL array");
+  if (!std::isfinite(dt) || dt == 0.0) return fail(TPM_EINVAL, "dt must be finite and non-zero");
+  TPM_HIP(hipSetDevice(s->opt.device));
+  hipStream_t st = (hipStream_t)stream;
+  auto& A = s->ad;
+  A.valid = false;
+  const int rl = 3 * s->np + 3;
+  const int nseg = (int)((nsteps + ckpt_every - 1) / ckpt_every);
+  size_t cap_n = A.cap_n;
+  {
+    int rc;
+    if ((rc = grow(A.table, A.cap_table, (size_t)(nsteps + 1) * rl))) return rc;
+    if ((rc = grow(A.ckpts, A.cap_ckpts, (size_t)(nseg + 1) * 6 * n))) return rc;
+    if (cap_n < (size_t)n || !A.work) {
+      dfree(A.work); dfree(A.dstep); dfree(A.reason); dfree(A.planet); dfree(A.treason);
+      const size_t nn = std::max<size_t>(n, 1);
+      TPM_HIP(hipMalloc(&A.work, sizeof(double) * 12 * nn));
+      TPM_HIP(hipMalloc(&A.dstep, sizeof(int64_t) * nn));
+      TPM_HIP(hipMalloc(&A.reason, sizeof(int32_t) * nn));
+      TPM_HIP(hipMalloc(&A.planet, sizeof(int32_t) * nn));
+      TPM_HIP(hipMalloc(&A.treason, sizeof(int32_t) * nn));
+      A.cap_n = n;
+    }
+  }
+  A.n = n;
+  A.nsteps = nsteps;
+  A.ckpt = ckpt_every;
+  A.nseg = nseg;
+  A.dt = dt;
+  // planet table of the whole run from the current planet state (not advanced)
+  {
+    const size_t b = sizeof(double) * 3 * std::max(s->np, 1);
+    double* rj = s->d_tmp + 6 * std::max(s->np, 1);
+    double* vj = rj + 3 * std::max(s->np, 1);
+    TPM_HIP(hipStreamSynchronize(s->sE));
+    TPM_HIP(hipMemcpyAsync(rj, s->d_rj, b, hipMemcpyDeviceToDevice, st));
+    TPM_HIP(hipMemcpyAsync(vj, s->d_vj, b, hipMemcpyDeviceToDevice, st));
+    const EphConst E = s->eph();
+    const int K = s->opt.chunk_steps;
+    for (int64_t c = 0; c == 0 || c * K < nsteps; ++c) {
+      const int ks = (int)std::min<int64_t>(K, nsteps - c * K);
+      TPM_HIP(launch_ephemeris_chunk(E, rj, vj, A.table + (size_t)c * K * rl, ks, dt, c * K,
+                                     s->d_flag, st));
+      if (nsteps == 0) break;
+    }
+  }
+  const SysConst S = s->sys();
+  TPM_HIP(launch_aos_to_soa(d_r0, d_v0, A.ckpts, n, st));
+  for (int k = 0; k < nseg; ++k) {
+    const int s0 = k * ckpt_every;
+    const int s1 = (int)std::min<int64_t>(nsteps, (int64_t)s0 + ckpt_every);
+    TPM_HIP(launch_ad_segment(S, dt, n, s0, s1, A.table, A.ckpts + (size_t)k * 6 * n,
+                              A.ckpts + (size_t)(k + 1) * 6 * n, nullptr, A.dstep, A.reason,
+                              A.planet, k == 0 ? 0 : 1, st));
+  }
+  if (nseg == 0) {
+    // no step: only the checks at step 0
+    TPM_HIP(launch_ad_segment(S, dt, n, 0, 0, A.table, A.ckpts, nullptr, nullptr, A.dstep,
+                              A.reason, A.planet, 0, st));
+  }
+  TPM_HIP(launch_soa_to_aos(A.ckpts + (size_t)nseg * 6 * n, d_rT, d_vT, n, st));
+  if (d_step) TPM_HIP(hipMemcpyAsync(d_step, A.dstep, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st));
+  if (d_reason) TPM_HIP(hipMemcpyAsync(d_reason, A.reason, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+  A.valid = true;
+  return TPM_OK;
+}
+
+int tpm_ad_backward(tpm_sim* s, const double* d_gRT, const double* d_gVT, double* d_gR0,
+                    double* d_gV0, void* stream) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  auto& A = s->ad;
+  if (!A.valid) return fail(TPM_ESTATE, "no tpm_ad_forward to differentiate");
+  const int64_t n = A.n;
+  if (n > 0 && (!d_gRT || !d_gVT || !d_gR0 || !d_gV0)) return fail(TPM_EINVAL, "NULL array");
+  TPM_HIP(hipSetDevice(s->opt.device));
+  hipStream_t st = (hipStream_t)stream;
+  {
+    int rc = grow(A.tape, A.cap_tape, (size_t)A.ckpt * 6 * n);
+    if (rc) return rc;
+  }
+  const SysConst S = s->sys();
+  double* lam = A.work;
+  TPM_HIP(launch_aos_to_soa(d_gRT, d_gVT, lam, n, st));
+  for (int k = A.nseg - 1; k >= 0; --k) {
+    const int s0 = k * A.ckpt;
+    const int s1 = (int)std::min<int64_t>(A.nsteps, (int64_t)s0 + A.ckpt);
+    // recompute the segment from its checkpoint, recording the state at the
+    // start of every step
+    TPM_HIP(launch_ad_segment(S, A.dt, n, s0, s1, A.table, A.ckpts + (size_t)k * 6 * n, nullptr,
+                              A.tape, A.dstep, nullptr, nullptr, 2, st));
+    TPM_HIP(launch_ad_reverse(S, A.dt, n, s0, s1, A.table, A.tape, lam, A.dstep, st));
+  }
+  TPM_HIP(launch_soa_to_aos(lam, d_gR0, d_gV0, n, st));
+  return TPM_OK;
+}
+
+int tpm_ad_tangent(tpm_sim* s, const double* d_dR0, const double* d_dV0, double* d_dRT,
+                   double* d_dVT, void* stream) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  auto& A = s->ad;
+  if (!A.valid) return fail(TPM_ESTATE, "no tpm_ad_forward to differentiate");
+  const int64_t n = A.n;
+  if (n > 0 && (!d_dR0 || !d_dV0 || !d_dRT || !d_dVT)) return fail(TPM_EINVAL, "NULL array");
+  TPM_HIP(hipSetDevice(s->opt.device));
+  hipStream_t st = (hipStream_t)stream;
+  const SysConst S = s->sys();
+  double* state = A.work;
+  double* tang = A.work + 6 * n;
+  TPM_HIP(hipMemcpyAsync(state, A.ckpts, sizeof(double) * 6 * n, hipMemcpyDeviceToDevice, st));
+  TPM_HIP(launch_aos_to_soa(d_dR0, d_dV0, tang, n, st));
+  for (int k = 0; k < A.nseg; ++k) {
+    const int s0 = k * A.ckpt;
+    const int s1 = (int)std::min<int64_t>(A.nsteps, (int64_t)s0 + A.ckpt);
+    TPM_HIP(launch_ad_tangent(S, A.dt, n, s0, s1, A.table, state, tang, A.treason, k == 0, st));
+  }
+  TPM_HIP(launch_soa_to_aos(tang, d_dRT, d_dVT, n, st));
   return TPM_OK;
 }
 
