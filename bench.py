@@ -79,6 +79,22 @@ def adjoint_ratio(P, W, torch, nsteps: int, n: int, ckpt: int):
             "survivors": survivors}
 
 
+def batched_run(P, W, nsteps: int):
+    """512 independent systems (Np 1..8, ~0.86M particles) in one graph launch."""
+    systems = W.make_batched(nsteps=nsteps)
+    t0 = time.perf_counter()
+    res, st = P.batch_integrate(systems, nsteps=nsteps)
+    t1 = time.perf_counter()
+    n = sum(w.n for w in systems)
+    return {"workload": f"batched_512: 512 systems, Np U{{1..8}}, {n} particles, dt = P_inner/30, "
+                        f"{nsteps} steps, one HIP-graph launch",
+            "value": st["active_particle_steps"] / (st["particle_ms"] / 1e3),
+            "unit": "particle-steps/s", "graph_ms": st["particle_ms"],
+            "call_s_incl_setup_and_tuning": t1 - t0,
+            "active_particle_steps": st["active_particle_steps"],
+            "queue_shape": {"sub_chunks": st["sub_chunks"], "waves_per_simd": st["waves_per_simd"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +110,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=100_000)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=100_000)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device with a plain copy "
                          "kernel (the reference for scaling HBM byte counters)")
@@ -180,6 +198,9 @@ def main():
     if not args.no_adjoint:
         line["adjoint"] = adjoint_ratio(P, W, torch, args.adjoint_steps, 16_384, 1000)
         print("adjoint done", file=sys.stderr, flush=True)
+    if not args.no_batched:
+        line["batched"] = batched_run(P, W, args.batched_steps)
+        print("batched done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_particles, args.cpu_steps)
     print(json.dumps(line))

@@ -82,6 +82,8 @@ typedef struct {
                                      particle launches alone (only with time_kernels) */
   int64_t compactions;            /* compactions in the last integrate            */
   int64_t count_by_reason[4];     /* over all particles                           */
+  int32_t sub_chunks;             /* work-queue shape used (after autotuning)     */
+  int32_t waves_per_simd;
 } tpm_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -171,6 +173,29 @@ int tpm_ad_backward(tpm_sim* sim, const double* d_gRT, const double* d_gVT, doub
                     double* d_gV0, void* stream);
 int tpm_ad_tangent(tpm_sim* sim, const double* d_dR0, const double* d_dV0, double* d_dRT,
                    double* d_dVT, void* stream);
+
+/* ---- many systems in one launch ---------------------------------------------
+ * nsys independent systems (central mass, 0..8 planets, particles, own time
+ * step) advanced by the same number of steps.  Host arrays; CSR-style offsets:
+ * system s has planets planet_off[s]..planet_off[s+1]-1 (mu_p, rp[.][3],
+ * vp[.][3], rcrit) and particles part_off[s]..part_off[s+1]-1 (r[.][3],
+ * v[.][3]); mu0[s], dt[s].  Outputs as in tpm_get_particles (planet indices
+ * local to the particle's system, caller order).  r_escape, kepler_iters,
+ * kepler_ftol, chunk_steps, block_threads and device come from opt (NULL =
+ * defaults); sub_chunks / waves_per_simd <= 0 select them by timing a short
+ * trial of each candidate (the choice is cached and never changes results).
+ * The planet maps of all systems run as one launch per chunk and the
+ * particles of all systems as one work queue (tiles of 64 particles of one
+ * system, most planets first); the whole run is captured into one HIP graph
+ * and launched once.  stats (may be NULL) receives the graph's run time and
+ * the active particle-steps.  Returns TPM_EPLANET (results written) if any
+ * system's planets came within a mutual Hill radius. */
+int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_t* planet_off,
+                        const double* mu_p, const double* rp, const double* vp,
+                        const double* rcrit, const int64_t* part_off, const double* r,
+                        const double* v, const double* dt, int64_t nsteps,
+                        const tpm_options* opt, double* r_out, double* v_out, int64_t* step_out,
+                        int32_t* reason_out, int32_t* planet_out, tpm_stats* stats);
 
 /* ---- unit entry points of the device math (host arrays) -------------------- */
 /* sin and cos of x[n] by the library's branch-free FP64 routine. */

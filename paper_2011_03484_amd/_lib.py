@@ -43,7 +43,8 @@ class Stats(C.Structure):
                 ("active_particle_steps", C.c_int64), ("wall_ms", C.c_double),
                 ("particle_ms", C.c_double), ("ephemeris_ms", C.c_double), ("chunks", C.c_int64),
                 ("particle_kernel_ms", C.c_double), ("compactions", C.c_int64),
-                ("count_by_reason", C.c_int64 * 4)]
+                ("count_by_reason", C.c_int64 * 4), ("sub_chunks", C.c_int32),
+                ("waves_per_simd", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "count_by_reason"}
@@ -76,6 +77,8 @@ SIGNATURES = {
                                  _P, _P, _P]),
     "tpm_ad_backward": (C.c_int, [_P] * 6),
     "tpm_ad_tangent": (C.c_int, [_P] * 6),
+    "tpm_batch_integrate": (C.c_int, [C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_int64,
+                                      _P, _P, _P, _P, _P, _P, _P]),
 }
 
 _lib = None
@@ -229,6 +232,46 @@ def debug_drift(mu, r, v, dt, kepler_iters=5, kepler_ftol=0.0):
     _check(load().tpm_debug_drift(float(mu), r.shape[0], _p(rv), _p(out), _p(ok), float(dt),
                                   int(kepler_iters), float(kepler_ftol)))
     return out[:, :3], out[:, 3:], ok.astype(bool)
+
+
+def batch_integrate(systems, nsteps=None, r_escape=None, kepler_iters=5, chunk_steps=0,
+                    sub_chunks=0, waves_per_simd=0, block_threads=0):
+    """Integrate many independent systems (workload objects) in one launch.
+
+    Returns (per-system list of result dicts, stats dict)."""
+    nsys = len(systems)
+    mu0 = np.array([w.mu0 for w in systems], dtype=np.float64)
+    poff = np.zeros(nsys + 1, np.int32)
+    poff[1:] = np.cumsum([w.np_ for w in systems])
+    qoff = np.zeros(nsys + 1, np.int64)
+    qoff[1:] = np.cumsum([w.n for w in systems])
+    cat = lambda xs, shape: np.ascontiguousarray(np.concatenate(xs) if len(xs) else np.zeros(shape))
+    mu_p = cat([w.mu for w in systems], (0,))
+    rp = cat([w.rp.reshape(-1, 3) for w in systems], (0, 3))
+    vp = cat([w.vp.reshape(-1, 3) for w in systems], (0, 3))
+    rc = cat([w.rcrit for w in systems], (0,))
+    r = cat([w.r for w in systems], (0, 3))
+    v = cat([w.v for w in systems], (0, 3))
+    dt = np.array([w.dt for w in systems], dtype=np.float64)
+    T = systems[0].nsteps if nsteps is None else int(nsteps)
+    o = default_options()
+    o.kepler_iters, o.chunk_steps, o.sub_chunks = kepler_iters, chunk_steps, sub_chunks
+    o.waves_per_simd, o.block_threads = waves_per_simd, block_threads
+    o.r_escape = systems[0].rmax if r_escape is None else r_escape
+    n = int(qoff[-1])
+    ro, vo = np.zeros((n, 3)), np.zeros((n, 3))
+    st = np.zeros(n, np.int64)
+    rs = np.zeros(n, np.int32)
+    pl = np.zeros(n, np.int32)
+    stats = Stats()
+    rc_ = load().tpm_batch_integrate(nsys, _p(mu0), _p(poff), _p(mu_p), _p(rp), _p(vp), _p(rc),
+                                     _p(qoff), _p(r), _p(v), _p(dt), T, C.byref(o), _p(ro), _p(vo),
+                                     _p(st), _p(rs), _p(pl), C.byref(stats))
+    out = [{"r": ro[qoff[i]:qoff[i + 1]], "v": vo[qoff[i]:qoff[i + 1]],
+            "deact_step": st[qoff[i]:qoff[i + 1]], "reason": rs[qoff[i]:qoff[i + 1]],
+            "planet": pl[qoff[i]:qoff[i + 1]]} for i in range(nsys)]
+    _check(rc_)
+    return out, stats.as_dict()
 
 
 def run_workload(w, nsteps=None, **opts):

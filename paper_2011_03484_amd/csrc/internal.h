@@ -28,6 +28,10 @@ struct Out {
   int32_t* planet;
 };
 
+struct KepConst {
+  double mu, inv_mu, sqrt_mu, inv_sqrt_mu;
+};
+
 struct SysConst {
   int np;
   double mu0, inv_mu0, sqrt_mu0, inv_sqrt_mu0;
@@ -95,6 +99,44 @@ hipError_t launch_helio_to_jacobi(const EphConst& E, const double* h, double* j,
 // backward run the range is taken in absolute order).
 hipError_t launch_active_steps(const int64_t* dstep, int n, int64_t step_begin, int64_t step_end,
                                unsigned long long* acc, hipStream_t st);
+
+// ---- many systems in one launch
+// Per-system constants of the batched particle kernel (device array).
+struct SysDev {
+  int np, kiters;
+  double ftol, rmax2, dt;
+  KepConst K;
+  double mu[MAX_NP];
+  double rcrit2[MAX_NP];
+  int64_t ring_off;      // offset (doubles) of this system's planet-table ring
+};
+
+// 64 consecutive working-set entries of one system.
+struct TileDesc {
+  int32_t sys, first, count, pad;
+};
+
+struct BatchQueueArgs {
+  unsigned long long* ctr;
+  unsigned long long base;
+  uint32_t* progress;
+  uint32_t epoch;
+  int ntiles, nsub, sub_steps, nsteps;
+  int64_t step0;
+  int slot;
+  int64_t slot_rows;     // rows per ring slot (chunk + 1)
+  int32_t* error;
+};
+
+hipError_t launch_ephemeris_batch(const EphConst* E, double* rj, double* vj, double* ring,
+                                  const int64_t* ring_off, int slot, int64_t slot_stride_rows,
+                                  int nsys, int nsteps, const double* dt, int64_t step0,
+                                  int64_t* flag, hipStream_t st);
+hipError_t launch_helio_to_jacobi_batch(const EphConst* E, const double* h, double* j, int nsys,
+                                        hipStream_t st);
+hipError_t launch_particle_batch(const SysDev* sys, const TileDesc* tiles, Work w, Out out,
+                                 const double* ring, const BatchQueueArgs& Q, int workers,
+                                 int block, hipStream_t st);
 
 // Unit checks of the device math (test entry points).
 hipError_t launch_sincos_test(const double* x, double* s, double* c, int n, hipStream_t st);

@@ -19,6 +19,7 @@
 // beyond pi are reduced by whole periods.
 #pragma once
 #include "dmath.hpp"
+#include "internal.h"
 
 namespace tpm {
 
@@ -26,9 +27,6 @@ constexpr double TWO_PI_HI = 0x1.921fb54442d18p+2;
 constexpr double TWO_PI_LO = 0x1.1a62633145c07p-52;
 constexpr double INV_TWO_PI = 0x1.45f306dc9c883p-3;
 
-struct KepConst {
-  double mu, inv_mu, sqrt_mu, inv_sqrt_mu;
-};
 
 // Drift (x, v) by dt about mass mu with k fixed Newton iterations.  Writes the
 // drifted state into (x, v) only where the return value is true.

@@ -165,6 +165,96 @@ particle_queue(Work w, const int32_t* __restrict__ d_nactive, Out out,
   }
 }
 
+// ---------------------------------------------------------- many systems
+// Item (s, t) of the batched queue: tile t (64 particles of one system, so the
+// planet row stays wave-uniform) through sub-chunk s; the tile's system picks
+// the planet count, constants, time step and table rows.
+template <int NP>
+TPM_DEV void batch_item(const SysDev& S, Work w, Out out, const double* __restrict__ ring,
+                        const BatchQueueArgs& Q, const TileDesc& T, int s_begin, int s_end,
+                        int lane) {
+  ChunkArgs<NP> A;
+#pragma unroll
+  for (int j = 0; j < (NP > 0 ? NP : 1); ++j) {
+    A.P.mu[j] = NP > 0 ? S.mu[j] : 0.0;
+    A.P.rcrit2[j] = NP > 0 ? S.rcrit2[j] : 0.0;
+  }
+  A.K = S.K;
+  A.rmax2 = S.rmax2;
+  A.ftol = S.ftol;
+  A.dt = S.dt;
+  A.kiters = S.kiters;
+  A.nsteps = Q.nsteps;
+  A.step0 = Q.step0;
+  const double* rows = ring + S.ring_off + (int64_t)Q.slot * Q.slot_rows * (3 * NP + 3);
+  const int i = T.first + lane;
+  const bool valid = lane < T.count;
+  if (S.kiters == 5)
+    advance<NP, 5>(w, out, rows, A, i, valid, s_begin, s_end);
+  else
+    advance<NP, 0>(w, out, rows, A, i, valid, s_begin, s_end);
+}
+
+__global__ void __launch_bounds__(256)
+particle_batch_queue(const SysDev* __restrict__ sys, const TileDesc* __restrict__ tiles, Work w,
+                     Out out, const double* __restrict__ ring, BatchQueueArgs Q) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long total = (unsigned long long)Q.ntiles * Q.nsub;
+  const unsigned long long one = lane == 0 ? 1ull : 0ull;
+  for (;;) {
+    const unsigned long long item = wave_uniform(atomicAdd(Q.ctr, one) - Q.base);
+    if (item >= total) break;
+    const int s = (int)(item / Q.ntiles);
+    const int t = (int)(item % Q.ntiles);
+    bool go = true;
+    if (s > 0) {
+      const uint32_t target = Q.epoch + (uint32_t)s;
+      uint32_t spins = 0;
+      for (;;) {
+        const uint32_t p = (uint32_t)__builtin_amdgcn_readfirstlane(
+            (int)__hip_atomic_load(Q.progress + t, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+        if ((int32_t)(p - target) >= 0) break;
+        if (++spins > SPIN_LIMIT) {
+          atomicOr(Q.error, 1);
+          go = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    const int s_begin = s * Q.sub_steps;
+    const int s_end = min(Q.nsteps, s_begin + Q.sub_steps);
+    if (go && s_begin < s_end) {
+      const TileDesc T = tiles[t];
+      const SysDev& S = sys[T.sys];
+      switch (S.np) {
+        case 0: batch_item<0>(S, w, out, ring, Q, T, s_begin, s_end, lane); break;
+        case 1: batch_item<1>(S, w, out, ring, Q, T, s_begin, s_end, lane); break;
+        case 2: batch_item<2>(S, w, out, ring, Q, T, s_begin, s_end, lane); break;
+        case 3: batch_item<3>(S, w, out, ring, Q, T, s_begin, s_end, lane); break;
+        case 4: batch_item<4>(S, w, out, ring, Q, T, s_begin, s_end, lane); break;
+        case 5: batch_item<5>(S, w, out, ring, Q, T, s_begin, s_end, lane); break;
+        case 6: batch_item<6>(S, w, out, ring, Q, T, s_begin, s_end, lane); break;
+        case 7: batch_item<7>(S, w, out, ring, Q, T, s_begin, s_end, lane); break;
+        default: batch_item<8>(S, w, out, ring, Q, T, s_begin, s_end, lane); break;
+      }
+    }
+    __hip_atomic_store(Q.progress + t, Q.epoch + (uint32_t)s + 1u, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+hipError_t launch_particle_batch(const SysDev* sys, const TileDesc* tiles, Work w, Out out,
+                                 const double* ring, const BatchQueueArgs& Q, int workers,
+                                 int block, hipStream_t st) {
+  if (Q.ntiles <= 0) return hipSuccess;
+  const int wpb = block / 64;
+  const int nblocks = (workers + wpb - 1) / wpb;
+  hipLaunchKernelGGL(particle_batch_queue, dim3(nblocks), dim3(block), 0, st, sys, tiles, w, out,
+                     ring, Q);
+  return hipGetLastError();
+}
+
 template <int NP>
 static hipError_t launch_np(const SysConst& S, Work w, const int32_t* d_nactive, int grid_n,
                             Out out, const double* rows, int nsteps, double dt, int64_t step0,
@@ -329,10 +419,9 @@ TPM_DEV bool hill_violation(const EphLane& L, const double (&hill2row)[NP + 1],
 }
 
 template <int NP>
-__global__ void __launch_bounds__(64)
-ephemeris_chunk(EphConst E, double* __restrict__ rj, double* __restrict__ vj,
-                double* __restrict__ rows, int nsteps, double dt, int64_t step0,
-                int64_t* __restrict__ flag) {
+TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* __restrict__ vj,
+                            double* __restrict__ rows, int nsteps, double dt, int64_t step0,
+                            int64_t* __restrict__ flag) {
   constexpr int ROW = 3 * NP + 3;
   // This wave is a serial chain that shares its SIMD with particle waves:
   // let it issue first.
@@ -428,6 +517,49 @@ ephemeris_chunk(EphConst E, double* __restrict__ rj, double* __restrict__ vj,
     if (any_unbound) *flag = -2;
     else if (fb != INT64_MAX) *flag = fb;
   }
+}
+
+template <int NP>
+__global__ void __launch_bounds__(64)
+ephemeris_chunk(EphConst E, double* __restrict__ rj, double* __restrict__ vj,
+                double* __restrict__ rows, int nsteps, double dt, int64_t step0,
+                int64_t* __restrict__ flag) {
+  ephemeris_body<NP>(E, rj, vj, rows, nsteps, dt, step0, flag);
+}
+
+// Many systems at once: workgroup b runs system b (its constants, Jacobi
+// state, table rows and flag are found through the per-system arrays).
+__global__ void __launch_bounds__(64)
+ephemeris_batch(const EphConst* __restrict__ E, double* __restrict__ rj, double* __restrict__ vj,
+                double* __restrict__ ring, const int64_t* __restrict__ ring_off, int slot,
+                int64_t slot_stride_rows, int nsteps, const double* __restrict__ dt,
+                int64_t step0, int64_t* __restrict__ flag) {
+  const int b = blockIdx.x;
+  const EphConst& e = E[b];
+  double* rows = ring + ring_off[b] + (int64_t)slot * slot_stride_rows * (3 * e.np + 3);
+  double* r = rj + 3 * MAX_NP * b;
+  double* v = vj + 3 * MAX_NP * b;
+  switch (e.np) {
+    case 1: ephemeris_body<1>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 2: ephemeris_body<2>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 3: ephemeris_body<3>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 4: ephemeris_body<4>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 5: ephemeris_body<5>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 6: ephemeris_body<6>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 7: ephemeris_body<7>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 8: ephemeris_body<8>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    default: ephemeris_body<0>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+  }
+}
+
+hipError_t launch_ephemeris_batch(const EphConst* E, double* rj, double* vj, double* ring,
+                                  const int64_t* ring_off, int slot, int64_t slot_stride_rows,
+                                  int nsys, int nsteps, const double* dt, int64_t step0,
+                                  int64_t* flag, hipStream_t st) {
+  if (nsys <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ephemeris_batch, dim3(nsys), dim3(64), 0, st, E, rj, vj, ring, ring_off, slot,
+                     slot_stride_rows, nsteps, dt, step0, flag);
+  return hipGetLastError();
 }
 
 template <int NP>
@@ -527,6 +659,36 @@ hipError_t launch_helio_to_jacobi(const EphConst& E, const double* h, double* j,
 #undef TPM_H2J
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// Heliocentric -> Jacobi for many systems: workgroup b converts system b's
+// planets (arrays [nsys][MAX_NP][3]).
+__global__ void __launch_bounds__(64)
+helio_to_jacobi_batch(const EphConst* __restrict__ E, const double* __restrict__ h,
+                      double* __restrict__ j) {
+  const int b = blockIdx.x;
+  const EphConst& e = E[b];
+  const int lane = threadIdx.x;
+  if (lane < 1 || lane > e.np) return;
+  const double* hb = h + 3 * MAX_NP * b;
+  double* jb = j + 3 * MAX_NP * b;
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  for (int k = 1; k < lane; ++k) {
+    sx = fma_(e.mu[k], hb[3 * (k - 1) + 0], sx);
+    sy = fma_(e.mu[k], hb[3 * (k - 1) + 1], sy);
+    sz = fma_(e.mu[k], hb[3 * (k - 1) + 2], sz);
+  }
+  const double ie = e.inv_eta[lane - 1];
+  jb[3 * (lane - 1) + 0] = fma_(-sx, ie, hb[3 * (lane - 1) + 0]);
+  jb[3 * (lane - 1) + 1] = fma_(-sy, ie, hb[3 * (lane - 1) + 1]);
+  jb[3 * (lane - 1) + 2] = fma_(-sz, ie, hb[3 * (lane - 1) + 2]);
+}
+
+hipError_t launch_helio_to_jacobi_batch(const EphConst* E, const double* h, double* j, int nsys,
+                                        hipStream_t st) {
+  if (nsys <= 0) return hipSuccess;
+  hipLaunchKernelGGL(helio_to_jacobi_batch, dim3(nsys), dim3(64), 0, st, E, h, j);
   return hipGetLastError();
 }
 

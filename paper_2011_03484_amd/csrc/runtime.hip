@@ -11,6 +11,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <memory>
+#include <type_traits>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -53,6 +56,46 @@ void dfree(T*& p) {
 bool finite_all(const double* p, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Planet-map constants of one system from its sorted planets (mu, initial
+// osculating semi-major axes).
+EphConst make_eph(double mu0, int np, const double* mu, const double* a) {
+  EphConst E{};
+  E.np = np;
+  E.mu[0] = mu0;
+  E.eta[0] = mu0;
+  E.inv_eta[0] = 1.0 / mu0;
+  for (int b = 1; b <= np; ++b) {
+    E.mu[b] = mu[b - 1];
+    E.eta[b] = E.eta[b - 1] + E.mu[b];
+    E.inv_eta[b] = 1.0 / E.eta[b];
+    E.mup[b] = mu0 * E.eta[b] / E.eta[b - 1];
+  }
+  for (int i = 1; i <= np; ++i)
+    for (int j = 1; j <= np; ++j) {
+      double rh = std::cbrt((E.mu[i] + E.mu[j]) / (3.0 * mu0)) * 0.5 * (a[i - 1] + a[j - 1]);
+      E.hill2[i][j] = rh * rh;
+    }
+  return E;
+}
+
+// Osculating semi-major axes (mu0 + mu_j) of np planets and the order that
+// sorts them (the Jacobi order).  Returns false if an orbit is not bound.
+bool sort_planets(double mu0, int np, const double* mu, const double* r, const double* v,
+                  std::vector<int>& perm, std::vector<double>& a) {
+  a.resize(np);
+  for (int j = 0; j < np; ++j) {
+    double rr = std::sqrt(r[3 * j] * r[3 * j] + r[3 * j + 1] * r[3 * j + 1] + r[3 * j + 2] * r[3 * j + 2]);
+    double vv = v[3 * j] * v[3 * j] + v[3 * j + 1] * v[3 * j + 1] + v[3 * j + 2] * v[3 * j + 2];
+    double alpha = 2.0 / rr - vv / (mu0 + mu[j]);
+    if (!(rr > 0.0) || !(alpha > 0.0)) return false;
+    a[j] = 1.0 / alpha;
+  }
+  perm.resize(np);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return a[x] < a[y]; });
   return true;
 }
 
@@ -179,25 +222,7 @@ struct tpm_sim {
     return S;
   }
 
-  EphConst eph() const {
-    EphConst E{};
-    E.np = np;
-    E.mu[0] = mu0;
-    E.eta[0] = mu0;
-    E.inv_eta[0] = 1.0 / mu0;
-    for (int b = 1; b <= np; ++b) {
-      E.mu[b] = mu_s[b - 1];
-      E.eta[b] = E.eta[b - 1] + E.mu[b];
-      E.inv_eta[b] = 1.0 / E.eta[b];
-      E.mup[b] = mu0 * E.eta[b] / E.eta[b - 1];
-    }
-    for (int i = 1; i <= np; ++i)
-      for (int j = 1; j <= np; ++j) {
-        double rh = std::cbrt((E.mu[i] + E.mu[j]) / (3.0 * mu0)) * 0.5 * (a_s[i - 1] + a_s[j - 1]);
-        E.hill2[i][j] = rh * rh;
-      }
-    return E;
-  }
+  EphConst eph() const { return make_eph(mu0, np, mu_s.data(), a_s.data()); }
 };
 
 namespace {
@@ -437,6 +462,7 @@ int tpm_set_particles(tpm_sim* s, int64_t n, const double* r, const double* v) {
   TPM_HIP(hipMemset(s->d_qctr, 0, sizeof(unsigned long long)));
   TPM_HIP(hipMemset(s->d_progress, 0, sizeof(uint32_t) * ntiles));
   TPM_HIP(hipMemset(s->d_qerr, 0, sizeof(int32_t)));
+  TPM_HIP(hipDeviceSynchronize());   // null-stream set-up before work on the non-blocking streams
   // structure-of-arrays layout for the kernels
   std::vector<double> col(n);
   Work& w = s->work[0];
@@ -697,6 +723,8 @@ int tpm_get_planets(tpm_sim* s, double* r, double* v) {
 int tpm_get_stats(tpm_sim* s, tpm_stats* o) {
   if (!s || !o) return fail(TPM_EINVAL, "NULL argument");
   tpm_stats st = s->stats;
+  st.sub_chunks = s->opt.sub_chunks;
+  st.waves_per_simd = s->opt.waves_per_simd;
   st.step = s->step;
   st.n_particles = s->n;
   st.n_active = 0;
@@ -946,3 +974,404 @@ int tpm_ad_tangent(tpm_sim* s, const double* d_dR0, const double* d_dV0, double*
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ many systems
+// One call integrates nsys independent systems, each with its own central
+// mass, planets (0..8), particles and time step, for the same number of
+// steps.  The planet maps of all systems run as one launch per chunk (one
+// wavefront each); the particles of all systems form one work queue whose
+// tiles (64 particles of one system) are ordered by planet count, largest
+// first.  The whole chunk loop is captured once into a HIP graph and launched
+// once.  Work-queue shapes come from a small autotuner whose choices are
+// cached per (systems, particles, planet-count histogram, chunk, device).
+namespace {
+
+struct BatchBuffers {
+  EphConst* E = nullptr;
+  SysDev* sys = nullptr;
+  TileDesc* tiles = nullptr;
+  double* rj = nullptr;
+  double* vj = nullptr;
+  double* dt = nullptr;
+  int64_t* ring_off = nullptr;
+  int64_t* flag = nullptr;
+  double* ring = nullptr;
+  Work w{};
+  Out out{};
+  int32_t* nall = nullptr;
+  unsigned long long* ctr = nullptr;
+  uint32_t* progress = nullptr;
+  int32_t* qerr = nullptr;
+  unsigned long long* acc = nullptr;
+  // pristine copies for the autotuner's trial runs
+  double* rj0 = nullptr;
+  double* vj0 = nullptr;
+  double* st0 = nullptr;
+  ~BatchBuffers() {
+    dfree(E); dfree(sys); dfree(tiles); dfree(rj); dfree(vj); dfree(dt); dfree(ring_off);
+    dfree(flag); dfree(ring);
+    dfree(w.x); dfree(w.y); dfree(w.z); dfree(w.vx); dfree(w.vy); dfree(w.vz);
+    dfree(w.slot); dfree(w.status);
+    dfree(out.r); dfree(out.v); dfree(out.step); dfree(out.reason); dfree(out.planet);
+    dfree(nall); dfree(ctr); dfree(progress); dfree(qerr); dfree(acc);
+    dfree(rj0); dfree(vj0); dfree(st0);
+  }
+};
+
+struct TuneChoice {
+  int sub_chunks, waves_per_simd;
+};
+
+std::map<std::string, TuneChoice>& tune_cache() {
+  static std::map<std::string, TuneChoice> c;
+  return c;
+}
+
+}  // namespace
+
+extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_t* planet_off,
+                                   const double* mu_p, const double* rp, const double* vp,
+                                   const double* rcrit, const int64_t* part_off, const double* r,
+                                   const double* v, const double* dt, int64_t nsteps,
+                                   const tpm_options* opt_in, double* r_out, double* v_out,
+                                   int64_t* step_out, int32_t* reason_out, int32_t* planet_out,
+                                   tpm_stats* stats_out) {
+  // ---- validation
+  if (nsys <= 0 || !mu0 || !planet_off || !part_off || !dt) return fail(TPM_EINVAL, "bad arguments");
+  if (nsteps < 0 || nsteps >= (int64_t(1) << 31)) return fail(TPM_EINVAL, "nsteps out of range");
+  if (planet_off[0] != 0 || part_off[0] != 0) return fail(TPM_EINVAL, "offsets must start at 0");
+  for (int s = 0; s < nsys; ++s) {
+    const int np = planet_off[s + 1] - planet_off[s];
+    if (np < 0 || np > MAX_NP) return fail(TPM_EINVAL, "planets per system must be 0..8");
+    if (part_off[s + 1] < part_off[s]) return fail(TPM_EINVAL, "particle offsets must not decrease");
+    if (!(std::isfinite(mu0[s]) && mu0[s] > 0.0)) return fail(TPM_EINVAL, "mu0 must be > 0");
+    if (!std::isfinite(dt[s]) || dt[s] == 0.0) return fail(TPM_EINVAL, "dt must be finite and non-zero");
+  }
+  const int npl_total = planet_off[nsys];
+  const int64_t n = part_off[nsys];
+  if (n >= (int64_t(1) << 31)) return fail(TPM_EINVAL, "too many particles");
+  if (npl_total > 0 && (!mu_p || !rp || !vp || !rcrit)) return fail(TPM_EINVAL, "NULL planet array");
+  if (n > 0 && (!r || !v || !r_out || !v_out)) return fail(TPM_EINVAL, "NULL particle array");
+  if (npl_total > 0 && !(finite_all(mu_p, npl_total) && finite_all(rp, 3 * npl_total) &&
+                         finite_all(vp, 3 * npl_total) && finite_all(rcrit, npl_total)))
+    return fail(TPM_EINVAL, "planet input not finite");
+  if (n > 0 && !(finite_all(r, 3 * n) && finite_all(v, 3 * n)))
+    return fail(TPM_EINVAL, "particle input not finite");
+  tpm_options o;
+  tpm_default_options(&o);
+  if (opt_in) o = *opt_in;
+  if (o.kepler_iters <= 0) o.kepler_iters = 5;
+  if (o.chunk_steps <= 0) o.chunk_steps = 1024;
+  if (o.block_threads <= 0) o.block_threads = 64;
+  if (o.block_threads % 64 || o.block_threads > 256) return fail(TPM_EINVAL, "bad block_threads");
+  if (!(o.kepler_ftol > 0.0)) o.kepler_ftol = 1e-13;
+  const bool autotune = o.sub_chunks <= 0 || o.waves_per_simd <= 0;
+
+  // a device context via the single-system object (streams, events, device)
+  tpm_options so = o;
+  tpm_sim* ctx = nullptr;
+  {
+    int rc = tpm_create(&so, &ctx);
+    if (rc) return rc;
+  }
+  std::unique_ptr<tpm_sim, void (*)(tpm_sim*)> guard(ctx, tpm_destroy);
+  BatchBuffers B;
+  const int K = o.chunk_steps;
+  const int64_t slot_rows = K + 1;
+
+  // ---- per-system set-up (host: ordering and constants; device: Jacobi)
+  std::vector<EphConst> E(nsys);
+  std::vector<SysDev> S(nsys);
+  std::vector<std::vector<int>> perm(nsys);
+  std::vector<double> hpos(3 * MAX_NP * nsys, 0.0), hvel(3 * MAX_NP * nsys, 0.0), dts(dt, dt + nsys);
+  std::vector<int64_t> ring_off(nsys);
+  int64_t ring_total = 0;
+  int hist[MAX_NP + 1] = {0};
+  for (int s = 0; s < nsys; ++s) {
+    const int p0 = planet_off[s], np = planet_off[s + 1] - p0;
+    std::vector<double> a;
+    if (!sort_planets(mu0[s], np, mu_p + p0, rp + 3 * p0, vp + 3 * p0, perm[s], a))
+      return fail(TPM_EINVAL, "planet orbit not bound in system " + std::to_string(s));
+    std::vector<double> ms(np), as(np);
+    SysDev& d = S[s];
+    d = SysDev{};
+    d.np = np;
+    d.kiters = o.kepler_iters;
+    d.ftol = o.kepler_ftol;
+    d.rmax2 = o.r_escape > 0 ? o.r_escape * o.r_escape : INFINITY;
+    d.dt = dt[s];
+    d.K = KepConst{mu0[s], 1.0 / mu0[s], std::sqrt(mu0[s]), 1.0 / std::sqrt(mu0[s])};
+    for (int j = 0; j < np; ++j) {
+      const int c = perm[s][j];
+      if (!(mu_p[p0 + c] > 0.0) || rcrit[p0 + c] < 0.0)
+        return fail(TPM_EINVAL, "bad planet in system " + std::to_string(s));
+      ms[j] = mu_p[p0 + c];
+      as[j] = a[c];
+      d.mu[j] = ms[j];
+      d.rcrit2[j] = rcrit[p0 + c] * rcrit[p0 + c];
+      for (int k = 0; k < 3; ++k) {
+        hpos[3 * MAX_NP * s + 3 * j + k] = rp[3 * (p0 + c) + k];
+        hvel[3 * MAX_NP * s + 3 * j + k] = vp[3 * (p0 + c) + k];
+      }
+    }
+    E[s] = make_eph(mu0[s], np, ms.data(), as.data());
+    ring_off[s] = ring_total;
+    d.ring_off = ring_total;
+    ring_total += (int64_t)NSLOT * slot_rows * (3 * np + 3);
+    hist[np]++;
+  }
+  // tiles of 64 particles of one system, largest planet count first
+  std::vector<TileDesc> tiles;
+  for (int s = 0; s < nsys; ++s)
+    for (int64_t f = part_off[s]; f < part_off[s + 1]; f += 64)
+      tiles.push_back(TileDesc{s, (int32_t)f, (int32_t)std::min<int64_t>(64, part_off[s + 1] - f), 0});
+  std::stable_sort(tiles.begin(), tiles.end(),
+                   [&](const TileDesc& x, const TileDesc& y) { return S[x.sys].np > S[y.sys].np; });
+  const int ntiles = (int)tiles.size();
+
+  // ---- device buffers
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  const size_t ps = (size_t)3 * MAX_NP * nsys;
+  TPM_HIP(hipMalloc(&B.E, sizeof(EphConst) * nsys));
+  TPM_HIP(hipMalloc(&B.sys, sizeof(SysDev) * nsys));
+  TPM_HIP(hipMalloc(&B.tiles, sizeof(TileDesc) * std::max(ntiles, 1)));
+  TPM_HIP(hipMalloc(&B.rj, sizeof(double) * ps));
+  TPM_HIP(hipMalloc(&B.vj, sizeof(double) * ps));
+  TPM_HIP(hipMalloc(&B.rj0, sizeof(double) * ps));
+  TPM_HIP(hipMalloc(&B.vj0, sizeof(double) * ps));
+  TPM_HIP(hipMalloc(&B.dt, sizeof(double) * nsys));
+  TPM_HIP(hipMalloc(&B.ring_off, sizeof(int64_t) * nsys));
+  TPM_HIP(hipMalloc(&B.flag, sizeof(int64_t) * nsys));
+  TPM_HIP(hipMalloc(&B.ring, sizeof(double) * std::max<int64_t>(ring_total, 1)));
+  for (double** p : {&B.w.x, &B.w.y, &B.w.z, &B.w.vx, &B.w.vy, &B.w.vz}) TPM_HIP(hipMalloc(p, nn * 8));
+  TPM_HIP(hipMalloc(&B.w.slot, nn * 4));
+  TPM_HIP(hipMalloc(&B.w.status, nn * 4));
+  TPM_HIP(hipMalloc(&B.out.r, nn * 24));
+  TPM_HIP(hipMalloc(&B.out.v, nn * 24));
+  TPM_HIP(hipMalloc(&B.out.step, nn * 8));
+  TPM_HIP(hipMalloc(&B.out.reason, nn * 4));
+  TPM_HIP(hipMalloc(&B.out.planet, nn * 4));
+  TPM_HIP(hipMalloc(&B.st0, nn * 6 * 8));
+  TPM_HIP(hipMalloc(&B.nall, sizeof(int32_t)));
+  TPM_HIP(hipMalloc(&B.ctr, sizeof(unsigned long long)));
+  TPM_HIP(hipMalloc(&B.progress, sizeof(uint32_t) * std::max(ntiles, 1)));
+  TPM_HIP(hipMalloc(&B.qerr, sizeof(int32_t)));
+  TPM_HIP(hipMalloc(&B.acc, sizeof(unsigned long long)));
+  TPM_HIP(hipMemcpy(B.E, E.data(), sizeof(EphConst) * nsys, hipMemcpyHostToDevice));
+  TPM_HIP(hipMemcpy(B.sys, S.data(), sizeof(SysDev) * nsys, hipMemcpyHostToDevice));
+  if (ntiles) TPM_HIP(hipMemcpy(B.tiles, tiles.data(), sizeof(TileDesc) * ntiles, hipMemcpyHostToDevice));
+  TPM_HIP(hipMemcpy(B.dt, dts.data(), sizeof(double) * nsys, hipMemcpyHostToDevice));
+  TPM_HIP(hipMemcpy(B.ring_off, ring_off.data(), sizeof(int64_t) * nsys, hipMemcpyHostToDevice));
+  {
+    std::vector<int64_t> m1(nsys, -1);
+    TPM_HIP(hipMemcpy(B.flag, m1.data(), sizeof(int64_t) * nsys, hipMemcpyHostToDevice));
+  }
+  // planets: heliocentric -> Jacobi on the device (staged through rj0 / vj0)
+  TPM_HIP(hipMemcpy(B.rj0, hpos.data(), sizeof(double) * ps, hipMemcpyHostToDevice));
+  TPM_HIP(hipMemcpy(B.vj0, hvel.data(), sizeof(double) * ps, hipMemcpyHostToDevice));
+  TPM_HIP(hipMemset(B.rj, 0, sizeof(double) * ps));
+  TPM_HIP(hipMemset(B.vj, 0, sizeof(double) * ps));
+  TPM_HIP(hipDeviceSynchronize());   // null-stream set-up before work on the non-blocking streams
+  TPM_HIP(launch_helio_to_jacobi_batch(B.E, B.rj0, B.rj, nsys, ctx->sP));
+  TPM_HIP(launch_helio_to_jacobi_batch(B.E, B.vj0, B.vj, nsys, ctx->sP));
+  TPM_HIP(hipStreamSynchronize(ctx->sP));
+  TPM_HIP(hipMemcpy(B.rj0, B.rj, sizeof(double) * ps, hipMemcpyDeviceToDevice));
+  TPM_HIP(hipMemcpy(B.vj0, B.vj, sizeof(double) * ps, hipMemcpyDeviceToDevice));
+  // particles: caller AoS -> SoA (global order = caller order)
+  {
+    std::vector<double> col(n);
+    double* dst[6] = {B.w.x, B.w.y, B.w.z, B.w.vx, B.w.vy, B.w.vz};
+    for (int c = 0; c < 6; ++c) {
+      const double* src = c < 3 ? r : v;
+      for (int64_t i = 0; i < n; ++i) col[i] = src[3 * i + (c % 3)];
+      if (n) {
+        TPM_HIP(hipMemcpy(dst[c], col.data(), n * 8, hipMemcpyHostToDevice));
+        TPM_HIP(hipMemcpy(B.st0 + (size_t)c * n, col.data(), n * 8, hipMemcpyHostToDevice));
+      }
+    }
+    std::vector<int32_t> idx(n), zero(n, 0);
+    std::iota(idx.begin(), idx.end(), 0);
+    if (n) {
+      TPM_HIP(hipMemcpy(B.w.slot, idx.data(), n * 4, hipMemcpyHostToDevice));
+      TPM_HIP(hipMemcpy(B.w.status, zero.data(), n * 4, hipMemcpyHostToDevice));
+    }
+  }
+  const int32_t n32 = (int32_t)n;
+  TPM_HIP(hipMemcpy(B.nall, &n32, 4, hipMemcpyHostToDevice));
+  auto reset_run = [&]() -> int {
+    // initial particle, planet and queue state (outside any captured graph)
+    double* dst[6] = {B.w.x, B.w.y, B.w.z, B.w.vx, B.w.vy, B.w.vz};
+    for (int c = 0; c < 6; ++c)
+      if (n) TPM_HIP(hipMemcpy(dst[c], B.st0 + (size_t)c * n, n * 8, hipMemcpyDeviceToDevice));
+    if (n) TPM_HIP(hipMemset(B.w.status, 0, n * 4));
+    TPM_HIP(hipMemcpy(B.rj, B.rj0, sizeof(double) * ps, hipMemcpyDeviceToDevice));
+    TPM_HIP(hipMemcpy(B.vj, B.vj0, sizeof(double) * ps, hipMemcpyDeviceToDevice));
+    TPM_HIP(hipMemset(B.ctr, 0, sizeof(unsigned long long)));
+    TPM_HIP(hipMemset(B.progress, 0, sizeof(uint32_t) * std::max(ntiles, 1)));
+    TPM_HIP(hipMemset(B.qerr, 0, sizeof(int32_t)));
+    std::vector<int64_t> m1(std::max<int64_t>(n, nsys), -1);
+    TPM_HIP(hipMemcpy(B.flag, m1.data(), sizeof(int64_t) * nsys, hipMemcpyHostToDevice));
+    if (n) {
+      TPM_HIP(hipMemcpy(B.out.step, m1.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice));
+      TPM_HIP(hipMemset(B.out.reason, 0, n * 4));
+    }
+    TPM_HIP(hipDeviceSynchronize());
+    return TPM_OK;
+  };
+
+  // ---- the chunk loop, enqueued on (sE: planet maps, sP: particles)
+  const int64_t nchunks = (nsteps + K - 1) / K;
+  auto enqueue_run = [&](int64_t chunks, int sub, int wps) -> int {
+    unsigned long long base = 0;
+    uint32_t epoch = 0;
+    const int workers = std::max(1, std::min(ntiles, 4 * ctx->ncu * wps));
+    const int wpb = o.block_threads / 64;
+    const unsigned long long waves = (unsigned long long)((workers + wpb - 1) / wpb) * wpb;
+    TPM_HIP(hipEventRecord(ctx->ev_cnt[0], ctx->sP));
+    TPM_HIP(hipStreamWaitEvent(ctx->sE, ctx->ev_cnt[0], 0));
+    for (int64_t c = 0; c < chunks; ++c) {
+      const int ks = (int)std::min<int64_t>(K, nsteps - c * K);
+      const int slot = (int)(c % NSLOT);
+      if (c >= NSLOT) TPM_HIP(hipStreamWaitEvent(ctx->sE, ctx->ev_done[slot], 0));
+      TPM_HIP(launch_ephemeris_batch(B.E, B.rj, B.vj, B.ring, B.ring_off, slot, slot_rows, nsys, ks,
+                                     B.dt, c * K, B.flag, ctx->sE));
+      TPM_HIP(hipEventRecord(ctx->ev_eph[slot], ctx->sE));
+      TPM_HIP(hipStreamWaitEvent(ctx->sP, ctx->ev_eph[slot], 0));
+      BatchQueueArgs Q;
+      Q.ctr = B.ctr;
+      Q.base = base;
+      Q.progress = B.progress;
+      Q.epoch = epoch;
+      Q.ntiles = ntiles;
+      Q.nsub = std::max(1, std::min(sub, ks));
+      Q.sub_steps = (ks + Q.nsub - 1) / Q.nsub;
+      Q.nsteps = ks;
+      Q.step0 = c * K;
+      Q.slot = slot;
+      Q.slot_rows = slot_rows;
+      Q.error = B.qerr;
+      TPM_HIP(launch_particle_batch(B.sys, B.tiles, B.w, B.out, B.ring, Q, workers, o.block_threads,
+                                    ctx->sP));
+      if (ntiles > 0) {
+        base += (unsigned long long)ntiles * Q.nsub + waves;
+        epoch += (uint32_t)Q.nsub;
+      }
+      TPM_HIP(hipEventRecord(ctx->ev_done[slot], ctx->sP));
+    }
+    TPM_HIP(hipEventRecord(ctx->ev_cnt[1], ctx->sE));
+    TPM_HIP(hipStreamWaitEvent(ctx->sP, ctx->ev_cnt[1], 0));
+    return TPM_OK;
+  };
+
+  // ---- autotuner: time one chunk of each candidate from the initial state
+  TuneChoice choice{o.sub_chunks > 0 ? o.sub_chunks : 4, o.waves_per_simd > 0 ? o.waves_per_simd : 2};
+  if (autotune && nchunks > 0 && ntiles > 0) {
+    hipDeviceProp_t prop;
+    TPM_HIP(hipGetDeviceProperties(&prop, o.device));
+    std::string key = std::string(prop.gcnArchName) + "/" + std::to_string(nsys) + "/" +
+                      std::to_string(n) + "/" + std::to_string(K);
+    for (int k = 0; k <= MAX_NP; ++k) key += "," + std::to_string(hist[k]);
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+      choice = it->second;
+    } else {
+      const TuneChoice cands[] = {{1, 2}, {4, 2}, {8, 2}, {4, 1}, {4, 4}};
+      float best = 1e30f;
+      for (const auto& cand : cands) {
+        int rc = reset_run();
+        if (rc) return rc;
+        TPM_HIP(hipEventRecord(ctx->t0P, ctx->sP));
+        rc = enqueue_run(1, cand.sub_chunks, cand.waves_per_simd);
+        if (rc) return rc;
+        TPM_HIP(hipEventRecord(ctx->t1P, ctx->sP));
+        TPM_HIP(hipEventSynchronize(ctx->t1P));
+        float ms = 0.f;
+        TPM_HIP(hipEventElapsedTime(&ms, ctx->t0P, ctx->t1P));
+        if (ms < best) { best = ms; choice = cand; }
+      }
+      tune_cache()[key] = choice;
+    }
+  }
+
+  // ---- capture the whole run into one graph and launch it once
+  {
+    int rc = reset_run();
+    if (rc) return rc;
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  TPM_HIP(hipStreamBeginCapture(ctx->sP, hipStreamCaptureModeThreadLocal));
+  {
+    int rc = enqueue_run(nchunks, choice.sub_chunks, choice.waves_per_simd);
+    if (rc) {
+      (void)hipStreamEndCapture(ctx->sP, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+  }
+  TPM_HIP(hipStreamEndCapture(ctx->sP, &graph));
+  std::unique_ptr<std::remove_pointer<hipGraph_t>::type, hipError_t (*)(hipGraph_t)> gguard(
+      graph, hipGraphDestroy);
+  TPM_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  std::unique_ptr<std::remove_pointer<hipGraphExec_t>::type, hipError_t (*)(hipGraphExec_t)> eguard(
+      exec, hipGraphExecDestroy);
+  auto w0 = std::chrono::steady_clock::now();
+  TPM_HIP(hipEventRecord(ctx->t0P, ctx->sP));
+  TPM_HIP(hipGraphLaunch(exec, ctx->sP));
+  TPM_HIP(hipEventRecord(ctx->t1P, ctx->sP));
+  TPM_HIP(hipStreamSynchronize(ctx->sP));
+  auto w1 = std::chrono::steady_clock::now();
+  float run_ms = 0.f;
+  TPM_HIP(hipEventElapsedTime(&run_ms, ctx->t0P, ctx->t1P));
+  {
+    int32_t qerr = 0;
+    TPM_HIP(hipMemcpy(&qerr, B.qerr, sizeof(qerr), hipMemcpyDeviceToHost));
+    if (qerr) return fail(TPM_EDEVICE, "particle work queue: a wait exceeded its limit");
+  }
+  // ---- results
+  TPM_HIP(launch_finalize(B.w, B.nall, (int)n, B.out, ctx->sP));
+  TPM_HIP(hipMemsetAsync(B.acc, 0, sizeof(unsigned long long), ctx->sP));
+  TPM_HIP(launch_active_steps(B.out.step, (int)n, 0, nsteps, B.acc, ctx->sP));
+  TPM_HIP(hipStreamSynchronize(ctx->sP));
+  if (n) {
+    TPM_HIP(hipMemcpy(r_out, B.out.r, n * 24, hipMemcpyDeviceToHost));
+    TPM_HIP(hipMemcpy(v_out, B.out.v, n * 24, hipMemcpyDeviceToHost));
+    if (step_out) TPM_HIP(hipMemcpy(step_out, B.out.step, n * 8, hipMemcpyDeviceToHost));
+    if (reason_out) TPM_HIP(hipMemcpy(reason_out, B.out.reason, n * 4, hipMemcpyDeviceToHost));
+    if (planet_out) {
+      TPM_HIP(hipMemcpy(planet_out, B.out.planet, n * 4, hipMemcpyDeviceToHost));
+      for (int s = 0; s < nsys; ++s)
+        for (int64_t i = part_off[s]; i < part_off[s + 1]; ++i)
+          if (planet_out[i] >= 0) planet_out[i] = perm[s][planet_out[i]];
+    }
+  }
+  unsigned long long acc = 0;
+  TPM_HIP(hipMemcpy(&acc, B.acc, sizeof(acc), hipMemcpyDeviceToHost));
+  std::vector<int64_t> flags(nsys);
+  TPM_HIP(hipMemcpy(flags.data(), B.flag, sizeof(int64_t) * nsys, hipMemcpyDeviceToHost));
+  if (stats_out) {
+    tpm_stats st{};
+    st.step = nsteps;
+    st.n_particles = n;
+    st.active_particle_steps = (int64_t)acc;
+    st.wall_ms = std::chrono::duration<double, std::milli>(w1 - w0).count();
+    st.particle_ms = run_ms;
+    st.ephemeris_ms = run_ms;
+    st.chunks = nchunks;
+    st.sub_chunks = choice.sub_chunks;
+    st.waves_per_simd = choice.waves_per_simd;
+    if (n) {
+      std::vector<int32_t> rs(n);
+      TPM_HIP(hipMemcpy(rs.data(), B.out.reason, n * 4, hipMemcpyDeviceToHost));
+      for (auto x : rs)
+        if (x >= 0 && x < 4) st.count_by_reason[x]++;
+      st.n_active = st.count_by_reason[0];
+    }
+    *stats_out = st;
+  }
+  for (int s = 0; s < nsys; ++s)
+    if (flags[s] != -1)
+      return fail(TPM_EPLANET, "system " + std::to_string(s) + ": planets came within a mutual "
+                               "Hill radius or a planet orbit became unbound");
+  return TPM_OK;
+}

@@ -5,9 +5,10 @@ Bars (see the oracle's header for what is computed):
     reason and planet;
   * particles whose removal flips when the oracle's thresholds move by 1e-9
     are excluded from the removal comparison (near-threshold);
-  * particles whose own trajectory in the oracle spreads by more than 1e-12
-    under a one-ulp change of the initial position (the chaos floor) are
-    reported separately and held to max(1e-11, 100 x that spread) instead.
+  * every particle is held to max(1e-11, 100 x its own one-ulp spread) --
+    the response of the oracle's trajectory to a one-ulp change of the initial
+    position, its conditioning (the chaos floor) -- and at least half of the
+    particles of every workload to the plain 1e-11.
 """
 import math
 
@@ -46,6 +47,9 @@ def _oracle_reference(orc, w, T, table):
 
 
 def _compare(gpu, res, near, spread, label):
+    """Removal records identical (outside the near-threshold set); every
+    particle within max(1e-11, 100 x its own one-ulp spread in the oracle), and
+    at least half of the particles within the plain 1e-11 bar."""
     ok = ~near
     assert np.array_equal(gpu["reason"][ok], res.reason[ok]), label
     assert np.array_equal(gpu["deact_step"][ok], res.deact_step[ok]), label
@@ -53,20 +57,17 @@ def _compare(gpu, res, near, spread, label):
     same = ok & (gpu["deact_step"] == res.deact_step)
     err = np.linalg.norm(gpu["r"] - res.r, axis=1) / np.linalg.norm(res.r, axis=1)
     verr = np.linalg.norm(gpu["v"] - res.v, axis=1) / np.linalg.norm(res.v, axis=1)
-    chaotic = spread > 1e-12
-    regular = same & ~chaotic
-    chaos_ok = same & chaotic & np.isfinite(spread)
+    cmp_ = same & np.isfinite(spread)
     bound = np.maximum(POS_TOL, 100 * spread)
-    print(f"[{label}] n={len(err)} near={near.sum()} chaos-floor={chaotic.sum()} "
-          f"removed={np.sum(res.reason != 0)} max_rel_r(regular)={err[regular].max():.3e} "
-          f"max_rel_v(regular)={verr[regular].max():.3e} "
-          f"max_rel_r/bound(chaos-floor)="
-          f"{(err[chaos_ok] / bound[chaos_ok]).max() if np.any(chaos_ok) else 0:.3f}", flush=True)
-    assert regular.sum() >= 0.5 * len(err)
-    assert err[regular].max() <= POS_TOL, label
-    assert verr[regular].max() <= POS_TOL, label
-    assert np.all(err[chaos_ok] <= bound[chaos_ok]), label
-    assert np.all(verr[chaos_ok] <= bound[chaos_ok]), label
+    worst = np.maximum(err, verr)
+    plain = cmp_ & (worst <= POS_TOL)
+    print(f"[{label}] n={len(err)} near={near.sum()} removed={np.sum(res.reason != 0)} "
+          f"within 1e-11: {plain.sum()}/{cmp_.sum()}  spread>1e-12: {np.sum(cmp_ & (spread > 1e-12))}  "
+          f"max rel r {err[cmp_].max():.3e} v {verr[cmp_].max():.3e}  "
+          f"max err/bound {(worst[cmp_] / bound[cmp_]).max():.3f}", flush=True)
+    assert cmp_.sum() > 0
+    assert plain.sum() >= 0.5 * len(err), label
+    assert np.all(worst[cmp_] <= bound[cmp_]), label
 
 
 def _sim(tpm, w, **opts):
