@@ -83,7 +83,7 @@ def batched_run(P, W, nsteps: int):
     """512 independent systems (Np 1..8, ~0.86M particles) in one graph launch."""
     systems = W.make_batched(nsteps=nsteps)
     t0 = time.perf_counter()
-    res, st = P.batch_integrate(systems, nsteps=nsteps)
+    res, st = P.batch_integrate(systems, nsteps=nsteps, strict=False)
     t1 = time.perf_counter()
     n = sum(w.n for w in systems)
     return {"workload": f"batched_512: 512 systems, Np U{{1..8}}, {n} particles, dt = P_inner/30, "
@@ -92,6 +92,7 @@ def batched_run(P, W, nsteps: int):
             "unit": "particle-steps/s", "graph_ms": st["particle_ms"],
             "call_s_incl_setup_and_tuning": t1 - t0,
             "active_particle_steps": st["active_particle_steps"],
+            "systems_with_planet_close_approach": int((st["planet_flag"] != -1).sum()),
             "queue_shape": {"sub_chunks": st["sub_chunks"], "waves_per_simd": st["waves_per_simd"]}}
 
 

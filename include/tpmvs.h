@@ -188,14 +188,17 @@ int tpm_ad_tangent(tpm_sim* sim, const double* d_dR0, const double* d_dV0, doubl
  * particles of all systems as one work queue (tiles of 64 particles of one
  * system, most planets first); the whole run is captured into one HIP graph
  * and launched once.  stats (may be NULL) receives the graph's run time and
- * the active particle-steps.  Returns TPM_EPLANET (results written) if any
- * system's planets came within a mutual Hill radius. */
+ * the active particle-steps.  planet_flag (may be NULL) receives per system
+ * -1, the first step at which two planets were within a mutual Hill radius,
+ * or -2 if a planet orbit became unbound; any flag makes the call return
+ * TPM_EPLANET (all results are still written). */
 int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_t* planet_off,
                         const double* mu_p, const double* rp, const double* vp,
                         const double* rcrit, const int64_t* part_off, const double* r,
                         const double* v, const double* dt, int64_t nsteps,
                         const tpm_options* opt, double* r_out, double* v_out, int64_t* step_out,
-                        int32_t* reason_out, int32_t* planet_out, tpm_stats* stats);
+                        int32_t* reason_out, int32_t* planet_out, tpm_stats* stats,
+                        int64_t* planet_flag);
 
 /* ---- unit entry points of the device math (host arrays) -------------------- */
 /* sin and cos of x[n] by the library's branch-free FP64 routine. */

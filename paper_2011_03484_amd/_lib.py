@@ -78,7 +78,7 @@ SIGNATURES = {
     "tpm_ad_backward": (C.c_int, [_P] * 6),
     "tpm_ad_tangent": (C.c_int, [_P] * 6),
     "tpm_batch_integrate": (C.c_int, [C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_int64,
-                                      _P, _P, _P, _P, _P, _P, _P]),
+                                      _P, _P, _P, _P, _P, _P, _P, _P]),
 }
 
 _lib = None
@@ -235,10 +235,13 @@ def debug_drift(mu, r, v, dt, kepler_iters=5, kepler_ftol=0.0):
 
 
 def batch_integrate(systems, nsteps=None, r_escape=None, kepler_iters=5, chunk_steps=0,
-                    sub_chunks=0, waves_per_simd=0, block_threads=0):
+                    sub_chunks=0, waves_per_simd=0, block_threads=0, strict=True):
     """Integrate many independent systems (workload objects) in one launch.
 
-    Returns (per-system list of result dicts, stats dict)."""
+    Returns (per-system list of result dicts, stats dict).  The stats carry
+    ``planet_flag`` per system (-1, or the first step of a planet-planet close
+    approach, or -2 for an unbound planet); with ``strict`` any flag raises
+    PlanetEncounterError (the results are complete either way)."""
     nsys = len(systems)
     mu0 = np.array([w.mu0 for w in systems], dtype=np.float64)
     poff = np.zeros(nsys + 1, np.int32)
@@ -264,14 +267,18 @@ def batch_integrate(systems, nsteps=None, r_escape=None, kepler_iters=5, chunk_s
     rs = np.zeros(n, np.int32)
     pl = np.zeros(n, np.int32)
     stats = Stats()
+    flags = np.zeros(nsys, np.int64)
     rc_ = load().tpm_batch_integrate(nsys, _p(mu0), _p(poff), _p(mu_p), _p(rp), _p(vp), _p(rc),
                                      _p(qoff), _p(r), _p(v), _p(dt), T, C.byref(o), _p(ro), _p(vo),
-                                     _p(st), _p(rs), _p(pl), C.byref(stats))
+                                     _p(st), _p(rs), _p(pl), C.byref(stats), _p(flags))
     out = [{"r": ro[qoff[i]:qoff[i + 1]], "v": vo[qoff[i]:qoff[i + 1]],
             "deact_step": st[qoff[i]:qoff[i + 1]], "reason": rs[qoff[i]:qoff[i + 1]],
             "planet": pl[qoff[i]:qoff[i + 1]]} for i in range(nsys)]
-    _check(rc_)
-    return out, stats.as_dict()
+    sd = stats.as_dict()
+    sd["planet_flag"] = flags
+    if strict or rc_ != TPM_EPLANET:
+        _check(rc_)
+    return out, sd
 
 
 def run_workload(w, nsteps=None, **opts):

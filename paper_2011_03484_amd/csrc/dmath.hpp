@@ -3,11 +3,13 @@
 //
 // * rcp / rsqrt start from the hardware approximations (v_rcp_f64, v_rsq_f64,
 //   about 23 good bits) and refine them by Newton-Raphson with fused
-//   multiply-adds; each refinement doubles the number of good bits.
+//   multiply-adds; each refinement doubles the number of good bits (two give
+//   full precision, one gives about 46 bits).
 // * sincos reduces the argument by pi/2 with the two-constant Cody-Waite scheme
 //   done in fused multiply-adds (exact first product for the quadrant counts
 //   used here, |q| <= 2^20), then evaluates the Taylor series of sin and cos on
-//   [-pi/4, pi/4] (truncation below 1e-19) and picks the quadrant with selects.
+//   [-pi/4, pi/4] (truncation below 1e-19) in Estrin's form and picks the
+//   quadrant with selects.
 //   The constants are pi/2 split into its nearest double and the nearest double
 //   to the remainder (from 50-digit pi; gen_constants.py reproduces them) and
 //   the reciprocals 1/n! of the Taylor series.
@@ -56,6 +58,17 @@ TPM_DEV double rsqrt(double x) {
   return h + h;
 }
 
+// 1/sqrt(x) good to about 2^-46 relative (one refinement): used where the
+// result only scales a small perturbation.
+TPM_DEV double rsqrt1(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = 0.5 * y;
+  double r = fma_(-g, h, 0.5);
+  h = fma_(h, r, h);
+  return h + h;
+}
+
 // sqrt(x) and 1/sqrt(x) together for x > 0.
 TPM_DEV void sqrt_rsqrt(double x, double& s, double& rs) {
   double y = __builtin_amdgcn_rsq(x);
@@ -96,29 +109,27 @@ constexpr double C14 = -1.0 / 87178291200.0;
 constexpr double C16 = 1.0 / 20922789888000.0;
 constexpr double C18 = -1.0 / 6402373705728000.0;
 
-// sin and cos of r for |r| <= pi/4 (plus a little slack).
+// sin and cos of r for |r| <= pi/4 (plus a little slack).  With z = r^2 the
+// two series in z are evaluated in Estrin's pairing (shared z^2, z^4), which
+// halves the dependent-FMA depth of Horner's rule at the same count.
 TPM_DEV void sincos_poly(double r, double& s, double& c) {
-  double r2 = r * r;
-  double ps = fma_(r2, S17, S15);
-  ps = fma_(r2, ps, S13);
-  ps = fma_(r2, ps, S11);
-  ps = fma_(r2, ps, S9);
-  ps = fma_(r2, ps, S7);
-  ps = fma_(r2, ps, S5);
-  ps = fma_(r2, ps, S3);
-  s = fma_(r * r2, ps, r);
-  double pc = fma_(r2, C18, C16);
-  pc = fma_(r2, pc, C14);
-  pc = fma_(r2, pc, C12);
-  pc = fma_(r2, pc, C10);
-  pc = fma_(r2, pc, C8);
-  pc = fma_(r2, pc, C6);
-  pc = fma_(r2, pc, C4);
-  // cos = 1 - r2/2 + r2^2 pc, with the rounding of 1 - r2/2 carried along
-  double hr = 0.5 * r2;
-  double w = 1.0 - hr;
-  double tail = (1.0 - w) - hr;
-  c = w + fma_(r2 * r2, pc, tail);
+  const double z = r * r;
+  const double z2 = z * z;
+  const double z4 = z2 * z2;
+  // sin r = r + r z (S3 + S5 z + ... + S17 z^7)
+  double s01 = fma_(S5, z, S3), s23 = fma_(S9, z, S7);
+  double s45 = fma_(S13, z, S11), s67 = fma_(S17, z, S15);
+  double ps = fma_(z4, fma_(z2, s67, s45), fma_(z2, s23, s01));
+  s = fma_(r * z, ps, r);
+  // cos r = 1 - z/2 + z^2 (C4 + C6 z + ... + C18 z^7), the rounding of
+  // 1 - z/2 carried along
+  double c01 = fma_(C6, z, C4), c23 = fma_(C10, z, C8);
+  double c45 = fma_(C14, z, C12), c67 = fma_(C18, z, C16);
+  double pc = fma_(z4, fma_(z2, c67, c45), fma_(z2, c23, c01));
+  double hz = 0.5 * z;
+  double w = 1.0 - hz;
+  double tail = (1.0 - w) - hz;
+  c = w + fma_(z2, pc, tail);
 }
 
 // sin(x), cos(x) for |x| up to about 2^20, no branches.

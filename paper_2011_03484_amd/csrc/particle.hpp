@@ -31,7 +31,8 @@ TPM_DEV int accel(const double* __restrict__ row, const PlanetConst<NP>& P,
     double dz = z - row[3 * j + 2];
     double d2 = fma_(dx, dx, fma_(dy, dy, dz * dz));
     hit = (hit < 0 && d2 < P.rcrit2[j]) ? j : hit;
-    double inv = rsqrt(d2);
+    // the kick is a perturbation (|a| << mu0/r^2): 2^-46 relative is ample
+    double inv = rsqrt1(d2);
     double k = P.mu[j] * (inv * inv) * inv;
     ax = fma_(-k, dx, ax);
     ay = fma_(-k, dy, ay);

@@ -1035,7 +1035,7 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
                                    const double* v, const double* dt, int64_t nsteps,
                                    const tpm_options* opt_in, double* r_out, double* v_out,
                                    int64_t* step_out, int32_t* reason_out, int32_t* planet_out,
-                                   tpm_stats* stats_out) {
+                                   tpm_stats* stats_out, int64_t* planet_flag) {
   // ---- validation
   if (nsys <= 0 || !mu0 || !planet_off || !part_off || !dt) return fail(TPM_EINVAL, "bad arguments");
   if (nsteps < 0 || nsteps >= (int64_t(1) << 31)) return fail(TPM_EINVAL, "nsteps out of range");
@@ -1369,9 +1369,16 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
     }
     *stats_out = st;
   }
+  if (planet_flag) std::copy(flags.begin(), flags.end(), planet_flag);
+  int nflag = 0, first = -1;
   for (int s = 0; s < nsys; ++s)
-    if (flags[s] != -1)
-      return fail(TPM_EPLANET, "system " + std::to_string(s) + ": planets came within a mutual "
-                               "Hill radius or a planet orbit became unbound");
+    if (flags[s] != -1) {
+      if (first < 0) first = s;
+      ++nflag;
+    }
+  if (nflag)
+    return fail(TPM_EPLANET, std::to_string(nflag) + " system(s), first " + std::to_string(first) +
+                                 ": planets came within a mutual Hill radius or a planet orbit "
+                                 "became unbound");
   return TPM_OK;
 }
