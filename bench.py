@@ -25,8 +25,35 @@ sys.path.insert(0, ROOT)
 # four planets and five Newton iterations (FMA = 2, ADD/MUL/transcendental
 # = 1), counted from the kernel's loop body (see the design notes' roofline
 # section, where the counter cross-check is recorded).
-FLOPS_PER_PARTICLE_STEP = {4: 647}
+FLOPS_PER_PARTICLE_STEP = {4: 629}
 FP64_PEAK_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "particle_queue_giants_100k_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    """Fingerprint of the HIP sources (traffic counters apply to one version)."""
+    import hashlib
+    h = hashlib.sha1()
+    csrc = os.path.join(ROOT, "paper_2011_03484_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(particle_steps_per_launch: float):
+    """HBM bytes per particle launch: the calibrated FETCH_SIZE + WRITE_SIZE
+    bytes per active particle-step of the committed counter runs, times this
+    run's particle-steps per launch; None unless the counters were taken on the
+    current kernel sources."""
+    try:
+        import json as _j
+        d = _j.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d["bytes_per_particle_step"] * particle_steps_per_launch
 
 
 def cpu_baseline(w, n_sample: int, steps_sample: int):
@@ -177,7 +204,7 @@ def main():
                    "kepler_iters": w.kepler_iters},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS if achieved else None,
-                     "traffic": None},
+                     "traffic": measured_traffic(aps / max(launches, 1))},
         "kernel": {"name": "particle_queue<4,5>", "launches": launches,
                    "avg_launch_ms": kern_ms / max(launches, 1),
                    "flops_per_particle_step": fpps,
@@ -189,12 +216,17 @@ def main():
     for s in sims:
         s.close()
     if args.copy_calibration_mb > 0:
+        # a plain device copy of known size, its source evicted from the
+        # last-level cache first by writing a larger buffer
         nbytes = args.copy_calibration_mb << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
+        flush = torch.empty(4 * nbytes // 8, dtype=torch.float64, device="cuda")
+        flush.fill_(2.0)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
+        del flush
         line["copy_calibration_bytes"] = nbytes
     if not args.no_adjoint:
         line["adjoint"] = adjoint_ratio(P, W, torch, args.adjoint_steps, 16_384, 1000)

@@ -101,7 +101,9 @@ int tpm_set_central(tpm_sim* sim, double mu0);
  * the encounter radius r_crit[np] >= 0 of each (a fixed distance or a Hill
  * multiple, sec. 2.2; see tpm_hill_radius).  Planets may be given in any order;
  * they are integrated sorted by osculating semi-major axis (the Jacobi order of
- * sec. 2.2) but every output uses the caller's order.  Resets the step count. */
+ * sec. 2.2) but every output uses the caller's order.  Resets the step count.
+ * TPM_EINVAL if a planet's osculating orbit about mu0 + mu_j is not bound
+ * (its semi-major axis fixes the order and the mutual Hill limits). */
 int tpm_set_planets(tpm_sim* sim, int32_t np, const double* mu, const double* r,
                     const double* v, const double* r_crit);
 
@@ -189,9 +191,12 @@ int tpm_ad_tangent(tpm_sim* sim, const double* d_dR0, const double* d_dV0, doubl
  * system, most planets first); the whole run is captured into one HIP graph
  * and launched once.  stats (may be NULL) receives the graph's run time and
  * the active particle-steps.  planet_flag (may be NULL) receives per system
- * -1, the first step at which two planets were within a mutual Hill radius,
- * or -2 if a planet orbit became unbound; any flag makes the call return
- * TPM_EPLANET (all results are still written). */
+ * the first of these events: -1 none, t >= 0 two planets within a mutual
+ * Hill radius at step t, -2 a planet orbit found unbound in a drift (before
+ * any close pair; it wins a tie with a pair seen at the end of the same step).
+ * Any flag makes the call return TPM_EPLANET; the run goes on and all results
+ * are still written.  A system whose planets are not all bound at the start is
+ * refused with TPM_EINVAL, as in tpm_set_planets. */
 int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_t* planet_off,
                         const double* mu_p, const double* rp, const double* vp,
                         const double* rcrit, const int64_t* part_off, const double* r,

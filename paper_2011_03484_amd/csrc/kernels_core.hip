@@ -471,13 +471,16 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
     rows[3 * NP + 0] = -ax; rows[3 * NP + 1] = -ay; rows[3 * NP + 2] = -az;
   }
   const double h = 0.5 * dt;
-  int64_t first_bad = -1;      // per lane: first step with a close pair
-  if (NP > 1 && hill_violation<NP>(L, hill2row, hx, hy, hz)) first_bad = step0;
-  bool unbound = false;
+  // Per lane, the first event as a key ordered in time: a close pair seen at
+  // step t has key 2t+1; an orbit found unbound while drifting from t-1 to t
+  // has key 2t, so it wins a tie with a close pair at t (it is found first).
+  int64_t first_ev = INT64_MAX;
+  if (NP > 1 && hill_violation<NP>(L, hill2row, hx, hy, hz)) first_ev = 2 * step0 + 1;
   for (int s = 0; s < nsteps; ++s) {
     wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
     bool bound = drift_converged(L.K, dt, L.body, jx, jy, jz, wx, wy, wz);
-    unbound = unbound || (L.body && !bound);
+    const int64_t t1 = step0 + s + 1;
+    first_ev = (first_ev == INT64_MAX && L.body && !bound) ? 2 * t1 : first_ev;
     helio_all<NP>(E, jx, jy, jz, hx, hy, hz);
     eph_accel<NP>(E, L, jx, jy, jz, hx, hy, hz, ax, ay, az);
     wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
@@ -498,25 +501,21 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
     }
     if (NP > 1) {
       bool bad = hill_violation<NP>(L, hill2row, hx, hy, hz);
-      first_bad = (first_bad < 0 && bad) ? step0 + s + 1 : first_bad;
+      first_ev = (first_ev == INT64_MAX && bad) ? 2 * t1 + 1 : first_ev;
     }
   }
   if (L.body) {
     rj[3 * (L.lane - 1) + 0] = jx; rj[3 * (L.lane - 1) + 1] = jy; rj[3 * (L.lane - 1) + 2] = jz;
     vj[3 * (L.lane - 1) + 0] = wx; vj[3 * (L.lane - 1) + 1] = wy; vj[3 * (L.lane - 1) + 2] = wz;
   }
-  // reduce the flags over the wavefront: unbound -> -2, else the earliest step
-  bool any_unbound = __any(unbound);
-  int64_t fb = first_bad < 0 ? INT64_MAX : first_bad;
+  // earliest event over the wavefront: unbound -> -2, a close pair -> its step
+  int64_t ev = first_ev;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
-    int64_t o = __shfl_xor(fb, off, 64);
-    fb = o < fb ? o : fb;
+    int64_t o = __shfl_xor(ev, off, 64);
+    ev = o < ev ? o : ev;
   }
-  if (L.lane == 0 && *flag == -1) {
-    if (any_unbound) *flag = -2;
-    else if (fb != INT64_MAX) *flag = fb;
-  }
+  if (L.lane == 0 && *flag == -1 && ev != INT64_MAX) *flag = (ev & 1) ? (ev >> 1) : -2;
 }
 
 template <int NP>

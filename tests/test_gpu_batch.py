@@ -91,3 +91,58 @@ def test_full_batched_workload_sampled(P, orc):
         eph = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, T, w.dt)
         ref, near, spread = _oracle_reference(orc, w, T, eph.table)
         _compare(res[idx], ref, near, spread, f"full/{w.name}/np{w.np_}")
+
+
+def test_batched_edge_systems(P, orc):
+    """A system with no planets, one with no particles, and one whose planets
+    start inside a mutual Hill radius, alongside ordinary systems: only the
+    close pair's system is flagged (at step 0, as in the oracle), every other
+    system equals its own single-system run bit for bit, and the no-planet
+    system matches the oracle."""
+    import math
+    from test_gpu_parity import _compare, _oracle_reference
+    T = 500
+    base = _systems(nsys=4, nmax=200, seed=9)
+    w0 = base[1]
+    noplanet = W.Workload("noplanet", w0.mu0, np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)),
+                          np.zeros(0), w0.rmax, w0.r.copy(), w0.v.copy(), w0.dt, T)
+    w1 = base[2]
+    empty = W.Workload("empty", w1.mu0, w1.mu.copy(), w1.rp.copy(), w1.vp.copy(), w1.rcrit.copy(),
+                       w1.rmax, np.zeros((0, 3)), np.zeros((0, 3)), w1.dt, T)
+    mu0 = W.MU_SUN
+    mu = np.array([1e-3, 1e-3]) * mu0
+    rp, vp = W.elements_to_cartesian(mu0 + mu, np.array([5.0, 5.05]), np.zeros(2), np.zeros(2),
+                                     np.zeros(2), np.zeros(2), np.array([0.0, 0.01]))
+    rr = np.array([[20.0, 0, 0], [0, 25.0, 0]])
+    vv = np.array([[0, math.sqrt(mu0 / 20.0), 0], [-math.sqrt(mu0 / 25.0), 0, 0]])
+    pair = W.Workload("pair", mu0, mu, rp, vp, np.zeros(2), w0.rmax, rr, vv, 0.1, T)
+    assert orc.ephemeris(mu0, mu, rp, vp, 10, 0.1).flag == 0
+    # a planet set on a hyperbolic orbit (v^2 > 2 mu / r) is refused at set-up:
+    # the Jacobi order needs every planet's semi-major axis
+    hyp = W.Workload("hyperbolic", mu0, mu[:1].copy(), np.array([[5.0, 0, 0]]),
+                     np.array([[0, 1.5 * math.sqrt(2 * (mu0 + mu[0]) / 5.0), 0]]), np.zeros(1),
+                     w0.rmax, rr.copy(), vv.copy(), 0.1, T)
+    with pytest.raises(P.TpmError, match="not bound in system 1"):
+        P.batch_integrate([base[0], hyp], nsteps=10, strict=False)
+    # two planets meeting at the line of nodes at step 412
+    from test_oracle_pins import late_pair
+    lm0, lmu, lrp, lvp, ldt, _, lfirst, _, _ = late_pair()
+    late = W.Workload("late_pair", lm0, lmu, lrp, lvp, np.zeros(2), w0.rmax, rr.copy(), vv.copy(),
+                      ldt, T)
+    systems = [base[0], noplanet, base[1], empty, pair, base[2], base[3], late]
+    res, stats = P.batch_integrate(systems, nsteps=T, strict=False)
+    flags = stats["planet_flag"]
+    # the pair is flagged at step 0 although its planets end up unbound later
+    assert flags[4] == orc.ephemeris(mu0, mu, rp, vp, T, 0.1).flag == 0, flags
+    assert flags[7] == orc.ephemeris(lm0, lmu, lrp, lvp, T, ldt).flag == lfirst, flags
+    assert np.all(flags[[0, 1, 2, 3, 5, 6]] == -1), flags
+    assert res[3]["r"].shape == (0, 3)
+    for i in (0, 1, 2, 5, 6):
+        ref = _single(P, systems[i], T)
+        for k in ("r", "v", "deact_step", "reason", "planet"):
+            assert np.array_equal(res[i][k], ref[k]), (systems[i].name, k)
+    eph = orc.ephemeris(noplanet.mu0, noplanet.mu, noplanet.rp, noplanet.vp, T, noplanet.dt)
+    ref, near, spread = _oracle_reference(orc, noplanet, T, eph.table)
+    _compare(res[1], ref, near, spread, "batched/noplanet")
+    with pytest.raises(P.PlanetEncounterError):
+        P.batch_integrate(systems, nsteps=T)

@@ -211,6 +211,41 @@ def test_planet_encounter_flag(orc):
                                      np.zeros(2), np.zeros(2), np.array([0.0, 0.01]))
     eph = orc.ephemeris(mu0, mu, rp, vp, 10, 0.1)
     assert eph.flag == 0
+    # the first event is reported: these planets later become unbound, the flag stays 0
+    assert orc.ephemeris(mu0, mu, rp, vp, 500, 0.1).flag == 0
+
+
+def late_pair(k0=412, dt=0.1, T=1000):
+    """Two planets of 1e-12 solar masses on the same circular orbit radius
+    (5 au) and phase, one inclined by 0.1 rad: they meet at the line of nodes.
+    The phase is chosen so that step k0 falls 1e-4 rad after a node passage.
+    Returns (mu0, mu, rp, vp, dt, T, first step within the mutual Hill limit
+    of the closed-form orbits, distance/limit at that step, smallest
+    distance/limit before it)."""
+    mu0 = W.MU_SUN
+    mu = np.array([1e-12, 1e-12]) * mu0
+    n = math.sqrt((mu0 + mu[0]) / 5.0 ** 3)
+    u0 = math.remainder(-n * k0 * dt + 1e-4, 2 * math.pi)
+    rp, vp = W.elements_to_cartesian(mu0 + mu, np.array([5.0, 5.0]), np.zeros(2),
+                                     np.array([0.0, 0.1]), np.zeros(2), np.zeros(2),
+                                     np.array([u0, u0]))
+    lim = ((mu[0] + mu[1]) / (3 * mu0)) ** (1 / 3) * 5.0
+    d = 2 * 5.0 * math.sin(0.05) * np.abs(np.sin(u0 + n * dt * np.arange(T + 1)))
+    first = int(np.argmax(d < lim))
+    return mu0, mu, rp, vp, dt, T, first, d[first] / lim, d[:first].min() / lim
+
+
+def test_planet_encounter_flag_step(orc):
+    """sec. 2.2 planet map assumption, checked at every step: the flagged step
+    of a later approach is the first step at which the closed-form two-body
+    orbits are within the mutual Hill limit (the planets' mutual pull at 1e-12
+    solar masses moves them far less than the margins asserted here).  A planet
+    on a hyperbolic orbit (v^2 > 2 mu / r) is flagged -2."""
+    mu0, mu, rp, vp, dt, T, first, inside, before = late_pair()
+    assert first == 412 and inside < 0.2 and before > 3.0
+    assert orc.ephemeris(mu0, mu, rp, vp, T, dt).flag == first
+    vh = 1.5 * math.sqrt(2 * (mu0 + mu[0]) / 5.0)
+    assert orc.ephemeris(mu0, mu[:1], np.array([[5.0, 0, 0]]), np.array([[0, vh, 0]]), 20, dt).flag == -2
 
 
 # ----------------------------------------------------- whole map vs direct N-body
