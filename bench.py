@@ -21,17 +21,29 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Executed FP64 flops of one active particle-step of the particle kernel at
-# four planets and five Newton iterations (FMA = 2, ADD/MUL/transcendental
-# = 1), counted from the kernel's loop body (see the design notes' roofline
-# section, where the counter cross-check is recorded).
-FLOPS_PER_PARTICLE_STEP = {4: 629}
+# FP64 flops of one active particle-step of the particle kernel at four
+# planets when all five Newton steps run (FMA = 2, ADD/MUL/transcendental = 1),
+# counted from the compiled step loop.  Lanes stop iterating once converged,
+# so this is an upper bound; the roofline uses the executed flops measured by
+# the counter runs below whenever they were taken on the current sources.
+FLOPS_PER_PARTICLE_STEP_ALL_NEWTON = {4: 633}
 FP64_PEAK_TFLOPS = 78.6
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "particle_queue_giants_100k_traffic.json")
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "particle_queue_giants_100k_counters.json")
+COUNTERS_MD = os.path.join(ROOT, "profiles", "particle_queue_giants_100k_counters.md")
+PMC_PASSES = {
+    "p1": "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 "
+          "SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU_FLOPS_FP64_TRANS",
+    "p2": "SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_ANY SQ_WAIT_INST_ANY "
+          "SQ_WAIT_ANY SQ_INSTS_SALU SQ_INSTS_SMEM",
+    "p3": "FETCH_SIZE",
+    "p4": "WRITE_SIZE",
+}
+PMC_BENCH_ARGS = ("--nsteps 20000 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched "
+                  "--copy-calibration-mb 256")
 
 
 def kernel_source_hash() -> str:
-    """Fingerprint of the HIP sources (traffic counters apply to one version)."""
+    """Fingerprint of the HIP sources (counter figures apply to one version)."""
     import hashlib
     h = hashlib.sha1()
     csrc = os.path.join(ROOT, "paper_2011_03484_amd", "csrc")
@@ -41,19 +53,112 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(particle_steps_per_launch: float):
-    """HBM bytes per particle launch: the calibrated FETCH_SIZE + WRITE_SIZE
-    bytes per active particle-step of the committed counter runs, times this
-    run's particle-steps per launch; None unless the counters were taken on the
+def counter_figures():
+    """Per active particle-step figures of the committed counter runs (executed
+    FP64 flops; calibrated HBM bytes), or None unless they were taken on the
     current kernel sources."""
     try:
-        import json as _j
-        d = _j.load(open(TRAFFIC_FILE))
+        d = json.load(open(COUNTERS_JSON))
     except (OSError, ValueError):
         return None
-    if d.get("source_hash") != kernel_source_hash():
+    return d if d.get("source_hash") == kernel_source_hash() else None
+
+
+def summarize_counters(pmc_dir: str) -> None:
+    """Write the counter summary (markdown) and its per-particle-step figures
+    (json) from the four rocprofv3 --pmc passes under pmc_dir/p1..p4, each made
+    by `rocprofv3 --pmc <PMC_PASSES[p]> --kernel-trace -f csv -d <pmc_dir>/<p>
+    -o run -- python3 bench.py <PMC_BENCH_ARGS>` with its output in
+    <pmc_dir>/<p>.log."""
+    import collections
+    import csv
+
+    def label(r):
+        k = r["Kernel_Name"]
+        if "particle_queue" in k:
+            return "particle_queue<4,5>"
+        if "copyBuffer" in k and int(r["Grid_Size"]) == 131072:
+            return "device copy 256 MiB"
         return None
-    return d["bytes_per_particle_step"] * particle_steps_per_launch
+
+    tot = collections.defaultdict(float)
+    cnt = collections.Counter()
+    for p in PMC_PASSES:
+        for r in csv.DictReader(open(os.path.join(pmc_dir, p, "run_counter_collection.csv"))):
+            lab = label(r)
+            if lab:
+                tot[(p, lab, r["Counter_Name"])] += float(r["Counter_Value"])
+                cnt[(p, lab, r["Counter_Name"])] += 1
+    kt, kn = 0.0, 0
+    for r in csv.DictReader(open(os.path.join(pmc_dir, "p2", "run_kernel_trace.csv"))):
+        if "particle_queue" in r["Kernel_Name"]:
+            kt += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+            kn += 1
+    runs = {p: json.loads([x for x in open(os.path.join(pmc_dir, p + ".log")) if x.startswith("{")][-1])
+            for p in PMC_PASSES}
+    src = {r["kernel_sources"] for r in runs.values()}
+    if len(src) != 1:
+        raise SystemExit(f"counter passes ran on different kernel sources: {src}")
+    src = src.pop()
+    aps = runs["p1"]["active_particle_steps"]
+    pq = "particle_queue<4,5>"
+    g = lambda p, c, lab=pq: tot[(p, lab, c)]
+    launches = cnt[("p1", pq, "SQ_WAVES")]
+    waves = g("p1", "SQ_WAVES") / launches
+    fetch_f = 262144.0 / g("p3", "FETCH_SIZE", "device copy 256 MiB")
+    write_f = 262144.0 / g("p4", "WRITE_SIZE", "device copy 256 MiB")
+    fetch_b = g("p3", "FETCH_SIZE") / launches * 1024 * fetch_f
+    write_b = g("p4", "WRITE_SIZE") / launches * 1024 * write_f
+    bpps = (fetch_b + write_b) / (aps / launches)
+    per = lambda c: 64 * g("p1", c) / aps
+    fpps = per("SQ_INSTS_VALU_FLOPS_FP64")
+    steps = int(PMC_BENCH_ARGS.split()[1])
+    out = [f"# particle_queue<4,5> counters -- giants_100k, 100,000 particles x {steps:,} steps "
+           f"({launches} launches)", "",
+           "Commands (one rocprofv3 run per pass, `cd /tmp && export TMPDIR=/tmp` first), then "
+           "`python3 bench.py --summarize-counters <out>` for this summary:", ""]
+    for p, c in PMC_PASSES.items():
+        out.append(f"    timeout -s KILL 90 rocprofv3 --pmc {c} --kernel-trace -f csv -d <out>/{p} "
+                   f"-o run -- python3 <repo>/bench.py {PMC_BENCH_ARGS} > <out>/{p}.log")
+    out += ["", f"Kernel sources of the counted runs: `bench.kernel_source_hash()` = `{src}`.", "",
+            f"Sums over the {launches} dispatches of the particle kernel and over the one 256 MiB "
+            "device-to-device copy (its source evicted from the last-level cache first by writing "
+            "a 1 GiB buffer), from `run_counter_collection.csv`:", "",
+            "| kernel | counter | value |", "|---|---|---|"]
+    for (p, lab, c), v in tot.items():
+        out.append(f"| {lab} | {c} | {v:.6g} |")
+    busy = g("p2", "SQ_ACTIVE_INST_VALU") / (1024 * kt * 2.4e9 / 4)
+    out += ["", f"Derived (particle kernel; kernel-trace time of pass 2 = {kt * 1e3:.1f} ms for "
+                f"{kn} launches; {aps:,} active particle-steps):", "",
+            f"* VALU instructions per wavefront-step: {g('p1', 'SQ_INSTS_VALU'):.4g} / ({waves:.0f} "
+            f"waves x {steps:,} steps) = {g('p1', 'SQ_INSTS_VALU') / (waves * steps):.0f}.",
+            f"* Executed FP64 per active particle-step (64 x instructions / particle-steps): "
+            f"{per('SQ_INSTS_VALU_FMA_F64'):.1f} FMA, {per('SQ_INSTS_VALU_MUL_F64'):.1f} mul, "
+            f"{per('SQ_INSTS_VALU_ADD_F64'):.1f} add, {per('SQ_INSTS_VALU_TRANS_F64'):.1f} "
+            f"transcendental; flops (FMA = 2) {fpps:.1f}.  All five Newton steps would give "
+            f"{FLOPS_PER_PARTICLE_STEP_ALL_NEWTON[4]} (static count of the compiled step loop); "
+            "lanes stop once converged.  Masked lanes of removed particles are included.",
+            f"* SIMD VALU occupancy: SQ_ACTIVE_INST_VALU / (1024 SIMDs x {kt * 1e3:.1f} ms x 2.4 GHz "
+            f"/ 4) = {busy * 100:.0f}%.",
+            f"* FP64 rate under the profiler: {fpps:.1f} x {aps:.4g} / {kt * 1e3:.1f} ms = "
+            f"{fpps * aps / kt / 1e12:.1f} TFLOP/s = {fpps * aps / kt / 1e12 / FP64_PEAK_TFLOPS * 100:.0f}% "
+            f"of {FP64_PEAK_TFLOPS}.",
+            f"* Calibration: the 256 MiB copy reads FETCH_SIZE "
+            f"{g('p3', 'FETCH_SIZE', 'device copy 256 MiB'):.0f} KiB (factor {fetch_f:.4f}) and "
+            f"WRITE_SIZE {g('p4', 'WRITE_SIZE', 'device copy 256 MiB'):.0f} KiB (factor {write_f:.4f}).",
+            f"* HBM traffic per launch, calibrated: fetch {fetch_b / 1e6:.2f} MB + write "
+            f"{write_b / 1e6:.2f} MB = {(fetch_b + write_b) / 1e6:.2f} MB for {aps / launches:,.0f} "
+            f"active particle-steps, i.e. {bpps:.4f} B per particle-step (algorithmic: 52 B in + 48 B "
+            f"out per particle per 256-step work item = 0.39 B), "
+            f"{(fetch_b + write_b) / (kt / kn) / 1e9:.0f} GB/s."]
+    open(COUNTERS_MD, "w").write("\n".join(out) + "\n")
+    json.dump({"kernel": pq, "workload": f"giants_100k, 100,000 particles x {steps} steps",
+               "source_hash": src, "flops_per_particle_step": fpps,
+               "bytes_per_particle_step": bpps, "fetch_factor": fetch_f, "write_factor": write_f,
+               "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+               "active_particle_steps_per_launch": aps / launches, "summary": os.path.basename(COUNTERS_MD)},
+              open(COUNTERS_JSON, "w"), indent=1)
+    print("\n".join(out[-6:]))
 
 
 def cpu_baseline(w, n_sample: int, steps_sample: int):
@@ -143,9 +248,15 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device with a plain copy "
                          "kernel (the reference for scaling HBM byte counters)")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="write the counter summary under profiles/ from rocprofv3 --pmc passes "
+                         "p1..p4 in DIR, then exit (no GPU use)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
+        return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
+        print("bench.py measures one GPU only: the library runs on a single MI355X "
               "(multi-GPU sharding is described in the design notes, not implemented).",
               file=sys.stderr)
         sys.exit(2)
@@ -182,8 +293,14 @@ def main():
     launches = sum(s["chunks"] for s in stats)
     eph_ms = sum(s["ephemeris_ms"] for s in stats)
     pstream_ms = sum(s["particle_ms"] for s in stats)
-    fpps = FLOPS_PER_PARTICLE_STEP.get(w.np_)
+    cf = counter_figures()
+    if cf is not None:
+        fpps, fsrc = cf["flops_per_particle_step"], "executed, from the committed counter runs"
+    else:
+        fpps = FLOPS_PER_PARTICLE_STEP_ALL_NEWTON.get(w.np_)
+        fsrc = "static count with all Newton steps (upper bound; counters not taken on these sources)"
     achieved = fpps * aps / (kern_ms / 1e3) / 1e12 if fpps and kern_ms > 0 else None
+    traffic = cf["bytes_per_particle_step"] * aps / max(launches, 1) if cf is not None else None
     line = {
         "metric": "FP64 particle-steps/sec and % FP64 peak, 1 MI355X; adjoint/forward cost ratio",
         "value": aps / secs,
@@ -204,14 +321,15 @@ def main():
                    "kepler_iters": w.kepler_iters},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS if achieved else None,
-                     "traffic": measured_traffic(aps / max(launches, 1))},
+                     "traffic": traffic},
         "kernel": {"name": "particle_queue<4,5>", "launches": launches,
                    "avg_launch_ms": kern_ms / max(launches, 1),
-                   "flops_per_particle_step": fpps,
+                   "flops_per_particle_step": fpps, "flops_source": fsrc,
                    "particle_steps_per_s_kernels_only": aps / (kern_ms / 1e3) if kern_ms else None,
                    "particle_stream_ms": pstream_ms, "ephemeris_stream_ms": eph_ms},
         "active_particle_steps": aps,
         "survivors_per_run": [s["count_by_reason"][0] for s in stats],
+        "kernel_sources": kernel_source_hash(),
     }
     for s in sims:
         s.close()

@@ -9,10 +9,12 @@
 //   fdot = -a^2 n sin x / (r1 r0),  gdot = 1 + (a/r1)(cos x - 1),
 // with r1 = a F'(x), give r' = f r + g v and v' = fdot r + gdot v.
 //
-// Particle version (drift_fixed): a fixed number k of Newton steps from a
-// fixed starting guess and no early exit, so every lane of a wavefront runs
-// the same instruction stream (sec. 2.2: the slowest lane of a group sets the
-// group's time, hence a fixed iteration count).  The starter is the
+// Particle version (drift_fixed): at most k Newton steps from a fixed
+// starting guess (sec. 2.2: a fixed iteration count, since the slowest lane of
+// a group sets the group's time).  A lane stops early only once its iterate
+// has converged to rounding (kepler_newton), so the result is the k-step
+// result up to an ulp or two, and the wavefront leaves the loop when every
+// lane has stopped.  The starter is the
 // second-order series root x0 = dM/(1-ec) - es dM^2 / (2 (1-ec)^3), clamped to
 // dM +- 2(|ec|+|es|) (a bracket of the root).  The drift is refused (returns
 // false) when the orbit is unbound or |F(x_k)| > ftol; mean anomaly steps
@@ -27,6 +29,29 @@ constexpr double TWO_PI_HI = 0x1.921fb54442d18p+2;
 constexpr double TWO_PI_LO = 0x1.1a62633145c07p-52;
 constexpr double INV_TWO_PI = 0x1.45f306dc9c883p-3;
 
+
+// At most kiters Newton steps on F(x) = x - ec sin x + es (1 - cos x) - dM
+// from xk.  A lane stops after a step whose correction is at most 2^-30 |x|:
+// the error left after that step is below e/(2(1-e)) (2^-30 |x|)^2, under one
+// ulp of x for e <= 0.99 and |x| <= 4, so the rest of the fixed count could
+// only move x by rounding.  The stop is each lane's own decision, so the
+// result of a particle does not depend on which particles share its
+// wavefront.  Lanes with a NaN state (unbound orbits) never stop early.
+TPM_DEV double kepler_newton(double ec, double es, double dM, int kiters, double xk) {
+  bool done = false;
+  for (int it = 0; it < kiters; ++it) {
+    if (__all(done)) break;
+    double s, c;
+    sincos(xk, s, c);
+    double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
+    double Fp = fma_(-ec, c, fma_(es, s, 1.0));
+    double xn = fma_(-F, rcp_newton(Fp), xk);
+    bool small = __builtin_fabs(xn - xk) <= 0x1p-30 * __builtin_fabs(xn);
+    xk = done ? xk : xn;
+    done = done || small;
+  }
+  return xk;
+}
 
 // Drift (x, v) by dt about mass mu with k fixed Newton iterations.  Writes the
 // drifted state into (x, v) only where the return value is true.
@@ -62,13 +87,8 @@ TPM_DEV bool drift_fixed(const KepConst& K, double dt, int kiters, double ftol,
   double xk = t * fma_(-0.5 * es * t, oinv, 1.0);
   double w = 2.0 * (__builtin_fabs(ec) + __builtin_fabs(es));
   xk = __builtin_fmin(__builtin_fmax(xk, dM - w), dM + w);
+  xk = kepler_newton(ec, es, dM, kiters, xk);
   double s, c;
-  for (int it = 0; it < kiters; ++it) {
-    sincos(xk, s, c);
-    double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
-    double Fp = fma_(-ec, c, fma_(es, s, 1.0));
-    xk = fma_(-F, rcp_newton(Fp), xk);
-  }
   sincos(xk, s, c);
   double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
   double Fp = fma_(-ec, c, fma_(es, s, 1.0));
