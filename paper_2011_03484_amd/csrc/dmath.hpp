@@ -1,5 +1,6 @@
 // FP64 device math for gfx950: reciprocal, reciprocal square root and sin/cos,
-// all branch-free so that every lane of a wavefront runs the same instructions.
+// free of lane-divergent branches, so every lane of a wavefront runs the same
+// instructions.
 //
 // * rcp / rsqrt start from the hardware approximations (v_rcp_f64, v_rsq_f64,
 //   about 23 good bits) and refine them by Newton-Raphson with fused
@@ -9,7 +10,8 @@
 //   done in fused multiply-adds (exact first product for the quadrant counts
 //   used here, |q| <= 2^20), then evaluates the Taylor series of sin and cos on
 //   [-pi/4, pi/4] (truncation below 1e-19) in Estrin's form and picks the
-//   quadrant with selects.
+//   quadrant with selects; a wavefront whose arguments are all inside
+//   [-0.78, 0.78] skips the reduction (same values).
 //   The constants are pi/2 split into its nearest double and the nearest double
 //   to the remainder (from 50-digit pi; gen_constants.py reproduces them) and
 //   the reciprocals 1/n! of the Taylor series.
@@ -132,8 +134,16 @@ TPM_DEV void sincos_poly(double r, double& s, double& c) {
   c = w + fma_(z2, pc, tail);
 }
 
-// sin(x), cos(x) for |x| up to about 2^20, no branches.
+// sin(x), cos(x) for |x| up to about 2^20.  When every active lane of the
+// wavefront has |x| <= 0.78 (< pi/4, so the quadrant count is 0 and the
+// reduction leaves x unchanged) the reduction is skipped; the values are the
+// same (the full path would only turn a -0 input into +0).  The only branch is
+// that wave-uniform one.
 TPM_DEV void sincos(double x, double& s, double& c) {
+  if (__all(__builtin_fabs(x) <= 0.78)) {
+    sincos_poly(x, s, c);
+    return;
+  }
   double q = __builtin_rint(x * TWO_OVER_PI);
   double r = fma_(-q, PIO2_HI, x);
   r = fma_(-q, PIO2_LO, r);

@@ -49,6 +49,7 @@ struct EphConst {
   double eta[MAX_NP + 1];       // eta_b = sum_{k<=b} mu_k
   double inv_eta[MAX_NP + 1];   // 1/eta_b
   double mup[MAX_NP + 1];       // Jacobi Kepler constant mu0 eta_b / eta_{b-1}
+  double cj[MAX_NP + 1];        // mu_b / eta_b: weight of r'_b in the heliocentric positions
   // squared mutual Hill radius ((mu_i+mu_j)/(3 mu0))^(1/3) (a_i + a_j)/2 with
   // the planets' osculating semi-major axes when they were set
   double hill2[MAX_NP + 1][MAX_NP + 1];

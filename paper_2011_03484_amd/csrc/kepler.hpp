@@ -110,8 +110,9 @@ TPM_DEV bool drift_fixed(const KepConst& K, double dt, int kiters, double ftol,
 }
 
 // Converged drift for the planets (a handful of lanes in one wavefront):
-// Newton until the correction is below 4 ulp of x on every lane, at most 40
-// steps; the loop condition is taken over the whole wavefront.
+// Newton until every lane has made a step whose correction is at most
+// 2^-30 |x| (converged to rounding, as in kepler_newton), at most 40 steps;
+// the loop condition is taken over the whole wavefront.
 TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
                              double& x, double& y, double& z,
                              double& vx, double& vy, double& vz) {
@@ -144,14 +145,16 @@ TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
   xk = __builtin_fmin(__builtin_fmax(xk, dM - w), dM + w);
   double s, c;
   bool done = !(lane_on && bound);
+  xk = done ? 0.0 : xk;   // idle lanes iterate at 0 and keep sincos on its short path
   for (int it = 0; it < 40; ++it) {
     if (__all(done)) break;
     sincos(xk, s, c);
     double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
     double Fp = fma_(-ec, c, fma_(es, s, 1.0));
-    double dx = F * rcp(Fp);
-    xk = done ? xk : xk - dx;
-    done = done || (__builtin_fabs(dx) <= 0x1p-50 * __builtin_fabs(xk));
+    double xn = fma_(-F, rcp_newton(Fp), xk);
+    bool small = __builtin_fabs(xn - xk) <= 0x1p-30 * __builtin_fabs(xn);
+    xk = done ? xk : xn;
+    done = done || small;
   }
   sincos(xk, s, c);
   double Fp = fma_(-ec, c, fma_(es, s, 1.0));

@@ -324,9 +324,11 @@ TPM_DEV double bcast(double v, int src) {
 }
 
 // Heliocentric positions of bodies 0..NP (body 0 at the origin) from the
-// Jacobi positions held by lanes 1..NP:
-//   r_b = r'_b + R_{b-1},  R_b = (eta_{b-1} R_{b-1} + mu_b r_b) / eta_b.
-// The results are wave-uniform.
+// Jacobi positions held by lanes 1..NP.  The barycentre of bodies 0..b is
+// R_b = R_{b-1} + (mu_b/eta_b) r'_b, so
+//   r_b = r'_b + R_{b-1} = r'_b + sum_{k<b} (mu_k/eta_k) r'_k:
+// the broadcasts are independent and the chain is one FMA per body.  The
+// results are wave-uniform.
 template <int NP>
 TPM_DEV void helio_all(const EphConst& E, double jx, double jy, double jz,
                        double (&hx)[NP + 1], double (&hy)[NP + 1], double (&hz)[NP + 1]) {
@@ -334,13 +336,11 @@ TPM_DEV void helio_all(const EphConst& E, double jx, double jy, double jz,
   hx[0] = 0.0; hy[0] = 0.0; hz[0] = 0.0;
 #pragma unroll
   for (int b = 1; b <= NP; ++b) {
-    double px = bcast(jx, b) + Rx;
-    double py = bcast(jy, b) + Ry;
-    double pz = bcast(jz, b) + Rz;
-    hx[b] = px; hy[b] = py; hz[b] = pz;
-    Rx = fma_(E.eta[b - 1], Rx, E.mu[b] * px) * E.inv_eta[b];
-    Ry = fma_(E.eta[b - 1], Ry, E.mu[b] * py) * E.inv_eta[b];
-    Rz = fma_(E.eta[b - 1], Rz, E.mu[b] * pz) * E.inv_eta[b];
+    const double px = bcast(jx, b), py = bcast(jy, b), pz = bcast(jz, b);
+    hx[b] = px + Rx; hy[b] = py + Ry; hz[b] = pz + Rz;
+    Rx = fma_(E.cj[b], px, Rx);
+    Ry = fma_(E.cj[b], py, Ry);
+    Rz = fma_(E.cj[b], pz, Rz);
   }
 }
 

@@ -72,6 +72,7 @@ EphConst make_eph(double mu0, int np, const double* mu, const double* a) {
     E.eta[b] = E.eta[b - 1] + E.mu[b];
     E.inv_eta[b] = 1.0 / E.eta[b];
     E.mup[b] = mu0 * E.eta[b] / E.eta[b - 1];
+    E.cj[b] = E.mu[b] / E.eta[b];
   }
   for (int i = 1; i <= np; ++i)
     for (int j = 1; j <= np; ++j) {

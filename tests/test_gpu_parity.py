@@ -96,6 +96,29 @@ def test_sincos_against_mpmath(tpm):
     assert worst <= 2.0
 
 
+def test_sincos_short_path(tpm):
+    """Wavefronts whose arguments all lie in [-0.78, 0.78] skip the pi/2
+    reduction: same values as the full path (forced here by one large
+    argument per wavefront), and within 2 ulp of mpmath."""
+    import mpmath
+    mpmath.mp.dps = 40
+    rng = np.random.default_rng(3)
+    small = rng.uniform(-0.78, 0.78, 63 * 64)
+    small[:4] = [0.78, -0.78, 1e-300, 0.0]
+    s1, c1 = tpm.debug_sincos(small)                  # short path in every wavefront
+    mixed = np.insert(small.reshape(64, 63), 0, 5.0, axis=1).ravel()
+    s2, c2 = tpm.debug_sincos(mixed)                  # full path in every wavefront
+    keep = np.arange(mixed.size) % 64 != 0
+    assert np.array_equal(s1, s2[keep]) and np.array_equal(c1, c2[keep])
+    worst = 0.0
+    for xi, si, ci in zip(small[::7], s1[::7], c1[::7]):
+        ms, mc = mpmath.sin(mpmath.mpf(xi)), mpmath.cos(mpmath.mpf(xi))
+        for got, ref in ((si, ms), (ci, mc)):
+            ulp = math.ulp(max(abs(float(ref)), 2.0 ** -1022))
+            worst = max(worst, float(abs(mpmath.mpf(got) - ref)) / ulp)
+    assert worst <= 2.0, worst
+
+
 def test_drift_matches_oracle(tpm, orc):
     """Fixed-iteration drift on the GPU vs the oracle's converged drift, within
     the problem's conditioning: 8x the oracle's response to a one-ulp change of
@@ -315,6 +338,33 @@ def test_resume_is_bitwise(tpm):
     for k in ("r", "v", "deact_step", "reason", "planet"):
         assert np.array_equal(part[k], full[k]), k
     assert s.stats()["step"] == 900
+
+
+def test_time_reversal(tpm, orc):
+    """The map is time-symmetric (sec. 2.2 leapfrog): T steps of dt, then T
+    steps of -dt on the same simulation, bring the surviving particles and the
+    planets back to their initial states; the backward half also matches the
+    oracle's backward run."""
+    w = W.giants_100k(n=2048, seed=9)
+    T = 1000
+    s = _sim(tpm, w)
+    s.integrate(T, w.dt)
+    mid = s.particles()
+    rp_mid, vp_mid = s.planets()
+    s.integrate(T, -w.dt)
+    back = s.particles()
+    rp, vp = s.planets()
+    ok = back["reason"] == tpm.ACTIVE
+    assert ok.sum() > 0.9 * w.n
+    err = np.linalg.norm(back["r"][ok] - w.r[ok], axis=1) / np.linalg.norm(w.r[ok], axis=1)
+    print(f"reversal: max rel position error {err.max():.2e} over {ok.sum()} particles", flush=True)
+    assert err.max() < 1e-11
+    assert np.max(np.abs(rp - w.rp)) < 3e-10
+    e2 = orc.ephemeris(w.mu0, w.mu, rp_mid, vp_mid, T, -w.dt)
+    ref = orc.particles(w.mu0, w.mu, w.rcrit, w.rmax, e2.table, -w.dt, mid["r"][ok], mid["v"][ok], T)
+    assert np.all(ref.reason == orc.ACTIVE)
+    rel = np.linalg.norm(back["r"][ok] - ref.r, axis=1) / np.linalg.norm(ref.r, axis=1)
+    assert rel.max() < 1e-11, rel.max()
 
 
 def test_invalid_inputs_rejected(tpm):
