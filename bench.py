@@ -238,6 +238,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--resync", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--sub-chunks", type=int, default=0, help="work items per tile per chunk (0 = library default)")
+    ap.add_argument("--waves-per-simd", type=int, default=0)
     ap.add_argument("--cpu-particles", type=int, default=16384)
     ap.add_argument("--cpu-steps", type=int, default=10000)
     ap.add_argument("--no-cpu", action="store_true")
@@ -272,7 +274,8 @@ def main():
     sims = []
     for _ in range(args.warmup + args.steps):
         s = P.Simulation(r_escape=w.rmax, kepler_iters=w.kepler_iters, chunk_steps=args.chunk,
-                         resync_chunks=args.resync, block_threads=args.block, time_kernels=True)
+                         resync_chunks=args.resync, block_threads=args.block, time_kernels=True,
+                         sub_chunks=args.sub_chunks, waves_per_simd=args.waves_per_simd)
         s.set_central(w.mu0)
         s.set_planets(w.mu, w.rp, w.vp, w.rcrit)
         s.set_particles(w.r, w.v)
@@ -331,6 +334,7 @@ def main():
                    "particle_stream_ms": pstream_ms, "ephemeris_stream_ms": eph_ms},
         "active_particle_steps": aps,
         "survivors_per_run": [s["count_by_reason"][0] for s in stats],
+        "run_ms": [round(s["wall_ms"], 1) for s in stats],
         "kernel_sources": kernel_source_hash(),
     }
     for s in sims:

@@ -22,7 +22,12 @@
  *    outputs are written into caller buffers; no pointer is kept.
  *  - Return value: TPM_OK (0) or a negative TPM_E* code; tpm_last_error()
  *    then describes the failure.  Nothing is thrown or aborted across the ABI.
- *  - A tpm_sim is used by one host thread at a time.
+ *  - A tpm_sim is used by one host thread at a time.  All simulations on a
+ *    device share that device's two library streams (created on first use,
+ *    kept until the process ends); calls that enqueue work on them take a
+ *    per-device lock, so calls from several threads on one device run one at
+ *    a time.  The derivative calls (tpm_ad_backward, tpm_ad_tangent) run on
+ *    the caller's stream.
  */
 #ifndef TPMVS_H
 #define TPMVS_H
@@ -61,7 +66,7 @@ typedef struct {
   int32_t chunk_steps;    /* steps per particle launch ("planetary chunk", sec. 2.2); 0 = 1024 */
   int32_t resync_chunks;  /* chunks between compactions ("resync interval", sec. 2.2); 0 = 4 */
   int32_t block_threads;  /* particle-kernel workgroup size (64..256, multiple of 64); 0 = 64 */
-  int32_t sub_chunks;     /* work items per tile and chunk (dynamic load balance); 0 = 4 */
+  int32_t sub_chunks;     /* work items per tile and chunk (dynamic load balance); 0 = 16 */
   int32_t waves_per_simd; /* particle wavefronts launched per SIMD (upper bound); 0 = 2 */
   double r_escape;        /* remove when |r| > r_escape; <= 0 disables                */
   double kepler_ftol;     /* Kepler-failure threshold on |F(x_k)|; 0 = 1e-13         */

@@ -59,9 +59,8 @@ TPM_DEV void drift_vals(const KepConst& K, double dt, int kiters, double ftol, d
   double xk = t * fma_(-0.5 * D.es * t, oinv, 1.0);
   double w = 2.0 * (__builtin_fabs(D.ec) + __builtin_fabs(D.es));
   xk = __builtin_fmin(__builtin_fmax(xk, dM - w), dM + w);
-  xk = kepler_newton(D.ec, D.es, dM, kiters, xk);
   double s, c;
-  sincos(xk, s, c);
+  xk = kepler_solve(D.ec, D.es, dM, kiters, xk, s, c);
   double F = fma_(-D.ec, s, fma_(D.es, 1.0 - c, xk - dM));
   D.Fp = fma_(-D.ec, c, fma_(D.es, s, 1.0));
   D.ok = bound && (__builtin_fabs(F) <= ftol);

@@ -30,19 +30,40 @@ constexpr double TWO_PI_LO = 0x1.1a62633145c07p-52;
 constexpr double INV_TWO_PI = 0x1.45f306dc9c883p-3;
 
 
+// sin/cos of an iterate; SHORT when every argument of the solve is known to
+// lie within +-0.78 (see short_args), so the pi/2 reduction is skipped (the
+// values are those of the full path); otherwise each call checks by itself.
+template <bool SHORT>
+TPM_DEV void sincos_it(double x, double& s, double& c) {
+  if (SHORT) sincos_poly(x, s, c);
+  else sincos(x, s, c);
+}
+
+// A lane's starter (clamped to dM +- w, w = 2(|ec| + |es|)), root and Newton
+// iterates stay within 0.66 of zero when |dM| <= 0.45 and w <= 0.2: then
+// e <= 0.1, the root lies within 2e of dM, F' >= 1 - e and |F''| <= e, so one
+// Newton step from the starter (at most 0.4 from the root) lands within 0.01
+// of the root and later steps closer still.
+TPM_DEV bool short_args(double dM, double w) {
+  return __builtin_fabs(dM) <= 0.45 && w <= 0.2;
+}
+
 // At most kiters Newton steps on F(x) = x - ec sin x + es (1 - cos x) - dM
-// from xk.  A lane stops after a step whose correction is at most 2^-30 |x|:
-// the error left after that step is below e/(2(1-e)) (2^-30 |x|)^2, under one
-// ulp of x for e <= 0.99 and |x| <= 4, so the rest of the fixed count could
-// only move x by rounding.  The stop is each lane's own decision, so the
-// result of a particle does not depend on which particles share its
-// wavefront.  Lanes with a NaN state (unbound orbits) never stop early.
+// from xk.  After its first two steps (fewer if kiters < 2), a lane stops
+// after a step whose correction is at most 2^-30 |x|: the error left after
+// that step is below e/(2(1-e)) (2^-30 |x|)^2, under one ulp of x for
+// e <= 0.99 and |x| <= 4, so the rest of the fixed count could only move x by
+// rounding.  The stop is each lane's own decision, so the result of a
+// particle does not depend on which particles share its wavefront (the
+// wavefront leaves the loop when all its lanes have stopped).  Lanes with a
+// NaN state (unbound orbits) never stop early.
+template <bool SHORT>
 TPM_DEV double kepler_newton(double ec, double es, double dM, int kiters, double xk) {
   bool done = false;
   for (int it = 0; it < kiters; ++it) {
-    if (__all(done)) break;
+    if (it >= 2 && __all(done)) break;
     double s, c;
-    sincos(xk, s, c);
+    sincos_it<SHORT>(xk, s, c);
     double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
     double Fp = fma_(-ec, c, fma_(es, s, 1.0));
     double xn = fma_(-F, rcp_newton(Fp), xk);
@@ -50,6 +71,16 @@ TPM_DEV double kepler_newton(double ec, double es, double dM, int kiters, double
     xk = done ? xk : xn;
     done = done || small;
   }
+  return xk;
+}
+
+// The Newton solve from the starter xk and sin/cos of its result.  (Each
+// sin/cos decides its short path by itself: one copy of the loop keeps the
+// particle kernel's registers within budget.)
+TPM_DEV double kepler_solve(double ec, double es, double dM, int kiters, double xk, double& s,
+                            double& c) {
+  xk = kepler_newton<false>(ec, es, dM, kiters, xk);
+  sincos(xk, s, c);
   return xk;
 }
 
@@ -87,9 +118,8 @@ TPM_DEV bool drift_fixed(const KepConst& K, double dt, int kiters, double ftol,
   double xk = t * fma_(-0.5 * es * t, oinv, 1.0);
   double w = 2.0 * (__builtin_fabs(ec) + __builtin_fabs(es));
   xk = __builtin_fmin(__builtin_fmax(xk, dM - w), dM + w);
-  xk = kepler_newton(ec, es, dM, kiters, xk);
   double s, c;
-  sincos(xk, s, c);
+  xk = kepler_solve(ec, es, dM, kiters, xk, s, c);
   double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
   double Fp = fma_(-ec, c, fma_(es, s, 1.0));
   bool ok = bound && (__builtin_fabs(F) <= ftol);
@@ -109,10 +139,30 @@ TPM_DEV bool drift_fixed(const KepConst& K, double dt, int kiters, double ftol,
   return ok;
 }
 
+// Newton for the planets: as kepler_newton, but up to 40 steps (converged
+// to rounding on every lane); idle lanes take no part.
+template <bool SHORT>
+TPM_DEV double planet_newton(double ec, double es, double dM, bool idle, double xk) {
+  bool done = idle;
+  for (int it = 0; it < 40; ++it) {
+    if (it >= 2 && __all(done)) break;
+    double s, c;
+    sincos_it<SHORT>(xk, s, c);
+    double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
+    double Fp = fma_(-ec, c, fma_(es, s, 1.0));
+    double xn = fma_(-F, rcp_newton(Fp), xk);
+    bool small = __builtin_fabs(xn - xk) <= 0x1p-30 * __builtin_fabs(xn);
+    xk = done ? xk : xn;
+    done = done || small;
+  }
+  return xk;
+}
+
 // Converged drift for the planets (a handful of lanes in one wavefront):
 // Newton until every lane has made a step whose correction is at most
-// 2^-30 |x| (converged to rounding, as in kepler_newton), at most 40 steps;
-// the loop condition is taken over the whole wavefront.
+// 2^-30 |x| (converged to rounding, as in kepler_newton; at least two
+// steps), at most 40 steps; the loop condition is taken over the whole
+// wavefront.
 TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
                              double& x, double& y, double& z,
                              double& vx, double& vy, double& vz) {
@@ -144,19 +194,15 @@ TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
   double w = 2.0 * (__builtin_fabs(ec) + __builtin_fabs(es));
   xk = __builtin_fmin(__builtin_fmax(xk, dM - w), dM + w);
   double s, c;
-  bool done = !(lane_on && bound);
-  xk = done ? 0.0 : xk;   // idle lanes iterate at 0 and keep sincos on its short path
-  for (int it = 0; it < 40; ++it) {
-    if (__all(done)) break;
+  const bool idle = !(lane_on && bound);
+  xk = idle ? 0.0 : xk;   // idle lanes iterate at 0, inside the short sin/cos path
+  if (__all(idle || short_args(dM, w))) {
+    xk = planet_newton<true>(ec, es, dM, idle, xk);
+    sincos_poly(xk, s, c);
+  } else {
+    xk = planet_newton<false>(ec, es, dM, idle, xk);
     sincos(xk, s, c);
-    double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
-    double Fp = fma_(-ec, c, fma_(es, s, 1.0));
-    double xn = fma_(-F, rcp_newton(Fp), xk);
-    bool small = __builtin_fabs(xn - xk) <= 0x1p-30 * __builtin_fabs(xn);
-    xk = done ? xk : xn;
-    done = done || small;
   }
-  sincos(xk, s, c);
   double Fp = fma_(-ec, c, fma_(es, s, 1.0));
   double cm1 = c - 1.0;
   double r1 = a * Fp;

@@ -58,7 +58,9 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
   }
   const double h = 0.5 * A.dt;
   for (int s = s_begin; s < s_end; ++s) {
-    if (__all(reason != ST_ACTIVE)) break;
+    // leave once every lane is removed (checked every 8 steps: the check
+    // itself costs a vector-to-scalar round trip)
+    if (((s - s_begin) & 7) == 0 && __all(reason != ST_ACTIVE)) break;
     const double* row = rows + (size_t)(s + 1) * ROW;
     if (reason == ST_ACTIVE) {
       double nx = x, ny = y, nz = z;
@@ -348,32 +350,95 @@ TPM_DEV void helio_all(const EphConst& E, double jx, double jy, double jz,
 struct EphLane {
   int lane;
   bool body;
-  double mu_self, mup, ie_prev;   // mu_b, mu'_b, 1/eta_{b-1}
+  double mup, ie_prev;            // mu'_b, 1/eta_{b-1} (0 on lanes that hold no body)
+  double nb;                      // 0 on body lanes, 1 elsewhere (keeps an rsqrt finite)
   KepConst K;                     // Kepler constant mu'_b for the drift
 };
+
+// Per-lane weights that turn the lane-dependent parts of a step into plain
+// FMAs (no selects on the lane index inside the step loop).
+template <int NP>
+struct EphW {
+  double wr[NP + 1];     // mu_k/eta_k for 1 <= k < lane, else 0 (own heliocentric position)
+  double wa[NP + 1];     // mu_k for k < lane, else 0 (sum_{k<b} mu_k a_k)
+  double mul[NP + 1];    // mu_l, 0 for the lane's own body
+  double self[NP + 1];   // 1 for the lane's own body, else 0
+  double hill2[NP + 1];  // squared mutual Hill radius with body j > lane, else 0
+};
+
+template <int NP>
+TPM_DEV EphW<NP> eph_weights(const EphConst& E, int lane) {
+  EphW<NP> W;
+#pragma unroll
+  for (int k = 0; k <= NP; ++k) {
+    W.wr[k] = (k >= 1 && k < lane) ? E.cj[k] : 0.0;
+    W.wa[k] = (k < lane) ? E.mu[k] : 0.0;
+    W.mul[k] = (k == lane) ? 0.0 : E.mu[k];
+    W.self[k] = (k == lane) ? 1.0 : 0.0;
+    W.hill2[k] = 0.0;
+  }
+#pragma unroll
+  for (int b = 1; b <= NP; ++b)
+#pragma unroll
+    for (int j = b + 1; j <= NP; ++j)
+      if (lane == b) W.hill2[j] = E.hill2[b][j];
+  return W;
+}
+
+// The lane's own heliocentric position r'_b + R_{b-1} from the broadcast
+// Jacobi positions (the same bits as helio_all's entry for body b; 0 on lane
+// 0).
+template <int NP>
+TPM_DEV void own_helio(const EphW<NP>& W, double jx, double jy, double jz,
+                       const double (&px)[NP + 1], const double (&py)[NP + 1],
+                       const double (&pz)[NP + 1], double& ox, double& oy, double& oz) {
+  double Rx = 0.0, Ry = 0.0, Rz = 0.0;
+#pragma unroll
+  for (int k = 1; k <= NP; ++k) {
+    Rx = fma_(W.wr[k], px[k], Rx);
+    Ry = fma_(W.wr[k], py[k], Ry);
+    Rz = fma_(W.wr[k], pz[k], Rz);
+  }
+  ox = jx + Rx; oy = jy + Ry; oz = jz + Rz;
+}
+
+// Heliocentric positions of all bodies and the lane's own one, from the Jacobi
+// positions held by lanes 1..NP (see helio_all).
+template <int NP>
+TPM_DEV void helio_step(const EphConst& E, const EphW<NP>& W, double jx, double jy, double jz,
+                        double (&hx)[NP + 1], double (&hy)[NP + 1], double (&hz)[NP + 1],
+                        double& ox, double& oy, double& oz) {
+  double px[NP + 1], py[NP + 1], pz[NP + 1];
+  double Rx = 0.0, Ry = 0.0, Rz = 0.0;
+  hx[0] = 0.0; hy[0] = 0.0; hz[0] = 0.0;
+  px[0] = 0.0; py[0] = 0.0; pz[0] = 0.0;
+#pragma unroll
+  for (int b = 1; b <= NP; ++b) {
+    px[b] = bcast(jx, b); py[b] = bcast(jy, b); pz[b] = bcast(jz, b);
+    hx[b] = px[b] + Rx; hy[b] = py[b] + Ry; hz[b] = pz[b] + Rz;
+    Rx = fma_(E.cj[b], px[b], Rx);
+    Ry = fma_(E.cj[b], py[b], Ry);
+    Rz = fma_(E.cj[b], pz[b], Rz);
+  }
+  own_helio<NP>(W, jx, jy, jz, px, py, pz, ox, oy, oz);
+}
 
 // Interaction acceleration of the lane's Jacobi body (lanes 1..NP):
 //   a'_b = a_b - (sum_{k<b} mu_k a_k)/eta_{b-1} + mu'_b r'_b/|r'_b|^3,
 // with a_k the Newtonian acceleration of body k; lane 0 gets a_0 (h0 = -a_0).
+// (ox, oy, oz) is the lane's own heliocentric position.
 template <int NP>
-TPM_DEV void eph_accel(const EphConst& E, const EphLane& L, double jx, double jy, double jz,
-                       const double (&hx)[NP + 1], const double (&hy)[NP + 1],
-                       const double (&hz)[NP + 1], double& ax, double& ay, double& az) {
-  double ox = hx[0], oy = hy[0], oz = hz[0];
-#pragma unroll
-  for (int b = 1; b <= NP; ++b) {
-    ox = (L.lane == b) ? hx[b] : ox;
-    oy = (L.lane == b) ? hy[b] : oy;
-    oz = (L.lane == b) ? hz[b] : oz;
-  }
+TPM_DEV void eph_accel(const EphConst& E, const EphLane& L, const EphW<NP>& W, double jx,
+                       double jy, double jz, const double (&hx)[NP + 1],
+                       const double (&hy)[NP + 1], const double (&hz)[NP + 1], double ox,
+                       double oy, double oz, double& ax, double& ay, double& az) {
   double nx = 0.0, ny = 0.0, nz = 0.0;
 #pragma unroll
   for (int l = 0; l <= NP; ++l) {
     double dx = ox - hx[l], dy = oy - hy[l], dz = oz - hz[l];
     double d2 = fma_(dx, dx, fma_(dy, dy, dz * dz));
-    bool self = (l == L.lane);
-    double inv = rsqrt(self ? 1.0 : d2);
-    double k = self ? 0.0 : E.mu[l] * (inv * inv) * inv;
+    double inv = rsqrt(d2 + W.self[l]);
+    double k = W.mul[l] * (inv * inv) * inv;
     nx = fma_(-k, dx, nx);
     ny = fma_(-k, dy, ny);
     nz = fma_(-k, dz, nz);
@@ -382,38 +447,30 @@ TPM_DEV void eph_accel(const EphConst& E, const EphLane& L, double jx, double jy
   double sx = 0.0, sy = 0.0, sz = 0.0;
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    double kx = bcast(nx, k), ky = bcast(ny, k), kz = bcast(nz, k);
-    bool use = k < L.lane;
-    sx = use ? fma_(E.mu[k], kx, sx) : sx;
-    sy = use ? fma_(E.mu[k], ky, sy) : sy;
-    sz = use ? fma_(E.mu[k], kz, sz) : sz;
+    sx = fma_(W.wa[k], bcast(nx, k), sx);
+    sy = fma_(W.wa[k], bcast(ny, k), sy);
+    sz = fma_(W.wa[k], bcast(nz, k), sz);
   }
   double r2 = fma_(jx, jx, fma_(jy, jy, jz * jz));
-  double inv = rsqrt(L.body ? r2 : 1.0);
+  double inv = rsqrt(r2 + L.nb);
   double kk = L.mup * (inv * inv) * inv;
-  ax = L.body ? fma_(kk, jx, fma_(-sx, L.ie_prev, nx)) : nx;
-  ay = L.body ? fma_(kk, jy, fma_(-sy, L.ie_prev, ny)) : ny;
-  az = L.body ? fma_(kk, jz, fma_(-sz, L.ie_prev, nz)) : nz;
+  // lane 0: jx = ie_prev = 0, so a = n
+  ax = fma_(kk, jx, fma_(-sx, L.ie_prev, nx));
+  ay = fma_(kk, jy, fma_(-sy, L.ie_prev, ny));
+  az = fma_(kk, jz, fma_(-sz, L.ie_prev, nz));
 }
 
 // Any pair (lane, j > lane) closer than their mutual Hill radius.
 template <int NP>
-TPM_DEV bool hill_violation(const EphLane& L, const double (&hill2row)[NP + 1],
+TPM_DEV bool hill_violation(const EphW<NP>& W, double ox, double oy, double oz,
                             const double (&hx)[NP + 1], const double (&hy)[NP + 1],
                             const double (&hz)[NP + 1]) {
-  double ox = hx[0], oy = hy[0], oz = hz[0];
-#pragma unroll
-  for (int b = 1; b <= NP; ++b) {
-    ox = (L.lane == b) ? hx[b] : ox;
-    oy = (L.lane == b) ? hy[b] : oy;
-    oz = (L.lane == b) ? hz[b] : oz;
-  }
   bool bad = false;
 #pragma unroll
   for (int j = 2; j <= NP; ++j) {
     double dx = ox - hx[j], dy = oy - hy[j], dz = oz - hz[j];
     double d2 = fma_(dx, dx, fma_(dy, dy, dz * dz));
-    bad = bad || (L.body && j > L.lane && d2 < hill2row[j]);
+    bad = bad || (d2 < W.hill2[j]);
   }
   return bad;
 }
@@ -429,18 +486,11 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
   EphLane L;
   L.lane = threadIdx.x;
   L.body = L.lane >= 1 && L.lane <= NP;
-  L.mu_self = 0.0; L.mup = 1.0; L.ie_prev = 0.0;
-  double hill2row[NP + 1];
+  L.mup = 1.0; L.ie_prev = 0.0; L.nb = L.body ? 0.0 : 1.0;
 #pragma unroll
-  for (int j = 0; j <= NP; ++j) hill2row[j] = 0.0;
-#pragma unroll
-  for (int b = 1; b <= NP; ++b) {
-    if (L.lane == b) {
-      L.mu_self = E.mu[b]; L.mup = E.mup[b]; L.ie_prev = E.inv_eta[b - 1];
-#pragma unroll
-      for (int j = 0; j <= NP; ++j) hill2row[j] = E.hill2[b][j];
-    }
-  }
+  for (int b = 1; b <= NP; ++b)
+    if (L.lane == b) { L.mup = E.mup[b]; L.ie_prev = E.inv_eta[b - 1]; }
+  const EphW<NP> W = eph_weights<NP>(E, L.lane);
   {
     double smu, rsmu;
     sqrt_rsqrt(L.mup, smu, rsmu);
@@ -452,21 +502,14 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
     wx = vj[3 * (L.lane - 1) + 0]; wy = vj[3 * (L.lane - 1) + 1]; wz = vj[3 * (L.lane - 1) + 2];
   }
   double hx[NP + 1], hy[NP + 1], hz[NP + 1];
-  double ax, ay, az;
-  helio_all<NP>(E, jx, jy, jz, hx, hy, hz);
-  eph_accel<NP>(E, L, jx, jy, jz, hx, hy, hz, ax, ay, az);
+  double ox, oy, oz, ax, ay, az;
+  helio_step<NP>(E, W, jx, jy, jz, hx, hy, hz, ox, oy, oz);
+  eph_accel<NP>(E, L, W, jx, jy, jz, hx, hy, hz, ox, oy, oz, ax, ay, az);
   // row 0: current state; lane b writes planet b, lane 0 writes h0 = -a_0
-  double ownx = hx[0], owny = hy[0], ownz = hz[0];
-#pragma unroll
-  for (int b = 1; b <= NP; ++b) {
-    ownx = (L.lane == b) ? hx[b] : ownx;
-    owny = (L.lane == b) ? hy[b] : owny;
-    ownz = (L.lane == b) ? hz[b] : ownz;
-  }
   if (L.body) {
-    rows[3 * (L.lane - 1) + 0] = ownx;
-    rows[3 * (L.lane - 1) + 1] = owny;
-    rows[3 * (L.lane - 1) + 2] = ownz;
+    rows[3 * (L.lane - 1) + 0] = ox;
+    rows[3 * (L.lane - 1) + 1] = oy;
+    rows[3 * (L.lane - 1) + 2] = oz;
   } else if (L.lane == 0) {
     rows[3 * NP + 0] = -ax; rows[3 * NP + 1] = -ay; rows[3 * NP + 2] = -az;
   }
@@ -475,32 +518,25 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
   // step t has key 2t+1; an orbit found unbound while drifting from t-1 to t
   // has key 2t, so it wins a tie with a close pair at t (it is found first).
   int64_t first_ev = INT64_MAX;
-  if (NP > 1 && hill_violation<NP>(L, hill2row, hx, hy, hz)) first_ev = 2 * step0 + 1;
+  if (NP > 1 && hill_violation<NP>(W, ox, oy, oz, hx, hy, hz)) first_ev = 2 * step0 + 1;
   for (int s = 0; s < nsteps; ++s) {
     wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
     bool bound = drift_converged(L.K, dt, L.body, jx, jy, jz, wx, wy, wz);
     const int64_t t1 = step0 + s + 1;
     first_ev = (first_ev == INT64_MAX && L.body && !bound) ? 2 * t1 : first_ev;
-    helio_all<NP>(E, jx, jy, jz, hx, hy, hz);
-    eph_accel<NP>(E, L, jx, jy, jz, hx, hy, hz, ax, ay, az);
+    helio_step<NP>(E, W, jx, jy, jz, hx, hy, hz, ox, oy, oz);
+    eph_accel<NP>(E, L, W, jx, jy, jz, hx, hy, hz, ox, oy, oz, ax, ay, az);
     wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
     double* row = rows + (size_t)(s + 1) * ROW;
-    ownx = hx[0]; owny = hy[0]; ownz = hz[0];
-#pragma unroll
-    for (int b = 1; b <= NP; ++b) {
-      ownx = (L.lane == b) ? hx[b] : ownx;
-      owny = (L.lane == b) ? hy[b] : owny;
-      ownz = (L.lane == b) ? hz[b] : ownz;
-    }
     if (L.body) {
-      row[3 * (L.lane - 1) + 0] = ownx;
-      row[3 * (L.lane - 1) + 1] = owny;
-      row[3 * (L.lane - 1) + 2] = ownz;
+      row[3 * (L.lane - 1) + 0] = ox;
+      row[3 * (L.lane - 1) + 1] = oy;
+      row[3 * (L.lane - 1) + 2] = oz;
     } else if (L.lane == 0) {
       row[3 * NP + 0] = -ax; row[3 * NP + 1] = -ay; row[3 * NP + 2] = -az;
     }
     if (NP > 1) {
-      bool bad = hill_violation<NP>(L, hill2row, hx, hy, hz);
+      bool bad = hill_violation<NP>(W, ox, oy, oz, hx, hy, hz);
       first_ev = (first_ev == INT64_MAX && bad) ? 2 * t1 + 1 : first_ev;
     }
   }

@@ -1,6 +1,7 @@
 // Host runtime behind the C ABI of include/tpmvs.h.
 //
-// One simulation = one device, two HIP streams at default priority:
+// One simulation = one device and the device's two HIP streams (default
+// priority, shared by every simulation on the device):
 //   stream E runs the planet map chunk by chunk into a ring of planet-table
 //   slots in HBM; stream P runs the particle kernel over each slot once its
 //   rows are written.  The planet map for chunk c+1 thus overlaps the particle
@@ -13,6 +14,7 @@
 #include <algorithm>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <type_traits>
 #include <chrono>
 #include <cmath>
@@ -43,6 +45,42 @@ int fail(int code, const std::string& msg) {
       return fail(e_ == hipErrorOutOfMemory ? TPM_ENOMEM : TPM_EDEVICE,                 \
                   std::string(#expr) + ": " + hipGetErrorString(e_));                   \
   } while (0)
+
+// The two streams of a device, created once per process and shared by all
+// simulations on that device.  A pair per simulation would let the two
+// streams of one simulation land on the same hardware queue once a process
+// holds more streams than the runtime has queues, and that serializes the
+// planet map behind the particle kernel.  The long pipelined calls
+// (integrate, batched integrate) hold the device's lock, so calls from several
+// threads on one device run one after another.
+struct DeviceStreams {
+  std::mutex lock;
+  hipStream_t sP = nullptr, sE = nullptr;
+};
+
+DeviceStreams& device_streams(int dev) {
+  static std::mutex m;
+  static std::map<int, std::unique_ptr<DeviceStreams>> all;
+  std::lock_guard<std::mutex> g(m);
+  auto& p = all[dev];
+  if (!p) p.reset(new DeviceStreams());
+  return *p;
+}
+
+// Create the device's stream pair on first use (device already current).
+hipError_t ensure_device_streams(DeviceStreams& D) {
+  static std::mutex m;
+  std::lock_guard<std::mutex> g(m);
+  if (D.sP) return hipSuccess;
+  hipStream_t a = nullptr, b = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  e = hipStreamCreateWithFlags(&b, hipStreamNonBlocking);
+  if (e != hipSuccess) { (void)hipStreamDestroy(a); return e; }
+  D.sP = a;
+  D.sE = b;
+  return hipSuccess;
+}
 
 constexpr int NSLOT = 8;   // planet-table ring slots
 constexpr int NCNT = 8;    // in-flight active-count readbacks
@@ -193,8 +231,9 @@ struct tpm_sim {
   }
   void release_ring() { dfree(d_ring); d_ring = nullptr; ring_rows = 0; }
   void release_base() {
-    if (sP) { (void)hipStreamSynchronize(sP); (void)hipStreamDestroy(sP); }
-    if (sE) { (void)hipStreamSynchronize(sE); (void)hipStreamDestroy(sE); }
+    // the streams belong to the device (shared); only wait for them
+    if (sP) (void)hipStreamSynchronize(sP);
+    if (sE) (void)hipStreamSynchronize(sE);
     for (int i = 0; i < NSLOT; ++i) {
       if (ev_eph[i]) (void)hipEventDestroy(ev_eph[i]);
       if (ev_done[i]) (void)hipEventDestroy(ev_done[i]);
@@ -302,7 +341,7 @@ int tpm_create(const tpm_options* opt, tpm_sim** out) {
   if (o.chunk_steps < 0 || o.resync_chunks < 0 || o.block_threads < 0 || o.sub_chunks < 0 ||
       o.waves_per_simd < 0)
     return fail(TPM_EINVAL, "negative option");
-  if (o.sub_chunks == 0) o.sub_chunks = 4;
+  if (o.sub_chunks == 0) o.sub_chunks = 16;
   if (o.waves_per_simd == 0) o.waves_per_simd = 2;
   if (o.waves_per_simd > 8) return fail(TPM_EINVAL, "waves_per_simd > 8");
   if (o.chunk_steps == 0) o.chunk_steps = 1024;
@@ -330,10 +369,14 @@ int tpm_create(const tpm_options* opt, tpm_sim** out) {
     fail(TPM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
     return true;
   };
-  if (bad(hipStreamCreateWithFlags(&s->sP, hipStreamNonBlocking), "stream") ||
-      bad(hipStreamCreateWithFlags(&s->sE, hipStreamNonBlocking), "stream")) {
-    delete s;
-    return TPM_EDEVICE;
+  {
+    DeviceStreams& D = device_streams(o.device);
+    if (bad(ensure_device_streams(D), "stream")) {
+      delete s;
+      return TPM_EDEVICE;
+    }
+    s->sP = D.sP;
+    s->sE = D.sE;
   }
   for (int i = 0; i < NSLOT; ++i)
     if (bad(hipEventCreateWithFlags(&s->ev_eph[i], hipEventDisableTiming), "event") ||
@@ -399,6 +442,7 @@ int tpm_set_planets(tpm_sim* s, int32_t np, const double* mu, const double* r, c
     a[j] = 1.0 / alpha;
   }
   TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   TPM_HIP(hipStreamSynchronize(s->sP));
   TPM_HIP(hipStreamSynchronize(s->sE));
   s->release_planets();
@@ -444,6 +488,7 @@ int tpm_set_particles(tpm_sim* s, int64_t n, const double* r, const double* v) {
   if (n > 0 && !(finite_all(r, 3 * n) && finite_all(v, 3 * n)))
     return fail(TPM_EINVAL, "particle input not finite");
   TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   TPM_HIP(hipStreamSynchronize(s->sP));
   s->release_particles();
   const size_t nn = (size_t)std::max<int64_t>(n, 1);
@@ -498,6 +543,7 @@ int tpm_set_planet_table(tpm_sim* s, const double* table, int64_t nrows) {
   if (!s) return fail(TPM_EINVAL, "sim is NULL");
   if (!s->planets_set) return fail(TPM_ESTATE, "tpm_set_planets must come first");
   TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   TPM_HIP(hipStreamSynchronize(s->sP));
   dfree(s->d_table);
   s->d_table = nullptr;
@@ -523,6 +569,7 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   if (s->d_table && s->step + nsteps > s->table_rows - 1)
     return fail(TPM_EINVAL, "supplied planet table too short");
   TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   auto w0 = std::chrono::steady_clock::now();
   const int K = s->opt.chunk_steps;
   const int R = s->opt.resync_chunks;
@@ -684,6 +731,7 @@ int tpm_get_particles(tpm_sim* s, double* r, double* v, int64_t* deact_step, int
   if (!s) return fail(TPM_EINVAL, "sim is NULL");
   if (!s->particles_set) return fail(TPM_ESTATE, "no particles");
   TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   const int64_t n = s->n;
   if (n == 0) return TPM_OK;
   TPM_HIP(launch_finalize(s->work[s->cur], s->d_nactive, s->n_active, s->out, s->sP));
@@ -706,6 +754,7 @@ int tpm_get_planets(tpm_sim* s, double* r, double* v) {
   const int np = s->np;
   if (np == 0) return TPM_OK;
   TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   TPM_HIP(hipStreamSynchronize(s->sE));
   TPM_HIP(launch_jacobi_to_helio(s->eph(), s->d_rj, s->d_vj, s->d_tmp, s->d_tmp + 3 * np, s->sE));
   std::vector<double> h(6 * np);
@@ -732,6 +781,7 @@ int tpm_get_stats(tpm_sim* s, tpm_stats* o) {
   for (int k = 0; k < 4; ++k) st.count_by_reason[k] = 0;
   if (s->particles_set && s->n > 0) {
     TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
     TPM_HIP(hipStreamSynchronize(s->sP));
     std::vector<int32_t> reason(s->n);
     TPM_HIP(launch_finalize(s->work[s->cur], s->d_nactive, s->n_active, s->out, s->sP));
@@ -751,6 +801,7 @@ int tpm_planet_table(tpm_sim* s, int64_t nsteps, double dt, double* table) {
   if (nsteps < 0 || !table) return fail(TPM_EINVAL, "bad arguments");
   if (!std::isfinite(dt) || dt == 0.0) return fail(TPM_EINVAL, "dt must be finite and non-zero");
   TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   const int np = s->np, rl = 3 * np + 3;
   double *rj = nullptr, *vj = nullptr, *rows = nullptr;
   int64_t* flag = nullptr;
@@ -858,6 +909,7 @@ int tpm_ad_forward(tpm_sim* s, int64_t n, const double* d_r0, const double* d_v0
   if (n > 0 && (!d_r0 || !d_v0 || !d_rT || !d_vT)) return fail(TPM_EINVAL, "NULL array");
   if (!std::isfinite(dt) || dt == 0.0) return fail(TPM_EINVAL, "dt must be finite and non-zero");
   TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   hipStream_t st = (hipStream_t)stream;
   auto& A = s->ad;
   A.valid = false;
@@ -1076,6 +1128,7 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
     if (rc) return rc;
   }
   std::unique_ptr<tpm_sim, void (*)(tpm_sim*)> guard(ctx, tpm_destroy);
+  std::lock_guard<std::mutex> dev_lock(device_streams(o.device).lock);
   BatchBuffers B;
   const int K = o.chunk_steps;
   const int64_t slot_rows = K + 1;
@@ -1265,7 +1318,7 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
   };
 
   // ---- autotuner: time one chunk of each candidate from the initial state
-  TuneChoice choice{o.sub_chunks > 0 ? o.sub_chunks : 4, o.waves_per_simd > 0 ? o.waves_per_simd : 2};
+  TuneChoice choice{o.sub_chunks > 0 ? o.sub_chunks : 16, o.waves_per_simd > 0 ? o.waves_per_simd : 2};
   if (autotune && nchunks > 0 && ntiles > 0) {
     hipDeviceProp_t prop;
     TPM_HIP(hipGetDeviceProperties(&prop, o.device));
@@ -1276,7 +1329,7 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
     if (it != tune_cache().end()) {
       choice = it->second;
     } else {
-      const TuneChoice cands[] = {{1, 2}, {4, 2}, {8, 2}, {4, 1}, {4, 4}};
+      const TuneChoice cands[] = {{4, 2}, {8, 2}, {16, 2}, {4, 4}, {16, 4}};
       float best = 1e30f;
       for (const auto& cand : cands) {
         int rc = reset_run();
