@@ -149,7 +149,8 @@ def summarize_counters(pmc_dir: str) -> None:
             f"* HBM traffic per launch, calibrated: fetch {fetch_b / 1e6:.2f} MB + write "
             f"{write_b / 1e6:.2f} MB = {(fetch_b + write_b) / 1e6:.2f} MB for {aps / launches:,.0f} "
             f"active particle-steps, i.e. {bpps:.4f} B per particle-step (algorithmic: 52 B in + 48 B "
-            f"out per particle per 256-step work item = 0.39 B), "
+            f"out per particle per 64-step work item, the default 16 items per 1,024-step chunk, "
+            f"= 1.56 B), "
             f"{(fetch_b + write_b) / (kt / kn) / 1e9:.0f} GB/s."]
     open(COUNTERS_MD, "w").write("\n".join(out) + "\n")
     json.dump({"kernel": pq, "workload": f"giants_100k, 100,000 particles x {steps} steps",

@@ -145,7 +145,7 @@ particle_queue(Work w, const int32_t* __restrict__ d_nactive, Out out,
       uint32_t spins = 0;
       for (;;) {
         const uint32_t p = (uint32_t)__builtin_amdgcn_readfirstlane(
-            (int)__hip_atomic_load(Q.progress + t, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+            (int)__hip_atomic_load(Q.progress + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if ((int32_t)(p - target) >= 0) break;
         if (++spins > SPIN_LIMIT) {
           atomicOr(Q.error, 1);
@@ -154,6 +154,10 @@ particle_queue(Work w, const int32_t* __restrict__ d_nactive, Out out,
         }
         __builtin_amdgcn_s_sleep(2);
       }
+      // One acquire after the wait.  An acquire per poll would invalidate
+      // the caches (L2 included on this multi-die device) on every iteration,
+      // costing every wavefront on the die its cached planet rows.
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     const int s_begin = s * Q.sub_steps;
     const int s_end = min(Q.nsteps, s_begin + Q.sub_steps);
@@ -214,7 +218,7 @@ particle_batch_queue(const SysDev* __restrict__ sys, const TileDesc* __restrict_
       uint32_t spins = 0;
       for (;;) {
         const uint32_t p = (uint32_t)__builtin_amdgcn_readfirstlane(
-            (int)__hip_atomic_load(Q.progress + t, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+            (int)__hip_atomic_load(Q.progress + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if ((int32_t)(p - target) >= 0) break;
         if (++spins > SPIN_LIMIT) {
           atomicOr(Q.error, 1);
@@ -223,6 +227,10 @@ particle_batch_queue(const SysDev* __restrict__ sys, const TileDesc* __restrict_
         }
         __builtin_amdgcn_s_sleep(2);
       }
+      // One acquire after the wait.  An acquire per poll would invalidate
+      // the caches (L2 included on this multi-die device) on every iteration,
+      // costing every wavefront on the die its cached planet rows.
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     const int s_begin = s * Q.sub_steps;
     const int s_end = min(Q.nsteps, s_begin + Q.sub_steps);
