@@ -341,11 +341,11 @@ int tpm_create(const tpm_options* opt, tpm_sim** out) {
   if (o.chunk_steps < 0 || o.resync_chunks < 0 || o.block_threads < 0 || o.sub_chunks < 0 ||
       o.waves_per_simd < 0)
     return fail(TPM_EINVAL, "negative option");
-  if (o.sub_chunks == 0) o.sub_chunks = 16;
+  if (o.sub_chunks == 0) o.sub_chunks = 64;
   if (o.waves_per_simd == 0) o.waves_per_simd = 2;
   if (o.waves_per_simd > 8) return fail(TPM_EINVAL, "waves_per_simd > 8");
-  if (o.chunk_steps == 0) o.chunk_steps = 1024;
-  if (o.resync_chunks == 0) o.resync_chunks = 4;
+  if (o.chunk_steps == 0) o.chunk_steps = 8192;
+  if (o.resync_chunks == 0) o.resync_chunks = 1;
   if (o.block_threads == 0) o.block_threads = 64;
   if (o.block_threads % 64 || o.block_threads > 256)
     return fail(TPM_EINVAL, "block_threads must be 64, 128, 192 or 256");
