@@ -54,7 +54,7 @@ TPM_DEV void drift_vals(const KepConst& K, double dt, int kiters, double ftol, d
   double dte = (D.q == 0.0) ? dt : D.dMr * ninv;
   dM = D.dMr;
   double om = 1.0 - D.ec;
-  double oinv = rcp(om);
+  double oinv = rcp_newton(om);
   double t = dM * oinv;
   double xk = t * fma_(-0.5 * D.es * t, oinv, 1.0);
   double w = 2.0 * (__builtin_fabs(D.ec) + __builtin_fabs(D.es));

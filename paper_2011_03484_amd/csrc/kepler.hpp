@@ -111,9 +111,9 @@ TPM_DEV bool drift_fixed(const KepConst& K, double dt, int kiters, double ftol,
   dMr = fma_(-q, TWO_PI_LO, dMr);
   double dte = (q == 0.0) ? dt : dMr * ninv;
   dM = dMr;
-  // starter
+  // starter (only a first guess: a one-refinement reciprocal is enough)
   double om = 1.0 - ec;
-  double oinv = rcp(om);
+  double oinv = rcp_newton(om);
   double t = dM * oinv;
   double xk = t * fma_(-0.5 * es * t, oinv, 1.0);
   double w = 2.0 * (__builtin_fabs(ec) + __builtin_fabs(es));
@@ -122,7 +122,8 @@ TPM_DEV bool drift_fixed(const KepConst& K, double dt, int kiters, double ftol,
   xk = kepler_solve(ec, es, dM, kiters, xk, s, c);
   double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
   double Fp = fma_(-ec, c, fma_(es, s, 1.0));
-  bool ok = bound && (__builtin_fabs(F) <= ftol);
+  // one compare: an unbound orbit counts as an infinite residual
+  const bool ok = (bound ? __builtin_fabs(F) : __builtin_inf()) <= ftol;
   double cm1 = c - 1.0;
   double r1 = a * Fp;
   double r1inv = rcp(r1);

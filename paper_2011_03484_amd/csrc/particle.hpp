@@ -23,14 +23,14 @@ TPM_DEV int accel(const double* __restrict__ row, const PlanetConst<NP>& P,
   ax = row[3 * NP + 0];
   ay = row[3 * NP + 1];
   az = row[3 * NP + 2];
-  int hit = -1;
+  double d2s[NP > 0 ? NP : 1];
 #pragma unroll
   for (int j = 0; j < NP; ++j) {
     double dx = x - row[3 * j + 0];
     double dy = y - row[3 * j + 1];
     double dz = z - row[3 * j + 2];
     double d2 = fma_(dx, dx, fma_(dy, dy, dz * dz));
-    hit = (hit < 0 && d2 < P.rcrit2[j]) ? j : hit;
+    d2s[j] = d2;
     // the kick is a perturbation (|a| << mu0/r^2): 2^-46 relative is ample
     double inv = rsqrt1(d2);
     double k = P.mu[j] * (inv * inv) * inv;
@@ -38,6 +38,11 @@ TPM_DEV int accel(const double* __restrict__ row, const PlanetConst<NP>& P,
     ay = fma_(-k, dy, ay);
     az = fma_(-k, dz, az);
   }
+  // lowest planet index inside its radius: scanning downwards, the last hit
+  // wins (one compare per planet, no combined lane predicates)
+  int hit = -1;
+#pragma unroll
+  for (int j = NP - 1; j >= 0; --j) hit = d2s[j] < P.rcrit2[j] ? j : hit;
   return hit;
 }
 
