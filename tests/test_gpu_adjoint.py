@@ -163,3 +163,37 @@ def test_gradient_vs_central_differences(env):
           f"median rel {np.median(rel[ok]):.2e}", flush=True)
     assert ok.sum() > 0.3 * w.n
     assert frac > 0.95
+
+
+def test_full_size_derivatives_sampled(env, orc):
+    """The 16,384-particle derivative workload (checkpoint every 1,000 steps),
+    2,000 steps: tangent and adjoint of every 128th particle against the
+    oracle's complex-step state-transition matrix."""
+    torch, P, AG = env
+    w = W.adjoint_16k().subset(nsteps=2000)
+    s = _sim(P, w)
+    r0 = _t(torch, w.r).requires_grad_(True)
+    v0 = _t(torch, w.v).requires_grad_(True)
+    rT, vT, step, _ = AG.integrate(s, r0, v0, w.nsteps, w.dt, 1000)
+    rng = np.random.default_rng(11)
+    dr, dv = rng.normal(size=(w.n, 3)), rng.normal(size=(w.n, 3))
+    tr, tv = AG.tangent(s, _t(torch, dr), _t(torch, dv))
+    gr, gv = rng.normal(size=(w.n, 3)), rng.normal(size=(w.n, 3))
+    (rT * _t(torch, gr)).sum().add((vT * _t(torch, gv)).sum()).backward()
+    idx = np.arange(0, w.n, 128)
+    eph = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, w.nsteps, w.dt)
+    ref = orc.particles(w.mu0, w.mu, w.rcrit, w.rmax, eph.table, w.dt, w.r[idx], w.v[idx], w.nsteps)
+    M = orc.stm(w.mu0, w.mu, w.rcrit, w.rmax, eph.table, w.dt, w.r[idx], w.v[idx], w.nsteps)
+    same = ref.deact_step == step.cpu().numpy()[idx]
+    tan = np.concatenate([tr.cpu().numpy()[idx], tv.cpu().numpy()[idx]], 1)
+    tan_ref = np.einsum("nij,nj->ni", M, np.concatenate([dr[idx], dv[idx]], 1))
+    adj = np.concatenate([r0.grad.cpu().numpy()[idx], v0.grad.cpu().numpy()[idx]], 1)
+    adj_ref = np.einsum("nij,ni->nj", M, np.concatenate([gr[idx], gv[idx]], 1))
+    norm = np.linalg.norm(M, axis=(1, 2))
+    et = np.linalg.norm(tan - tan_ref, axis=1) / (np.linalg.norm(tan_ref, axis=1) + 1e-300)
+    ea = np.linalg.norm(adj - adj_ref, axis=1) / (np.linalg.norm(adj_ref, axis=1) + 1e-300)
+    ok = same & (norm < 1e4)
+    print(f"full-size derivatives: tangent {et[ok].max():.2e}, adjoint {ea[ok].max():.2e}, "
+          f"compared {ok.sum()}/{len(idx)}", flush=True)
+    assert ok.sum() > 0.5 * len(idx)
+    assert et[ok].max() < 1e-8 and ea[ok].max() < 1e-8

@@ -394,3 +394,66 @@ def test_full_size_giants_sampled(tpm, orc):
     res, near, spread = _oracle_reference(orc, sub, T, eph.table)
     gs = {k: g[k][idx] for k in ("r", "v", "deact_step", "reason", "planet")}
     _compare(gs, res, near, spread, "giants_100k/full")
+
+
+def test_full_size_resonant_sampled(tpm, orc):
+    """The 200,000-particle resonant workload (e up to 0.5, i up to 20 degrees:
+    more Newton steps and the long sin/cos path) in the default launch
+    configuration, 1,000 steps; every 199th particle checked against the
+    oracle."""
+    w = W.resonant_200k()
+    T = 1000
+    g = _run(tpm, w, T)
+    idx = np.arange(0, w.n, 199)
+    sub = w.subset()
+    sub.r, sub.v = w.r[idx], w.v[idx]
+    eph = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, T, w.dt)
+    res, near, spread = _oracle_reference(orc, sub, T, eph.table)
+    gs = {k: g[k][idx] for k in ("r", "v", "deact_step", "reason", "planet")}
+    _compare(gs, res, near, spread, "resonant_200k/full")
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 191])
+def test_ragged_and_empty_particle_sets(tpm, orc, n):
+    """Working sets that are empty, a single particle, or end in a partial
+    wavefront tile, against the oracle element by element."""
+    w = W.giants_100k(n=max(n, 1), seed=21).subset(n=n)
+    T = 300
+    g = _run(tpm, w, T)
+    assert g["r"].shape == (n, 3)
+    if n == 0:
+        return
+    eph = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, T, w.dt)
+    res, near, spread = _oracle_reference(orc, w, T, eph.table)
+    _compare(g, res, near, spread, f"ragged/{n}")
+
+
+def test_eight_planets_single_system(tpm, orc):
+    """The largest planet count (8) on the single-system path: planet table and
+    particles against the oracle."""
+    rng = np.random.default_rng(88)
+    mu0 = W.MU_SUN
+    a = np.array([0.4, 0.7, 1.0, 1.5, 5.2, 9.5, 19.2, 30.1])
+    mu = np.array([1.7e-7, 2.4e-6, 3.0e-6, 3.2e-7, 9.5e-4, 2.9e-4, 4.4e-5, 5.2e-5]) * mu0
+    rp, vp = W.elements_to_cartesian(mu0 + mu, a, rng.uniform(0, 0.05, 8), rng.uniform(0, 0.03, 8),
+                                     rng.uniform(0, 2 * math.pi, 8), rng.uniform(0, 2 * math.pi, 8),
+                                     rng.uniform(0, 2 * math.pi, 8))
+    n = 700
+    ar = rng.uniform(2.0, 4.5, n)
+    r, v = W.elements_to_cartesian(np.full(n, mu0), ar, rng.uniform(0, 0.1, n),
+                                   rng.uniform(0, 0.1, n), rng.uniform(0, 2 * math.pi, n),
+                                   rng.uniform(0, 2 * math.pi, n), rng.uniform(0, 2 * math.pi, n))
+    rcrit = W.hill_radius(mu0, mu, a)
+    dt = 0.4 / 365.25 * 20          # 1/30 of the innermost period, roughly
+    T = 800
+    w = W.Workload("eight", mu0, mu, rp, vp, rcrit, 100.0, r, v, dt, T)
+    s = _sim(tpm, w)
+    table = s.planet_table(T, dt)
+    eph = orc.ephemeris(mu0, mu, rp, vp, T, dt)
+    assert eph.flag == -1
+    scale = np.abs(eph.table).max()
+    assert np.max(np.abs(table - eph.table)) <= 1e-11 * scale
+    s.integrate(T, dt)
+    g = s.particles()
+    res, near, spread = _oracle_reference(orc, w, T, eph.table)
+    _compare(g, res, near, spread, "eight_planets")
