@@ -4,8 +4,8 @@
 //    for hundreds of steps (sec. 2.2: a single kernel loops over the planet
 //    chunk so each particle is read and written once per chunk), with the
 //    chunk's (tile, sub-chunk) items handed out dynamically to wavefronts.
-//    Every lane reads the same planet-table row, so the row is fetched with
-//    scalar loads (wave-uniform address) into SGPRs.
+//    Every lane reads the same planet-table row: broadcast vector loads into
+//    VGPRs, one step ahead of its use.
 //  * ephemeris_chunk - one wavefront; lane b holds Jacobi body b.  Wisdom-Holman
 //    kick-drift-kick of the planets (sec. 2.2, planet integration) writing the
 //    heliocentric positions and the indirect term h0 per step.
@@ -29,12 +29,13 @@ struct ChunkArgs {
 };
 
 // Advance particle i of the working set through steps [s_begin, s_end) of a
-// chunk whose rows start at `rows` (row k = step step0 + k).  The step loop
-// is uniform across the wavefront (s_begin, s_end are wave-uniform), so row
-// addresses stay wave-uniform and are read with scalar loads; removed lanes
-// are masked off and the wavefront leaves early once none is active.
-// KIT > 0 fixes the Newton count at compile time.
-template <int NP, int KIT>
+// chunk whose rows start at `rows` (row k = step step0 + k; all rows of the
+// chunk are written before the launch).  The step loop is uniform across the
+// wavefront (s_begin, s_end are wave-uniform); removed lanes are masked off
+// and the wavefront leaves early once none is active.  KIT > 0 fixes the
+// Newton count at compile time; PREFETCH fetches each planet row a step
+// ahead into VGPRs (for launches with about one wavefront per SIMD).
+template <int NP, int KIT, bool PREFETCH>
 TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const ChunkArgs<NP>& A,
                      int i, bool valid, int s_begin, int s_end) {
   constexpr int ROW = 3 * NP + 3;
@@ -57,11 +58,8 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
     }
   }
   const double h = 0.5 * A.dt;
-  for (int s = s_begin; s < s_end; ++s) {
-    // leave once every lane is removed (checked every 8 steps: the check
-    // itself costs a vector-to-scalar round trip)
-    if (((s - s_begin) & 7) == 0 && __all(reason != ST_ACTIVE)) break;
-    const double* row = rows + (size_t)(s + 1) * ROW;
+  // one step s -> s + 1, with the row that ends it (row s + 1)
+  auto step = [&](int s, const auto& row) {
     if (reason == ST_ACTIVE) {
       double nx = x, ny = y, nz = z;
       double nvx = fma_(h, ax, vx), nvy = fma_(h, ay, vy), nvz = fma_(h, az, vz);
@@ -81,6 +79,34 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
           reason = ST_ESCAPE; dstep = A.step0 + s + 1;
         }
       }
+    }
+  };
+  // leave once every lane is removed (checked every 8 steps: the check itself
+  // costs a vector-to-scalar round trip)
+  auto all_removed = [&](int s) {
+    return ((s - s_begin) & 7) == 0 && __all(reason != ST_ACTIVE);
+  };
+  if (PREFETCH) {
+    // The row that ends step s is fetched during step s - 1, into the one of
+    // two alternating VGPR buffers that step s - 1 does not use: with one
+    // wavefront per SIMD (the usual case once removals have thinned the
+    // working set) nothing else hides that load's latency.
+    const int zero = opaque_zero_vgpr();
+    Row<NP> ra, rb;
+    load_row<NP>(ra, rows + (size_t)(s_begin + 1) * ROW, zero);
+    for (int s = s_begin; s < s_end; s += 2) {
+      if (all_removed(s)) break;
+      load_row<NP>(rb, rows + (size_t)min(s + 2, s_end) * ROW, zero);
+      step(s, ra.v);
+      if (s + 1 >= s_end) break;
+      load_row<NP>(ra, rows + (size_t)min(s + 3, s_end) * ROW, zero);
+      step(s + 1, rb.v);
+    }
+  } else {
+    // many wavefronts per SIMD: rows by scalar loads at their use
+    for (int s = s_begin; s < s_end; ++s) {
+      if (all_removed(s)) break;
+      step(s, rows + (size_t)(s + 1) * ROW);
     }
   }
   if (!valid) return;
@@ -163,7 +189,7 @@ particle_queue(Work w, const int32_t* __restrict__ d_nactive, Out out,
     const int s_end = min(Q.nsteps, s_begin + Q.sub_steps);
     if (go && s_begin < s_end) {       // the last sub-chunks of a short chunk may be empty
       const int i = t * 64 + lane;
-      advance<NP, KIT>(w, out, rows, A, i, i < n, s_begin, s_end);
+      advance<NP, KIT, true>(w, out, rows, A, i, i < n, s_begin, s_end);
     }
     // publish completion; the release orders every store of this item
     __hip_atomic_store(Q.progress + t, Q.epoch + (uint32_t)s + 1u, __ATOMIC_RELEASE,
@@ -196,9 +222,9 @@ TPM_DEV void batch_item(const SysDev& S, Work w, Out out, const double* __restri
   const int i = T.first + lane;
   const bool valid = lane < T.count;
   if (S.kiters == 5)
-    advance<NP, 5>(w, out, rows, A, i, valid, s_begin, s_end);
+    advance<NP, 5, false>(w, out, rows, A, i, valid, s_begin, s_end);
   else
-    advance<NP, 0>(w, out, rows, A, i, valid, s_begin, s_end);
+    advance<NP, 0, false>(w, out, rows, A, i, valid, s_begin, s_end);
 }
 
 __global__ void __launch_bounds__(256)

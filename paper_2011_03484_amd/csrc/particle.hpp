@@ -13,12 +13,35 @@ struct PlanetConst {
   double rcrit2[NP > 0 ? NP : 1];
 };
 
+// One planet-table row (r_1..r_NP, h0) held in VGPRs.
+template <int NP>
+struct Row {
+  double v[3 * NP + 3];
+};
+
+// A zero the compiler cannot see through, in a VGPR.  Added to a wave-uniform
+// address it turns the row's loads into vector loads (one broadcast request
+// per load): the row then lands in VGPRs, which can hold the next row while
+// the current step runs, instead of in SGPRs, which are fully used.
+TPM_DEV int opaque_zero_vgpr() {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return z;
+}
+
+// Load a row into VGPRs (issued early; the first use waits for it).
+template <int NP>
+TPM_DEV void load_row(Row<NP>& R, const double* __restrict__ row, int zero) {
+#pragma unroll
+  for (int k = 0; k < 3 * NP + 3; ++k) R.v[k] = row[zero + k];
+}
+
 // Kick acceleration from one table row (sec. 2.2, kick equation):
 //   a = h0 - sum_j mu_j d_j / |d_j|^3,   d_j = r - r_j,
 // and the encounter test |d_j| < rcrit_j (lowest j wins; -1 if none).
 // The row (3 NP + 3 doubles: r_1..r_NP, h0) is the same for every lane.
-template <int NP>
-TPM_DEV int accel(const double* __restrict__ row, const PlanetConst<NP>& P,
+template <int NP, typename RowT>
+TPM_DEV int accel(const RowT& row, const PlanetConst<NP>& P,
                   double x, double y, double z, double& ax, double& ay, double& az) {
   ax = row[3 * NP + 0];
   ay = row[3 * NP + 1];
