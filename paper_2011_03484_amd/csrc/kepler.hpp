@@ -49,39 +49,65 @@ TPM_DEV bool short_args(double dM, double w) {
 }
 
 // At most kiters Newton steps on F(x) = x - ec sin x + es (1 - cos x) - dM
-// from xk.  After its first two steps (fewer if kiters < 2), a lane stops
-// after a step whose correction is at most 2^-30 |x|: the error left after
-// that step is below e/(2(1-e)) (2^-30 |x|)^2, under one ulp of x for
-// e <= 0.99 and |x| <= 4, so the rest of the fixed count could only move x by
-// rounding.  The stop is each lane's own decision, so the result of a
-// particle does not depend on which particles share its wavefront (the
-// wavefront leaves the loop when all its lanes have stopped).  Lanes with a
-// NaN state (unbound orbits) never stop early.
+// from xk.  A lane stops after the first step whose correction is at most
+// 2^-30 |x|: the error left after that step is below
+// e/(2(1-e)) (2^-30 |x|)^2, under one ulp of x for e <= 0.99 and |x| <= 4, so
+// the rest of the fixed count could only move x by rounding.  The stop is each
+// lane's own decision, so the result of a particle does not depend on which
+// particles share its wavefront; the wavefront leaves the loop once all its
+// lanes have stopped, after two steps at the least.  Lanes with a NaN state
+// (unbound orbits) never stop early; lanes that start with done set take no
+// part.
+//
+// Returns the root and, in (s, c), its sine and cosine.  A lane's (s, c) are
+// fixed in the step where it stops, like its root: from sin/cos of the point
+// x of that step and the step's correction d (the root is x - d,
+// |d| <= 2^-30 |x - d|), the first-order rotation
+//   sin(x - d) = s - c d,  cos(x - d) = c + s d
+// leaves out terms of size d^2/2 <= 2^-61 (x - d)^2, under 0.05 ulp of
+// either value.  Lanes still iterating when the step budget runs out get
+// sin/cos of their last iterate afresh; lanes that start with done set get
+// (0, 1) (their xk is 0).  Each lane's values depend only on its own
+// iterates, whichever lanes share its wavefront.
 template <bool SHORT>
-TPM_DEV double kepler_newton(double ec, double es, double dM, int kiters, double xk) {
-  bool done = false;
+TPM_DEV double kepler_newton(double ec, double es, double dM, int kiters, bool done, double xk,
+                             double& s, double& c) {
+  bool converged = false;   // wave-uniform: every lane stopped
+  s = 0.0;
+  c = 1.0;
   for (int it = 0; it < kiters; ++it) {
-    if (it >= 2 && __all(done)) break;
-    double s, c;
-    sincos_it<SHORT>(xk, s, c);
-    double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
-    double Fp = fma_(-ec, c, fma_(es, s, 1.0));
+    if (it >= 2 && __all(done)) {
+      converged = true;
+      break;
+    }
+    double sv, cv;
+    sincos_it<SHORT>(xk, sv, cv);
+    double F = fma_(-ec, sv, fma_(es, 1.0 - cv, xk - dM));
+    double Fp = fma_(-ec, cv, fma_(es, sv, 1.0));
     double xn = fma_(-F, rcp_newton(Fp), xk);
-    bool small = __builtin_fabs(xn - xk) <= 0x1p-30 * __builtin_fabs(xn);
+    const double d = xk - xn;
+    bool small = __builtin_fabs(d) <= 0x1p-30 * __builtin_fabs(xn);
+    const double sn = fma_(-cv, d, sv), cn = fma_(sv, d, cv);
+    s = done ? s : sn;
+    c = done ? c : cn;
     xk = done ? xk : xn;
     done = done || small;
+  }
+  if (!converged) {
+    double sf, cf;
+    sincos_it<SHORT>(xk, sf, cf);
+    s = done ? s : sf;
+    c = done ? c : cf;
   }
   return xk;
 }
 
-// The Newton solve from the starter xk and sin/cos of its result.  (Each
-// sin/cos decides its short path by itself: one copy of the loop keeps the
-// particle kernel's registers within budget.)
+// The particles' Newton solve from the starter xk, with sin/cos of its result.
+// (Each sin/cos decides its short path by itself: one copy of the loop keeps
+// the particle kernel's registers within budget.)
 TPM_DEV double kepler_solve(double ec, double es, double dM, int kiters, double xk, double& s,
                             double& c) {
-  xk = kepler_newton<false>(ec, es, dM, kiters, xk);
-  sincos(xk, s, c);
-  return xk;
+  return kepler_newton<false>(ec, es, dM, kiters, false, xk, s, c);
 }
 
 // Drift (x, v) by dt about mass mu with k fixed Newton iterations.  Writes the
@@ -140,30 +166,10 @@ TPM_DEV bool drift_fixed(const KepConst& K, double dt, int kiters, double ftol,
   return ok;
 }
 
-// Newton for the planets: as kepler_newton, but up to 40 steps (converged
-// to rounding on every lane); idle lanes take no part.
-template <bool SHORT>
-TPM_DEV double planet_newton(double ec, double es, double dM, bool idle, double xk) {
-  bool done = idle;
-  for (int it = 0; it < 40; ++it) {
-    if (it >= 2 && __all(done)) break;
-    double s, c;
-    sincos_it<SHORT>(xk, s, c);
-    double F = fma_(-ec, s, fma_(es, 1.0 - c, xk - dM));
-    double Fp = fma_(-ec, c, fma_(es, s, 1.0));
-    double xn = fma_(-F, rcp_newton(Fp), xk);
-    bool small = __builtin_fabs(xn - xk) <= 0x1p-30 * __builtin_fabs(xn);
-    xk = done ? xk : xn;
-    done = done || small;
-  }
-  return xk;
-}
-
 // Converged drift for the planets (a handful of lanes in one wavefront):
 // Newton until every lane has made a step whose correction is at most
-// 2^-30 |x| (converged to rounding, as in kepler_newton; at least two
-// steps), at most 40 steps; the loop condition is taken over the whole
-// wavefront.
+// 2^-30 |x| (converged to rounding, as in kepler_newton; the wavefront runs
+// two steps at the least), at most 40 steps.
 TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
                              double& x, double& y, double& z,
                              double& vx, double& vy, double& vz) {
@@ -197,13 +203,8 @@ TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
   double s, c;
   const bool idle = !(lane_on && bound);
   xk = idle ? 0.0 : xk;   // idle lanes iterate at 0, inside the short sin/cos path
-  if (__all(idle || short_args(dM, w))) {
-    xk = planet_newton<true>(ec, es, dM, idle, xk);
-    sincos_poly(xk, s, c);
-  } else {
-    xk = planet_newton<false>(ec, es, dM, idle, xk);
-    sincos(xk, s, c);
-  }
+  if (__all(idle || short_args(dM, w))) xk = kepler_newton<true>(ec, es, dM, 40, idle, xk, s, c);
+  else xk = kepler_newton<false>(ec, es, dM, 40, idle, xk, s, c);
   double Fp = fma_(-ec, c, fma_(es, s, 1.0));
   double cm1 = c - 1.0;
   double r1 = a * Fp;
