@@ -195,7 +195,7 @@ TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
   double dte = (q == 0.0) ? dt : dMr * ninv;
   dM = dMr;
   double om = 1.0 - ec;
-  double oinv = rcp(om);
+  double oinv = rcp_newton(om);   // a first guess only: one refinement is enough
   double t = dM * oinv;
   double xk = t * fma_(-0.5 * es * t, oinv, 1.0);
   double w = 2.0 * (__builtin_fabs(ec) + __builtin_fabs(es));

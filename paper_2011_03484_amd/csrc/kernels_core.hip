@@ -548,16 +548,18 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
     rows[3 * NP + 0] = -ax; rows[3 * NP + 1] = -ay; rows[3 * NP + 2] = -az;
   }
   const double h = 0.5 * dt;
-  // Per lane, the first event as a key ordered in time: a close pair seen at
-  // step t has key 2t+1; an orbit found unbound while drifting from t-1 to t
-  // has key 2t, so it wins a tie with a close pair at t (it is found first).
-  int64_t first_ev = INT64_MAX;
-  if (NP > 1 && hill_violation<NP>(W, ox, oy, oz, hx, hy, hz)) first_ev = 2 * step0 + 1;
+  // Per lane, the first event as a key ordered in time, counted from step0: a
+  // close pair seen at step step0 + t has key 2t+1; an orbit found unbound
+  // while drifting from step0 + t - 1 to step0 + t has key 2t, so it wins a tie
+  // with a close pair at that step (it is found first).  Keys grow with t, so
+  // the first event is the smallest key.
+  uint32_t first_ev = UINT32_MAX;
+  if (NP > 1 && hill_violation<NP>(W, ox, oy, oz, hx, hy, hz)) first_ev = 1u;
   for (int s = 0; s < nsteps; ++s) {
     wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
     bool bound = drift_converged(L.K, dt, L.body, jx, jy, jz, wx, wy, wz);
-    const int64_t t1 = step0 + s + 1;
-    first_ev = (first_ev == INT64_MAX && L.body && !bound) ? 2 * t1 : first_ev;
+    const uint32_t k1 = 2u * (uint32_t)(s + 1);
+    first_ev = __builtin_elementwise_min(first_ev, (L.body && !bound) ? k1 : UINT32_MAX);
     helio_step<NP>(E, W, jx, jy, jz, hx, hy, hz, ox, oy, oz);
     eph_accel<NP>(E, L, W, jx, jy, jz, hx, hy, hz, ox, oy, oz, ax, ay, az);
     wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
@@ -571,7 +573,7 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
     }
     if (NP > 1) {
       bool bad = hill_violation<NP>(W, ox, oy, oz, hx, hy, hz);
-      first_ev = (first_ev == INT64_MAX && bad) ? 2 * t1 + 1 : first_ev;
+      first_ev = __builtin_elementwise_min(first_ev, bad ? k1 + 1u : UINT32_MAX);
     }
   }
   if (L.body) {
@@ -579,13 +581,14 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
     vj[3 * (L.lane - 1) + 0] = wx; vj[3 * (L.lane - 1) + 1] = wy; vj[3 * (L.lane - 1) + 2] = wz;
   }
   // earliest event over the wavefront: unbound -> -2, a close pair -> its step
-  int64_t ev = first_ev;
+  uint32_t ev = first_ev;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
-    int64_t o = __shfl_xor(ev, off, 64);
+    uint32_t o = __shfl_xor(ev, off, 64);
     ev = o < ev ? o : ev;
   }
-  if (L.lane == 0 && *flag == -1 && ev != INT64_MAX) *flag = (ev & 1) ? (ev >> 1) : -2;
+  if (L.lane == 0 && *flag == -1 && ev != UINT32_MAX)
+    *flag = (ev & 1u) ? step0 + (int64_t)(ev >> 1) : -2;
 }
 
 template <int NP>
@@ -621,10 +624,14 @@ ephemeris_batch(const EphConst* __restrict__ E, double* __restrict__ rj, double*
   }
 }
 
+// The planet map's event keys count the steps of one launch in 32 bits.
+constexpr int MAX_EPH_STEPS = 1 << 30;
+
 hipError_t launch_ephemeris_batch(const EphConst* E, double* rj, double* vj, double* ring,
                                   const int64_t* ring_off, int slot, int64_t slot_stride_rows,
                                   int nsys, int nsteps, const double* dt, int64_t step0,
                                   int64_t* flag, hipStream_t st) {
+  if (nsteps < 0 || nsteps > MAX_EPH_STEPS) return hipErrorInvalidValue;
   if (nsys <= 0) return hipSuccess;
   hipLaunchKernelGGL(ephemeris_batch, dim3(nsys), dim3(64), 0, st, E, rj, vj, ring, ring_off, slot,
                      slot_stride_rows, nsteps, dt, step0, flag);
@@ -642,6 +649,7 @@ static hipError_t eph_np(const EphConst& E, double* rj, double* vj, double* rows
 hipError_t launch_ephemeris_chunk(const EphConst& E, double* rj, double* vj, double* rows,
                                   int nsteps, double dt, int64_t step0, int64_t* flag,
                                   hipStream_t st) {
+  if (nsteps < 0 || nsteps > MAX_EPH_STEPS) return hipErrorInvalidValue;
   switch (E.np) {
     case 0: return eph_np<0>(E, rj, vj, rows, nsteps, dt, step0, flag, st);
     case 1: return eph_np<1>(E, rj, vj, rows, nsteps, dt, step0, flag, st);
