@@ -213,6 +213,12 @@ int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_t* planet_o
 /* ---- unit entry points of the device math (host arrays) -------------------- */
 /* sin and cos of x[n] by the library's branch-free FP64 routine. */
 int tpm_debug_sincos(int64_t n, const double* x, double* s, double* c);
+/* The library's FP64 reciprocal square root and its relatives, for x[n]
+ * finite and > 0 (else TPM_EINVAL): out[5 i + k] holds, for k = 0..4,
+ * 1/sqrt(x), sqrt(x), 1/x, x^(-3/2) and x^(-3/2) to about 2^-45 (the
+ * perturbation kick's factor).  out holds 5 n doubles; both arrays are host
+ * memory owned by the caller. */
+int tpm_debug_rsqrt(int64_t n, const double* x, double* out);
 /* One fixed-iteration Kepler drift about mu of each rv[n][6] (x, y, z, vx, vy,
  * vz) by dt; ok[n] = 0 where the drift was refused (TPM_KEPLER rule). */
 int tpm_debug_drift(double mu, int64_t n, const double* rv_in, double* rv_out, int32_t* ok,

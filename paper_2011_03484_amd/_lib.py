@@ -71,6 +71,7 @@ SIGNATURES = {
     "tpm_planet_table": (C.c_int, [_P, C.c_int64, C.c_double, _P]),
     "tpm_set_planet_table": (C.c_int, [_P, _P, C.c_int64]),
     "tpm_debug_sincos": (C.c_int, [C.c_int64, _P, _P, _P]),
+    "tpm_debug_rsqrt": (C.c_int, [C.c_int64, _P, _P]),
     "tpm_debug_drift": (C.c_int, [C.c_double, C.c_int64, _P, _P, _P, C.c_double, C.c_int32,
                                   C.c_double]),
     "tpm_ad_forward": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int64, C.c_double, C.c_int32, _P, _P,

@@ -141,6 +141,7 @@ hipError_t launch_particle_batch(const SysDev* sys, const TileDesc* tiles, Work 
 
 // Unit checks of the device math (test entry points).
 hipError_t launch_sincos_test(const double* x, double* s, double* c, int n, hipStream_t st);
+hipError_t launch_rsqrt_test(const double* x, double* out, int n, hipStream_t st);
 hipError_t launch_drift_test(const SysConst& S, const double* rv_in, double* rv_out, int32_t* ok,
                              int n, double dt, hipStream_t st);
 

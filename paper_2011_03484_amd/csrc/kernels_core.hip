@@ -385,6 +385,8 @@ struct EphLane {
   int lane;
   bool body;
   double mup, ie_prev;            // mu'_b, 1/eta_{b-1} (0 on lanes that hold no body)
+  double kc;                      // coefficient of the kick's Kepler term (see eph_accel)
+  double cw;                      // weight of the central term in the lane's own kick
   double nb;                      // 0 on body lanes, 1 elsewhere (keeps an rsqrt finite)
   KepConst K;                     // Kepler constant mu'_b for the drift
 };
@@ -460,23 +462,32 @@ TPM_DEV void helio_step(const EphConst& E, const EphW<NP>& W, double jx, double 
 // Interaction acceleration of the lane's Jacobi body (lanes 1..NP):
 //   a'_b = a_b - (sum_{k<b} mu_k a_k)/eta_{b-1} + mu'_b r'_b/|r'_b|^3,
 // with a_k the Newtonian acceleration of body k; lane 0 gets a_0 (h0 = -a_0).
-// (ox, oy, oz) is the lane's own heliocentric position.
+// (ox, oy, oz) is the lane's own heliocentric position.  For the innermost
+// body the heliocentric and Jacobi vectors are the same (bit for bit), so its
+// central term -mu_0 r/|r|^3 and the Kepler term combine into
+// (mu'_1 - mu_0) r/|r|^3: kc holds that difference (exact in floating point,
+// the two coefficients being within a factor two) and cw = 0 drops the
+// central term from the lane's own sum.  The two terms would otherwise cancel
+// to about mu_1/mu_0 of their size and amplify their rounding by mu_0/mu_1.
+// The broadcast a_1 keeps its central term.
 template <int NP>
 TPM_DEV void eph_accel(const EphConst& E, const EphLane& L, const EphW<NP>& W, double jx,
                        double jy, double jz, const double (&hx)[NP + 1],
                        const double (&hy)[NP + 1], const double (&hz)[NP + 1], double ox,
                        double oy, double oz, double& ax, double& ay, double& az) {
-  double nx = 0.0, ny = 0.0, nz = 0.0;
+  // the planets' pulls (l >= 1), then the central body's (l = 0, at the origin)
+  double px = 0.0, py = 0.0, pz = 0.0;
 #pragma unroll
-  for (int l = 0; l <= NP; ++l) {
+  for (int l = 1; l <= NP; ++l) {
     double dx = ox - hx[l], dy = oy - hy[l], dz = oz - hz[l];
     double d2 = fma_(dx, dx, fma_(dy, dy, dz * dz));
-    double inv = rsqrt(d2 + W.self[l]);
-    double k = W.mul[l] * (inv * inv) * inv;
-    nx = fma_(-k, dx, nx);
-    ny = fma_(-k, dy, ny);
-    nz = fma_(-k, dz, nz);
+    double k = mul_rsqrt3(W.mul[l], d2 + W.self[l]);
+    px = fma_(-k, dx, px);
+    py = fma_(-k, dy, py);
+    pz = fma_(-k, dz, pz);
   }
+  const double k0 = mul_rsqrt3(W.mul[0], fma_(ox, ox, fma_(oy, oy, oz * oz)) + W.self[0]);
+  const double nx = fma_(-k0, ox, px), ny = fma_(-k0, oy, py), nz = fma_(-k0, oz, pz);
   // sum_{k<b} mu_k a_k from the broadcast Newtonian accelerations
   double sx = 0.0, sy = 0.0, sz = 0.0;
 #pragma unroll
@@ -486,12 +497,12 @@ TPM_DEV void eph_accel(const EphConst& E, const EphLane& L, const EphW<NP>& W, d
     sz = fma_(W.wa[k], bcast(nz, k), sz);
   }
   double r2 = fma_(jx, jx, fma_(jy, jy, jz * jz));
-  double inv = rsqrt(r2 + L.nb);
-  double kk = L.mup * (inv * inv) * inv;
+  double kk = mul_rsqrt3(L.kc, r2 + L.nb);
+  const double kw = k0 * L.cw;
   // lane 0: jx = ie_prev = 0, so a = n
-  ax = fma_(kk, jx, fma_(-sx, L.ie_prev, nx));
-  ay = fma_(kk, jy, fma_(-sy, L.ie_prev, ny));
-  az = fma_(kk, jz, fma_(-sz, L.ie_prev, nz));
+  ax = fma_(kk, jx, fma_(-sx, L.ie_prev, fma_(-kw, ox, px)));
+  ay = fma_(kk, jy, fma_(-sy, L.ie_prev, fma_(-kw, oy, py)));
+  az = fma_(kk, jz, fma_(-sz, L.ie_prev, fma_(-kw, oz, pz)));
 }
 
 // Any pair (lane, j > lane) closer than their mutual Hill radius.
@@ -524,6 +535,12 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
 #pragma unroll
   for (int b = 1; b <= NP; ++b)
     if (L.lane == b) { L.mup = E.mup[b]; L.ie_prev = E.inv_eta[b - 1]; }
+  L.kc = L.mup;
+  L.cw = 1.0;
+  if (NP >= 1 && L.lane == 1) {
+    L.kc = E.mup[1] - E.mu[0];
+    L.cw = 0.0;
+  }
   const EphW<NP> W = eph_weights<NP>(E, L.lane);
   {
     double smu, rsmu;
@@ -950,6 +967,26 @@ __global__ void sincos_test_kernel(const double* x, double* s, double* c, int n)
 hipError_t launch_sincos_test(const double* x, double* s, double* c, int n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(sincos_test_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, s, c, n);
+  return hipGetLastError();
+}
+
+// Per argument: rsqrt, sqrt (sqrt_rsqrt), rcp, mul_rsqrt3(1, x), mul_rsqrt3_1(1, x).
+__global__ void rsqrt_test_kernel(const double* x, double* out, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = x[i];
+  double sq, rs;
+  sqrt_rsqrt(v, sq, rs);
+  out[5 * (size_t)i + 0] = rsqrt(v);
+  out[5 * (size_t)i + 1] = sq;
+  out[5 * (size_t)i + 2] = rcp(v);
+  out[5 * (size_t)i + 3] = mul_rsqrt3(1.0, v);
+  out[5 * (size_t)i + 4] = mul_rsqrt3_1(1.0, v);
+}
+
+hipError_t launch_rsqrt_test(const double* x, double* out, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rsqrt_test_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, out, n);
   return hipGetLastError();
 }
 

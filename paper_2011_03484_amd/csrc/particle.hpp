@@ -54,9 +54,8 @@ TPM_DEV int accel(const RowT& row, const PlanetConst<NP>& P,
     double dz = z - row[3 * j + 2];
     double d2 = fma_(dx, dx, fma_(dy, dy, dz * dz));
     d2s[j] = d2;
-    // the kick is a perturbation (|a| << mu0/r^2): 2^-46 relative is ample
-    double inv = rsqrt1(d2);
-    double k = P.mu[j] * (inv * inv) * inv;
+    // the kick is a perturbation (|a| << mu0/r^2): 2^-45 relative is ample
+    double k = mul_rsqrt3_1(P.mu[j], d2);
     ax = fma_(-k, dx, ax);
     ay = fma_(-k, dy, ay);
     az = fma_(-k, dz, az);

@@ -852,6 +852,24 @@ int tpm_debug_sincos(int64_t n, const double* x, double* s_out, double* c_out) {
   return TPM_OK;
 }
 
+int tpm_debug_rsqrt(int64_t n, const double* x, double* out) {
+  if (n < 0 || n >= (int64_t(1) << 31) || (n && (!x || !out)))
+    return fail(TPM_EINVAL, "bad arguments");
+  for (int64_t i = 0; i < n; ++i)
+    if (!(x[i] > 0.0) || !std::isfinite(x[i])) return fail(TPM_EINVAL, "arguments must be finite and > 0");
+  if (n == 0) return TPM_OK;
+  double *dx = nullptr, *dout = nullptr;
+  hipError_t e = hipMalloc(&dx, n * 8);
+  if (e == hipSuccess) e = hipMalloc(&dout, n * 5 * 8);
+  if (e == hipSuccess) e = hipMemcpy(dx, x, n * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_rsqrt_test(dx, dout, (int)n, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(out, dout, n * 5 * 8, hipMemcpyDeviceToHost);
+  dfree(dx); dfree(dout);
+  TPM_HIP(e);
+  return TPM_OK;
+}
+
 int tpm_debug_drift(double mu, int64_t n, const double* rv_in, double* rv_out, int32_t* ok,
                     double dt, int32_t kepler_iters, double kepler_ftol) {
   if (n < 0 || n >= (int64_t(1) << 31) || (n && (!rv_in || !rv_out || !ok)))
