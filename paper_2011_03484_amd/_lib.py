@@ -92,6 +92,11 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2011_03484_amd.build` (no CPU fallback exists)")
+        # torch bundles a HIP runtime with the same soname as the system one the
+        # library links; loading torch first makes both use that one copy (a
+        # second copy loaded after the library's leaves the library without a
+        # device)
+        import torch  # noqa: F401
         lib = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(lib, name)
@@ -222,6 +227,14 @@ def debug_sincos(x):
     s, c = np.zeros_like(x), np.zeros_like(x)
     _check(load().tpm_debug_sincos(x.shape[0], _p(x), _p(s), _p(c)))
     return s, c
+
+
+def debug_rsqrt(x):
+    """Columns: 1/sqrt(x), sqrt(x), 1/x, x^-1.5, x^-1.5 (first-order factor)."""
+    x = _f64(x, (-1,))
+    out = np.zeros((x.shape[0], 5))
+    _check(load().tpm_debug_rsqrt(x.shape[0], _p(x), _p(out)))
+    return out
 
 
 def debug_drift(mu, r, v, dt, kepler_iters=5, kepler_ftol=0.0):
