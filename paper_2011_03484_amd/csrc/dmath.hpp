@@ -33,6 +33,13 @@ namespace tpm {
 
 TPM_DEV double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// True when p holds on every active lane: the ballot of p is the lane mask a
+// vector compare already produced, so the test is a scalar compare against
+// exec (no round trip of the predicate through a vector register).
+TPM_DEV bool wave_all(bool p) {
+  return __builtin_amdgcn_ballot_w64(p) == __builtin_amdgcn_read_exec();
+}
+
 // 1/x to rounding: y (1 + e + e^2), e = 1 - x y.
 TPM_DEV double rcp(double x) {
   double y = __builtin_amdgcn_rcp(x);
@@ -138,7 +145,7 @@ TPM_DEV void sincos_poly(double r, double& s, double& c) {
 // same (the full path would only turn a -0 input into +0).  The only branch is
 // that wave-uniform one.
 TPM_DEV void sincos(double x, double& s, double& c) {
-  if (__all(__builtin_fabs(x) <= 0.78)) {
+  if (wave_all(__builtin_fabs(x) <= 0.78)) {
     sincos_poly(x, s, c);
     return;
   }

@@ -76,7 +76,7 @@ TPM_DEV double kepler_newton(double ec, double es, double dM, int kiters, bool d
   s = 0.0;
   c = 1.0;
   for (int it = 0; it < kiters; ++it) {
-    if (it >= 2 && __all(done)) {
+    if (it >= 2 && wave_all(done)) {
       converged = true;
       break;
     }
@@ -91,7 +91,7 @@ TPM_DEV double kepler_newton(double ec, double es, double dM, int kiters, bool d
     s = done ? s : sn;
     c = done ? c : cn;
     xk = done ? xk : xn;
-    done = done || small;
+    done = done | small;
   }
   if (!converged) {
     double sf, cf;
@@ -203,7 +203,7 @@ TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
   double s, c;
   const bool idle = !(lane_on && bound);
   xk = idle ? 0.0 : xk;   // idle lanes iterate at 0, inside the short sin/cos path
-  if (__all(idle || short_args(dM, w))) xk = kepler_newton<true>(ec, es, dM, 40, idle, xk, s, c);
+  if (wave_all(idle | short_args(dM, w))) xk = kepler_newton<true>(ec, es, dM, 40, idle, xk, s, c);
   else xk = kepler_newton<false>(ec, es, dM, 40, idle, xk, s, c);
   double Fp = fma_(-ec, c, fma_(es, s, 1.0));
   double cm1 = c - 1.0;

@@ -84,7 +84,7 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
   // leave once every lane is removed (checked every 8 steps: the check itself
   // costs a vector-to-scalar round trip)
   auto all_removed = [&](int s) {
-    return ((s - s_begin) & 7) == 0 && __all(reason != ST_ACTIVE);
+    return ((s - s_begin) & 7) == 0 && wave_all(reason != ST_ACTIVE);
   };
   if (PREFETCH) {
     // The row that ends step s is fetched during step s - 1, into the one of

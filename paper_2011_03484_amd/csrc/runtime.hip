@@ -83,6 +83,7 @@ hipError_t ensure_device_streams(DeviceStreams& D) {
 }
 
 constexpr int NSLOT = 8;   // planet-table ring slots
+constexpr int FIRST_CHUNK_STEPS = 1024;   // longest first chunk of an on-the-fly run
 constexpr int NCNT = 8;    // in-flight active-count readbacks
 
 template <class T>
@@ -574,7 +575,13 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   const int K = s->opt.chunk_steps;
   const int R = s->opt.resync_chunks;
   const int rl = 3 * s->np + 3;
-  const int64_t nchunks = (nsteps + K - 1) / K;
+  // The particles wait for the whole first chunk of the planet map before
+  // they start, so when the map runs on the fly the first chunk is short;
+  // chunk c covers steps [begin(c), begin(c + 1)) of this call.
+  const int K0 = s->d_table ? K : std::min(K, FIRST_CHUNK_STEPS);
+  auto begin = [K, K0](int64_t c) -> int64_t { return c == 0 ? 0 : K0 + (c - 1) * (int64_t)K; };
+  auto length = [&](int64_t c) -> int { return (int)(std::min(begin(c + 1), nsteps) - begin(c)); };
+  const int64_t nchunks = nsteps == 0 ? 0 : nsteps <= K0 ? 1 : 1 + (nsteps - K0 + K - 1) / K;
   if (!s->d_table) {
     int rc = ensure_ring(s, (int64_t)K + 1);
     if (rc) return rc;
@@ -600,11 +607,11 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   auto enqueue_eph = [&](int64_t upto) -> int {
     for (; eph_next <= upto && eph_next < nchunks; ++eph_next) {
       const int64_t c = eph_next;
-      const int ks = (int)std::min<int64_t>(K, nsteps - c * K);
+      const int ks = length(c);
       const int slot = (int)(c % NSLOT);
       double* srow = s->d_ring + (size_t)slot * s->ring_rows * rl;
       TPM_HIP(hipStreamWaitEvent(s->sE, s->ev_done[slot], 0));
-      TPM_HIP(launch_ephemeris_chunk(E, s->d_rj, s->d_vj, srow, ks, dt, s->step + c * K,
+      TPM_HIP(launch_ephemeris_chunk(E, s->d_rj, s->d_vj, srow, ks, dt, s->step + begin(c),
                                      s->d_flag, s->sE));
       TPM_HIP(hipEventRecord(s->ev_eph[slot], s->sE));
     }
@@ -626,9 +633,9 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   };
   int n_grid = s->n_active;
   for (int64_t c = 0; c < nchunks; ++c) {
-    const int ks = (int)std::min<int64_t>(K, nsteps - c * K);
+    const int ks = length(c);
     const int slot = (int)(c % NSLOT);
-    const int64_t step0 = s->step + c * K;
+    const int64_t step0 = s->step + begin(c);
     const double* rows;
     if (s->d_table) {
       rows = s->d_table + (size_t)step0 * rl;
