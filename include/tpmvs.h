@@ -63,10 +63,15 @@ enum {
 
 typedef struct {
   int32_t kepler_iters;   /* fixed Newton iterations per drift (sec. 2.2: five); default 5 */
-  int32_t chunk_steps;    /* steps per particle launch ("planetary chunk", sec. 2.2); 0 = 8192 */
+  int32_t chunk_steps;    /* steps per particle launch ("planetary chunk", sec. 2.2); 0 = 8192.
+                             When the planet map runs alongside the particles (no table
+                             supplied), the first launch of each integrate call covers at
+                             most 1,024 steps: the particles wait for its whole planet chunk */
   int32_t resync_chunks;  /* chunks between compactions ("resync interval", sec. 2.2); 0 = 1 */
   int32_t block_threads;  /* particle-kernel workgroup size (64..256, multiple of 64); 0 = 64 */
-  int32_t sub_chunks;     /* work items per tile and chunk (dynamic load balance); 0 = 64 */
+  int32_t sub_chunks;     /* work items per tile in a full chunk (dynamic load balance); a
+                             shorter chunk gets proportionally fewer items of the same
+                             length; 0 = 64 */
   int32_t waves_per_simd; /* particle wavefronts launched per SIMD (upper bound); 0 = 2 */
   double r_escape;        /* remove when |r| > r_escape; <= 0 disables                */
   double kepler_ftol;     /* Kepler-failure threshold on |F(x_k)|; 0 = 1e-13         */

@@ -658,7 +658,10 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
       QL.base = s->q_base;
       QL.progress = s->d_progress;
       QL.epoch = s->q_epoch;
-      QL.nsub = std::max(1, std::min(s->opt.sub_chunks, ks));
+      // items keep the length of a full chunk's (K / sub_chunks steps): a short
+      // chunk gets fewer items, not shorter ones
+      const int item = std::max(1, K / std::max(1, s->opt.sub_chunks));
+      QL.nsub = std::max(1, std::min(s->opt.sub_chunks, (ks + item - 1) / item));
       const int ntiles = (n_grid + 63) / 64;
       QL.workers = std::max(1, std::min(ntiles * QL.nsub, 4 * s->ncu * s->opt.waves_per_simd));
       QL.workers = std::min(QL.workers, ntiles);
