@@ -64,6 +64,21 @@ def counter_figures():
     return d if d.get("source_hash") == kernel_source_hash() else None
 
 
+# the library's defaults (include/tpmvs.h): chunk length, first-chunk cap when
+# the planet map runs alongside, work items per tile and chunk
+DEFAULT_CHUNK_STEPS, FIRST_CHUNK_STEPS, DEFAULT_SUB_CHUNKS = 8192, 1024, 64
+
+
+def default_chunks(nsteps: int) -> list:
+    """Chunk lengths of an on-the-fly run of nsteps with the default options."""
+    out, done = [], 0
+    while done < nsteps:
+        k = min(FIRST_CHUNK_STEPS if not out else DEFAULT_CHUNK_STEPS, nsteps - done)
+        out.append(k)
+        done += k
+    return out
+
+
 def summarize_counters(pmc_dir: str) -> None:
     """Write the counter summary (markdown) and its per-particle-step figures
     (json) from the four rocprofv3 --pmc passes under pmc_dir/p1..p4, each made
@@ -113,6 +128,10 @@ def summarize_counters(pmc_dir: str) -> None:
     per = lambda c: 64 * g("p1", c) / aps
     fpps = per("SQ_INSTS_VALU_FLOPS_FP64")
     steps = int(PMC_BENCH_ARGS.split()[1])
+    chunks = default_chunks(steps)
+    item = DEFAULT_CHUNK_STEPS // DEFAULT_SUB_CHUNKS
+    items = [-(-k // item) for k in chunks]
+    alg_b = 100.0 * sum(items) / steps
     out = [f"# particle_queue<4,5> counters -- giants_100k, 100,000 particles x {steps:,} steps "
            f"({launches} launches)", "",
            "Commands (one rocprofv3 run per pass, `cd /tmp && export TMPDIR=/tmp` first), then "
@@ -148,10 +167,11 @@ def summarize_counters(pmc_dir: str) -> None:
             f"WRITE_SIZE {g('p4', 'WRITE_SIZE', 'device copy 256 MiB'):.0f} KiB (factor {write_f:.4f}).",
             f"* HBM traffic per launch, calibrated: fetch {fetch_b / 1e6:.2f} MB + write "
             f"{write_b / 1e6:.2f} MB = {(fetch_b + write_b) / 1e6:.2f} MB for {aps / launches:,.0f} "
-            f"active particle-steps, i.e. {bpps:.4f} B per particle-step (algorithmic: 52 B in + 48 B "
-            f"out per particle per 64-step work item, the default 16 items per 1,024-step chunk, "
-            f"= 1.56 B), "
-            f"{(fetch_b + write_b) / (kt / kn) / 1e9:.0f} GB/s."]
+            f"active particle-steps, i.e. {bpps:.4f} B per particle-step (algorithmic: each "
+            f"particle's state, 52 B in and 48 B out, moves once per work item of {item} steps; with the "
+            f"library's default layout this run has chunks of {', '.join(f'{k:,}' for k in chunks)} "
+            f"steps with {', '.join(str(i) for i in items)} items, so 100 B x {sum(items)} / "
+            f"{steps:,} = {alg_b:.3f} B), {(fetch_b + write_b) / (kt / kn) / 1e9:.0f} GB/s."]
     open(COUNTERS_MD, "w").write("\n".join(out) + "\n")
     json.dump({"kernel": pq, "workload": f"giants_100k, 100,000 particles x {steps} steps",
                "source_hash": src, "flops_per_particle_step": fpps,
