@@ -92,6 +92,25 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+// Device buffers of one call, freed when the holder goes out of scope (also
+// on the early error returns of TPM_HIP).
+struct DevScope {
+  std::vector<void*> held;
+  template <class T>
+  hipError_t alloc(T*& out, size_t bytes) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e == hipSuccess) {
+      held.push_back(q);
+      out = static_cast<T*>(q);
+    }
+    return e;
+  }
+  ~DevScope() {
+    for (void* q : held) (void)hipFree(q);
+  }
+};
+
 bool finite_all(const double* p, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(p[i])) return false;
@@ -346,6 +365,7 @@ int tpm_create(const tpm_options* opt, tpm_sim** out) {
   if (o.waves_per_simd == 0) o.waves_per_simd = 2;
   if (o.waves_per_simd > 8) return fail(TPM_EINVAL, "waves_per_simd > 8");
   if (o.chunk_steps == 0) o.chunk_steps = 8192;
+  if (o.chunk_steps > (1 << 30)) return fail(TPM_EINVAL, "chunk_steps > 2^30");
   if (o.resync_chunks == 0) o.resync_chunks = 1;
   if (o.block_threads == 0) o.block_threads = 64;
   if (o.block_threads % 64 || o.block_threads > 256)
@@ -817,10 +837,11 @@ int tpm_planet_table(tpm_sim* s, int64_t nsteps, double dt, double* table) {
   int64_t* flag = nullptr;
   size_t b = sizeof(double) * 3 * std::max(np, 1);
   TPM_HIP(hipStreamSynchronize(s->sE));
-  TPM_HIP(hipMalloc(&rj, b));
-  TPM_HIP(hipMalloc(&vj, b));
-  TPM_HIP(hipMalloc(&flag, sizeof(int64_t)));
-  TPM_HIP(hipMalloc(&rows, sizeof(double) * (nsteps + 1) * rl));
+  DevScope mem;
+  TPM_HIP(mem.alloc(rj, b));
+  TPM_HIP(mem.alloc(vj, b));
+  TPM_HIP(mem.alloc(flag, sizeof(int64_t)));
+  TPM_HIP(mem.alloc(rows, sizeof(double) * (nsteps + 1) * rl));
   TPM_HIP(hipMemcpy(rj, s->d_rj, b, hipMemcpyDeviceToDevice));
   TPM_HIP(hipMemcpy(vj, s->d_vj, b, hipMemcpyDeviceToDevice));
   int64_t m1 = -1;
@@ -838,7 +859,6 @@ int tpm_planet_table(tpm_sim* s, int64_t nsteps, double dt, double* table) {
   TPM_HIP(hipMemcpy(t.data(), rows, sizeof(double) * t.size(), hipMemcpyDeviceToHost));
   int64_t f = -1;
   TPM_HIP(hipMemcpy(&f, flag, sizeof(f), hipMemcpyDeviceToHost));
-  dfree(rj); dfree(vj); dfree(rows); dfree(flag);
   permute_table(s, t.data(), table, nsteps + 1, true);
   if (f == -2) return fail(TPM_EPLANET, "a planet orbit became unbound");
   if (f >= 0) return fail(TPM_EPLANET, "two planets came within a mutual Hill radius");
@@ -850,15 +870,15 @@ int tpm_debug_sincos(int64_t n, const double* x, double* s_out, double* c_out) {
     return fail(TPM_EINVAL, "bad arguments");
   if (n == 0) return TPM_OK;
   double *dx, *ds, *dc;
-  TPM_HIP(hipMalloc(&dx, n * 8));
-  TPM_HIP(hipMalloc(&ds, n * 8));
-  TPM_HIP(hipMalloc(&dc, n * 8));
+  DevScope mem;
+  TPM_HIP(mem.alloc(dx, n * 8));
+  TPM_HIP(mem.alloc(ds, n * 8));
+  TPM_HIP(mem.alloc(dc, n * 8));
   TPM_HIP(hipMemcpy(dx, x, n * 8, hipMemcpyHostToDevice));
   TPM_HIP(launch_sincos_test(dx, ds, dc, (int)n, nullptr));
   TPM_HIP(hipDeviceSynchronize());
   TPM_HIP(hipMemcpy(s_out, ds, n * 8, hipMemcpyDeviceToHost));
   TPM_HIP(hipMemcpy(c_out, dc, n * 8, hipMemcpyDeviceToHost));
-  dfree(dx); dfree(ds); dfree(dc);
   return TPM_OK;
 }
 
@@ -868,15 +888,14 @@ int tpm_debug_rsqrt(int64_t n, const double* x, double* out) {
   for (int64_t i = 0; i < n; ++i)
     if (!(x[i] > 0.0) || !std::isfinite(x[i])) return fail(TPM_EINVAL, "arguments must be finite and > 0");
   if (n == 0) return TPM_OK;
-  double *dx = nullptr, *dout = nullptr;
-  hipError_t e = hipMalloc(&dx, n * 8);
-  if (e == hipSuccess) e = hipMalloc(&dout, n * 5 * 8);
-  if (e == hipSuccess) e = hipMemcpy(dx, x, n * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_rsqrt_test(dx, dout, (int)n, nullptr);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipMemcpy(out, dout, n * 5 * 8, hipMemcpyDeviceToHost);
-  dfree(dx); dfree(dout);
-  TPM_HIP(e);
+  double *dx, *dout;
+  DevScope mem;
+  TPM_HIP(mem.alloc(dx, n * 8));
+  TPM_HIP(mem.alloc(dout, n * 5 * 8));
+  TPM_HIP(hipMemcpy(dx, x, n * 8, hipMemcpyHostToDevice));
+  TPM_HIP(launch_rsqrt_test(dx, dout, (int)n, nullptr));
+  TPM_HIP(hipDeviceSynchronize());
+  TPM_HIP(hipMemcpy(out, dout, n * 5 * 8, hipMemcpyDeviceToHost));
   return TPM_OK;
 }
 
@@ -896,15 +915,15 @@ int tpm_debug_drift(double mu, int64_t n, const double* rv_in, double* rv_out, i
   S.ftol = kepler_ftol > 0 ? kepler_ftol : 1e-13;
   double *di, *dout;
   int32_t* dok;
-  TPM_HIP(hipMalloc(&di, n * 48));
-  TPM_HIP(hipMalloc(&dout, n * 48));
-  TPM_HIP(hipMalloc(&dok, n * 4));
+  DevScope mem;
+  TPM_HIP(mem.alloc(di, n * 48));
+  TPM_HIP(mem.alloc(dout, n * 48));
+  TPM_HIP(mem.alloc(dok, n * 4));
   TPM_HIP(hipMemcpy(di, rv_in, n * 48, hipMemcpyHostToDevice));
   TPM_HIP(launch_drift_test(S, di, dout, dok, (int)n, dt, nullptr));
   TPM_HIP(hipDeviceSynchronize());
   TPM_HIP(hipMemcpy(rv_out, dout, n * 48, hipMemcpyDeviceToHost));
   TPM_HIP(hipMemcpy(ok, dok, n * 4, hipMemcpyDeviceToHost));
-  dfree(di); dfree(dout); dfree(dok);
   return TPM_OK;
 }
 
@@ -1143,6 +1162,7 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
   if (opt_in) o = *opt_in;
   if (o.kepler_iters <= 0) o.kepler_iters = 5;
   if (o.chunk_steps <= 0) o.chunk_steps = 1024;
+  if (o.chunk_steps > (1 << 30)) return fail(TPM_EINVAL, "chunk_steps > 2^30");
   if (o.block_threads <= 0) o.block_threads = 64;
   if (o.block_threads % 64 || o.block_threads > 256) return fail(TPM_EINVAL, "bad block_threads");
   if (!(o.kepler_ftol > 0.0)) o.kepler_ftol = 1e-13;

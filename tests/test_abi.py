@@ -51,3 +51,19 @@ def test_create_without_gpu_reports_device_error():
     with pytest.raises(_lib.TpmError) as e:
         _lib.Simulation()
     assert e.value.code == _lib.TPM_EDEVICE
+
+
+def test_invalid_arguments_refused_before_device_work():
+    """Argument checks come first: these calls fail with TPM_EINVAL on any
+    machine, GPU or not, without touching the device."""
+    from paper_2011_03484_amd import _lib
+    for bad in ([1.0, 0.0], [-1.0], [float("nan")], [float("inf")]):
+        with pytest.raises(_lib.TpmError) as e:
+            _lib.debug_rsqrt(bad)
+        assert e.value.code == _lib.TPM_EINVAL, bad
+    with pytest.raises(_lib.TpmError) as e:
+        _lib.Simulation(chunk_steps=(1 << 30) + 1)
+    assert e.value.code == _lib.TPM_EINVAL
+    with pytest.raises(_lib.TpmError) as e:
+        _lib.Simulation(waves_per_simd=9)
+    assert e.value.code == _lib.TPM_EINVAL
