@@ -18,6 +18,11 @@ FLAGS = [
     "-ffp-contract=off",
     # never emit packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FP64 FMAs as three-address v_fma_f64: the two-address v_fmac_f64
+    # overwrites its addend, so an addend that stays live (a series constant
+    # held in a VGPR, a value used again) costs a v_mov_b64 copy per FMA (the
+    # planet-map kernels turn it back on for themselves)
+    "-Xclang", "-target-feature", "-Xclang", "-fmacf64-inst",
     "-Wno-unused-result",
 ]
 

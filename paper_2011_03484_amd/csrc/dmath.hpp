@@ -139,6 +139,33 @@ TPM_DEV void sincos_poly(double r, double& s, double& c) {
   c = w + fma_(z2, pc, tail);
 }
 
+// sincos_poly by Horner's rule: fewer instructions, longer dependency chains.
+// The planet map's lone wavefront runs it faster (its time is its instruction
+// count); the particle kernels, with many wavefronts per SIMD, prefer Estrin's
+// shorter chains.  The values agree to rounding.
+TPM_DEV void sincos_poly_horner(double r, double& s, double& c) {
+  const double z = r * r;
+  double ps = fma_(S17, z, S15);
+  ps = fma_(ps, z, S13);
+  ps = fma_(ps, z, S11);
+  ps = fma_(ps, z, S9);
+  ps = fma_(ps, z, S7);
+  ps = fma_(ps, z, S5);
+  ps = fma_(ps, z, S3);
+  s = fma_(r * z, ps, r);
+  double pc = fma_(C18, z, C16);
+  pc = fma_(pc, z, C14);
+  pc = fma_(pc, z, C12);
+  pc = fma_(pc, z, C10);
+  pc = fma_(pc, z, C8);
+  pc = fma_(pc, z, C6);
+  pc = fma_(pc, z, C4);
+  const double hz = 0.5 * z;
+  const double w = 1.0 - hz;
+  const double tail = (1.0 - w) - hz;
+  c = w + fma_(z * z, pc, tail);
+}
+
 // sin(x), cos(x) for |x| up to about 2^20.  When every active lane of the
 // wavefront has |x| <= 0.78 (< pi/4, so the quadrant count is 0 and the
 // reduction leaves x unchanged) the reduction is skipped; the values are the

@@ -32,10 +32,12 @@ constexpr double INV_TWO_PI = 0x1.45f306dc9c883p-3;
 
 // sin/cos of an iterate; SHORT when every argument of the solve is known to
 // lie within +-0.78 (see short_args), so the pi/2 reduction is skipped (the
-// values are those of the full path); otherwise each call checks by itself.
+// values are those of the full path up to the polynomial's evaluation order);
+// otherwise each call checks by itself.  Only the planet map takes the SHORT
+// form, evaluated by Horner's rule (see sincos_poly_horner).
 template <bool SHORT>
 TPM_DEV void sincos_it(double x, double& s, double& c) {
-  if (SHORT) sincos_poly(x, s, c);
+  if (SHORT) sincos_poly_horner(x, s, c);
   else sincos(x, s, c);
 }
 

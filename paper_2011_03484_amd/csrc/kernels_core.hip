@@ -520,6 +520,16 @@ TPM_DEV bool hill_violation(const EphW<NP>& W, double ox, double oy, double oz,
   return bad;
 }
 
+// The planet map's kernels keep the two-address FP64 FMA (v_fmac_f64), which
+// the library's build otherwise turns off: its lone wavefront runs faster with
+// the shorter encoding, the particle kernels without the copies it costs.
+// (A device-code attribute: the host pass of the same source does not know it.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define TPM_PLANET_KERNEL __attribute__((target("fmacf64-inst")))
+#else
+#define TPM_PLANET_KERNEL
+#endif
+
 template <int NP>
 TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* __restrict__ vj,
                             double* __restrict__ rows, int nsteps, double dt, int64_t step0,
@@ -609,7 +619,7 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
 }
 
 template <int NP>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) TPM_PLANET_KERNEL
 ephemeris_chunk(EphConst E, double* __restrict__ rj, double* __restrict__ vj,
                 double* __restrict__ rows, int nsteps, double dt, int64_t step0,
                 int64_t* __restrict__ flag) {
@@ -618,7 +628,7 @@ ephemeris_chunk(EphConst E, double* __restrict__ rj, double* __restrict__ vj,
 
 // Many systems at once: workgroup b runs system b (its constants, Jacobi
 // state, table rows and flag are found through the per-system arrays).
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) TPM_PLANET_KERNEL
 ephemeris_batch(const EphConst* __restrict__ E, double* __restrict__ rj, double* __restrict__ vj,
                 double* __restrict__ ring, const int64_t* __restrict__ ring_off, int slot,
                 int64_t slot_stride_rows, int nsteps, const double* __restrict__ dt,

@@ -150,7 +150,9 @@ def test_rsqrt_family(tpm):
     rs = 1 / np.sqrt(xl)
     refs = [rs, np.sqrt(xl), 1 / xl, rs * rs * rs, rs * rs * rs]
     bars = [2 * 2.0 ** -53, 2.0 ** -52, 2.0 ** -52, 3 * 2.0 ** -53, 2.0 ** -45]
-    finite = np.all(np.isfinite(np.asarray(refs, dtype=np.float64)), axis=0) & (x > 1e-300) & (x < 1e300)
+    with np.errstate(over="ignore"):      # x^-1.5 of the tiniest arguments exceeds double range
+        finite = np.all(np.isfinite(np.asarray(refs, dtype=np.float64)), axis=0)
+    finite &= (x > 1e-300) & (x < 1e300)
     names = ["rsqrt", "sqrt", "rcp", "x^-1.5", "x^-1.5 first order"]
     for k, (ref, bar) in enumerate(zip(refs, bars)):
         rel = np.abs((out[finite, k].astype(np.longdouble) - ref[finite]) / ref[finite]).astype(np.float64)
