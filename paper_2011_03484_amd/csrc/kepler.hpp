@@ -104,6 +104,34 @@ TPM_DEV double kepler_newton(double ec, double es, double dM, int kiters, bool d
   return xk;
 }
 
+// Newton for the planet map: as kepler_newton, but no lane freezes.  The
+// planet map's wavefront always holds the same bodies in the same lanes, so
+// its results cannot depend on which lanes share it.  Every lane iterates
+// until the last step of each non-idle lane was a correction of at most
+// 2^-30 |x|, and its sin/cos come from that last step's rotation (as in
+// kepler_newton); at most 40 steps, after which sin/cos are evaluated afresh.
+// Idle lanes iterate on values that are never used.
+template <bool SHORT>
+TPM_DEV double planet_newton(double ec, double es, double dM, bool idle, double xk, double& s,
+                             double& c) {
+  bool done = idle;
+  for (int it = 0; it < 40; ++it) {
+    if (it >= 2 && wave_all(done)) return xk;
+    double sv, cv;
+    sincos_it<SHORT>(xk, sv, cv);
+    const double F = fma_(-ec, sv, fma_(es, 1.0 - cv, xk - dM));
+    const double Fp = fma_(-ec, cv, fma_(es, sv, 1.0));
+    const double xn = fma_(-F, rcp_newton(Fp), xk);
+    const double d = xk - xn;
+    done = idle | (__builtin_fabs(d) <= 0x1p-30 * __builtin_fabs(xn));
+    s = fma_(-cv, d, sv);
+    c = fma_(sv, d, cv);
+    xk = xn;
+  }
+  sincos_it<SHORT>(xk, s, c);
+  return xk;
+}
+
 // The particles' Newton solve from the starter xk, with sin/cos of its result.
 // (Each sin/cos decides its short path by itself: one copy of the loop keeps
 // the particle kernel's registers within budget.)
@@ -170,8 +198,7 @@ TPM_DEV bool drift_fixed(const KepConst& K, double dt, int kiters, double ftol,
 
 // Converged drift for the planets (a handful of lanes in one wavefront):
 // Newton until every lane has made a step whose correction is at most
-// 2^-30 |x| (converged to rounding, as in kepler_newton; the wavefront runs
-// two steps at the least), at most 40 steps.
+// 2^-30 |x| (converged to rounding; planet_newton), at most 40 steps.
 TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
                              double& x, double& y, double& z,
                              double& vx, double& vy, double& vz) {
@@ -205,8 +232,8 @@ TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
   double s, c;
   const bool idle = !(lane_on && bound);
   xk = idle ? 0.0 : xk;   // idle lanes iterate at 0, inside the short sin/cos path
-  if (wave_all(idle | short_args(dM, w))) xk = kepler_newton<true>(ec, es, dM, 40, idle, xk, s, c);
-  else xk = kepler_newton<false>(ec, es, dM, 40, idle, xk, s, c);
+  if (wave_all(idle | short_args(dM, w))) xk = planet_newton<true>(ec, es, dM, idle, xk, s, c);
+  else xk = planet_newton<false>(ec, es, dM, idle, xk, s, c);
   double Fp = fma_(-ec, c, fma_(es, s, 1.0));
   double cm1 = c - 1.0;
   double r1 = a * Fp;
