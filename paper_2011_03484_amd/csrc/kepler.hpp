@@ -110,7 +110,7 @@ TPM_DEV double kepler_newton(double ec, double es, double dM, int kiters, bool d
 // until the last step of each non-idle lane was a correction of at most
 // 2^-30 |x|, and its sin/cos come from that last step's rotation (as in
 // kepler_newton); at most 40 steps, after which sin/cos are evaluated afresh.
-// Idle lanes iterate on values that are never used.
+// Idle lanes (dM = 0, x = 0) stay at x = 0.
 template <bool SHORT>
 TPM_DEV double planet_newton(double ec, double es, double dM, bool idle, double xk, double& s,
                              double& c) {
@@ -198,7 +198,11 @@ TPM_DEV bool drift_fixed(const KepConst& K, double dt, int kiters, double ftol,
 
 // Converged drift for the planets (a handful of lanes in one wavefront):
 // Newton until every lane has made a step whose correction is at most
-// 2^-30 |x| (converged to rounding; planet_newton), at most 40 steps.
+// 2^-30 |x| (converged to rounding; planet_newton), at most 40 steps.  A lane
+// that holds no body, or whose body is found unbound (the return value is then
+// false), drifts for no time on a stand-in bound orbit (alpha = 1): dM = 0,
+// x = 0, f = gdot = 1 and g = fdot = 0 exactly, so its state is left as it
+// was without any select on the result.
 TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
                              double& x, double& y, double& z,
                              double& vx, double& vy, double& vz) {
@@ -208,9 +212,12 @@ TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
   double r0, rinv;
   sqrt_rsqrt(lane_on ? r2 : 1.0, r0, rinv);
   double alpha = fma_(-v2, K.inv_mu, 2.0 * rinv);
-  bool bound = alpha > 0.0;
+  const bool bound = alpha > 0.0;
+  const bool idle = !(lane_on && bound);
+  alpha = idle ? 1.0 : alpha;
+  dt = idle ? 0.0 : dt;
   double sa, rsa;
-  sqrt_rsqrt(bound ? alpha : 1.0, sa, rsa);
+  sqrt_rsqrt(alpha, sa, rsa);
   double a = rsa * rsa;
   a = fma_(a, fma_(-alpha, a, 1.0), a);
   double n = K.sqrt_mu * sa * alpha;
@@ -230,8 +237,6 @@ TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
   double w = 2.0 * (__builtin_fabs(ec) + __builtin_fabs(es));
   xk = __builtin_fmin(__builtin_fmax(xk, dM - w), dM + w);
   double s, c;
-  const bool idle = !(lane_on && bound);
-  xk = idle ? 0.0 : xk;   // idle lanes iterate at 0, inside the short sin/cos path
   if (wave_all(idle | short_args(dM, w))) xk = planet_newton<true>(ec, es, dM, idle, xk, s, c);
   else xk = planet_newton<false>(ec, es, dM, idle, xk, s, c);
   double Fp = fma_(-ec, c, fma_(es, s, 1.0));
@@ -242,11 +247,10 @@ TPM_DEV bool drift_converged(const KepConst& K, double dt, bool lane_on,
   double g = fma_(s - xk, ninv, dte);
   double fd = -(a * a) * n * s * rinv * r1inv;
   double gd = fma_(a * r1inv, cm1, 1.0);
-  bool upd = lane_on && bound;
   double nx = fma_(f, x, g * vx), ny = fma_(f, y, g * vy), nz = fma_(f, z, g * vz);
   double nvx = fma_(fd, x, gd * vx), nvy = fma_(fd, y, gd * vy), nvz = fma_(fd, z, gd * vz);
-  x = upd ? nx : x; y = upd ? ny : y; z = upd ? nz : z;
-  vx = upd ? nvx : vx; vy = upd ? nvy : vy; vz = upd ? nvz : vz;
+  x = nx; y = ny; z = nz;
+  vx = nvx; vy = nvy; vz = nvz;
   return bound;
 }
 
