@@ -141,7 +141,9 @@ TPM_DEV double kepler_solve(double ec, double es, double dM, int kiters, double 
 }
 
 // Drift (x, v) by dt about mass mu with k fixed Newton iterations.  Writes the
-// drifted state into (x, v) only where the return value is true.
+// drifted state into (x, v) on every lane; where the return value is false
+// (the drift is refused) that state is meaningless and the caller keeps its
+// own copy of the old one.
 TPM_DEV bool drift_fixed(const KepConst& K, double dt, int kiters, double ftol,
                          double& x, double& y, double& z,
                          double& vx, double& vy, double& vz) {
@@ -187,12 +189,10 @@ TPM_DEV bool drift_fixed(const KepConst& K, double dt, int kiters, double ftol,
   double g = fma_(s - xk, ninv, dte);
   double fd = -(a * a) * n * s * rinv * r1inv;
   double gd = fma_(a * r1inv, cm1, 1.0);
-  if (ok) {
-    double nx = fma_(f, x, g * vx), ny = fma_(f, y, g * vy), nz = fma_(f, z, g * vz);
-    double nvx = fma_(fd, x, gd * vx), nvy = fma_(fd, y, gd * vy), nvz = fma_(fd, z, gd * vz);
-    x = nx; y = ny; z = nz;
-    vx = nvx; vy = nvy; vz = nvz;
-  }
+  double nx = fma_(f, x, g * vx), ny = fma_(f, y, g * vy), nz = fma_(f, z, g * vz);
+  double nvx = fma_(fd, x, gd * vx), nvy = fma_(fd, y, gd * vy), nvz = fma_(fd, z, gd * vz);
+  x = nx; y = ny; z = nz;
+  vx = nvx; vy = nvy; vz = nvz;
   return ok;
 }
 

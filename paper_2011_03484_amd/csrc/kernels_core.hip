@@ -46,16 +46,27 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
     x = w.x[i]; y = w.y[i]; z = w.z[i];
     vx = w.vx[i]; vy = w.vy[i]; vz = w.vz[i];
   }
+  // A lane's removal record (the state it keeps, step, reason, planet) is
+  // written out in the step that removes it, so the state registers can be
+  // overwritten unconditionally; a removed lane takes no further part.
+  int32_t reason = valid ? ST_ACTIVE : -1;
+  auto record = [&](int32_t why, int64_t st, int32_t pl, double rx, double ry, double rz,
+                    double ux, double uy, double uz) {
+    const int k = w.slot[i];
+    out.r[3 * k + 0] = rx; out.r[3 * k + 1] = ry; out.r[3 * k + 2] = rz;
+    out.v[3 * k + 0] = ux; out.v[3 * k + 1] = uy; out.v[3 * k + 2] = uz;
+    out.step[k] = st;
+    out.reason[k] = why;
+    out.planet[k] = pl;
+    w.status[i] = why;
+    reason = why;
+  };
   double ax, ay, az;
   int hit = accel<NP>(rows + (size_t)s_begin * ROW, A.P, x, y, z, ax, ay, az);
-  int32_t reason = valid ? ST_ACTIVE : -1, planet = -1;
-  int64_t dstep = -1;
   if (valid) {
-    if (hit >= 0) {
-      reason = ST_ENCOUNTER; planet = hit; dstep = A.step0 + s_begin;
-    } else if (fma_(x, x, fma_(y, y, z * z)) > A.rmax2) {
-      reason = ST_ESCAPE; dstep = A.step0 + s_begin;
-    }
+    if (hit >= 0) record(ST_ENCOUNTER, A.step0 + s_begin, hit, x, y, z, vx, vy, vz);
+    else if (fma_(x, x, fma_(y, y, z * z)) > A.rmax2)
+      record(ST_ESCAPE, A.step0 + s_begin, -1, x, y, z, vx, vy, vz);
   }
   const double h = 0.5 * A.dt;
   // one step s -> s + 1, with the row that ends it (row s + 1)
@@ -63,22 +74,20 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
     if (reason == ST_ACTIVE) {
       double nx = x, ny = y, nz = z;
       double nvx = fma_(h, ax, vx), nvy = fma_(h, ay, vy), nvz = fma_(h, az, vz);
-      bool ok = drift_fixed(A.K, A.dt, kiters, A.ftol, nx, ny, nz, nvx, nvy, nvz);
+      const bool ok = drift_fixed(A.K, A.dt, kiters, A.ftol, nx, ny, nz, nvx, nvy, nvz);
       double bx, by, bz;
-      int hit1 = accel<NP>(row, A.P, nx, ny, nz, bx, by, bz);
-      double r2 = fma_(nx, nx, fma_(ny, ny, nz * nz));
-      if (!ok) {
-        reason = ST_KEPLER; dstep = A.step0 + s;
-      } else {
-        x = nx; y = ny; z = nz;
-        ax = bx; ay = by; az = bz;
-        vx = fma_(h, ax, nvx); vy = fma_(h, ay, nvy); vz = fma_(h, az, nvz);
-        if (hit1 >= 0) {
-          reason = ST_ENCOUNTER; planet = hit1; dstep = A.step0 + s + 1;
-        } else if (r2 > A.rmax2) {
-          reason = ST_ESCAPE; dstep = A.step0 + s + 1;
-        }
+      const int hit1 = accel<NP>(row, A.P, nx, ny, nz, bx, by, bz);
+      const double r2 = fma_(nx, nx, fma_(ny, ny, nz * nz));
+      nvx = fma_(h, bx, nvx); nvy = fma_(h, by, nvy); nvz = fma_(h, bz, nvz);
+      if (!ok | (hit1 >= 0) | (r2 > A.rmax2)) {
+        // a Kepler failure keeps the state at the start of the step
+        if (!ok) record(ST_KEPLER, A.step0 + s, -1, x, y, z, vx, vy, vz);
+        else if (hit1 >= 0) record(ST_ENCOUNTER, A.step0 + s + 1, hit1, nx, ny, nz, nvx, nvy, nvz);
+        else record(ST_ESCAPE, A.step0 + s + 1, -1, nx, ny, nz, nvx, nvy, nvz);
       }
+      x = nx; y = ny; z = nz;
+      vx = nvx; vy = nvy; vz = nvz;
+      ax = bx; ay = by; az = bz;
     }
   };
   // leave once every lane is removed (checked every 8 steps: the check itself
@@ -109,16 +118,7 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
       step(s, rows + (size_t)(s + 1) * ROW);
     }
   }
-  if (!valid) return;
-  if (reason != ST_ACTIVE) {
-    const int k = w.slot[i];
-    out.r[3 * k + 0] = x; out.r[3 * k + 1] = y; out.r[3 * k + 2] = z;
-    out.v[3 * k + 0] = vx; out.v[3 * k + 1] = vy; out.v[3 * k + 2] = vz;
-    out.step[k] = dstep;
-    out.reason[k] = reason;
-    out.planet[k] = planet;
-    w.status[i] = reason;
-  } else {
+  if (reason == ST_ACTIVE) {
     w.x[i] = x; w.y[i] = y; w.z[i] = z;
     w.vx[i] = vx; w.vy[i] = vy; w.vz[i] = vz;
   }
@@ -1007,8 +1007,10 @@ __global__ void drift_test_kernel(KepConst K, int kiters, double ftol, const dou
   double x = in[6 * i + 0], y = in[6 * i + 1], z = in[6 * i + 2];
   double vx = in[6 * i + 3], vy = in[6 * i + 4], vz = in[6 * i + 5];
   bool g = drift_fixed(K, dt, kiters, ftol, x, y, z, vx, vy, vz);
-  out[6 * i + 0] = x; out[6 * i + 1] = y; out[6 * i + 2] = z;
-  out[6 * i + 3] = vx; out[6 * i + 4] = vy; out[6 * i + 5] = vz;
+  // a refused drift leaves the state as it was
+  out[6 * i + 0] = g ? x : in[6 * i + 0]; out[6 * i + 1] = g ? y : in[6 * i + 1];
+  out[6 * i + 2] = g ? z : in[6 * i + 2]; out[6 * i + 3] = g ? vx : in[6 * i + 3];
+  out[6 * i + 4] = g ? vy : in[6 * i + 4]; out[6 * i + 5] = g ? vz : in[6 * i + 5];
   ok[i] = g ? 1 : 0;
 }
 
