@@ -351,12 +351,47 @@ hipError_t launch_particle_chunk(const SysConst& S, Work w, const int32_t* d_nac
 // scalar registers (no LDS round trip), and everything per step is branch-free
 // except the wave-uniform Newton loop of the planets' Kepler drifts.
 
-// Value of v on lane `src` (a compile-time constant), returned wave-uniform.
+// Value of v on lane `src` (a compile-time constant), returned wave-uniform
+// in an SGPR pair.
 TPM_DEV double bcast(double v, int src) {
   uint64_t u = __builtin_bit_cast(uint64_t, v);
   uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
   uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Value of v on lane SRC (below 16) on every lane of each row of 16, by a DPP
+// row broadcast (row_newbcast) into a VGPR.  The planet map's bodies sit in
+// lanes 0..8, and its other lanes' values are never used.
+template <int SRC>
+TPM_DEV double bcast_row(double v) {
+  static_assert(SRC >= 0 && SRC < 16, "row broadcast source");
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x150 + SRC, 0xF,
+                                                             0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32),
+                                                             0x150 + SRC, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// The planet map's broadcast of lane src's value.  The single-system map (a
+// lone wavefront) reads it into SGPRs, since its FMAs run faster with a scalar
+// operand; the many-system map, one wavefront per system, broadcasts it in
+// VGPRs, which frees the SGPRs it otherwise spills (3% faster there).
+template <bool ROWB>
+TPM_DEV double eph_bcast(double v, int src) {
+  if (!ROWB) return bcast(v, src);
+  switch (src) {
+    case 0: return bcast_row<0>(v);
+    case 1: return bcast_row<1>(v);
+    case 2: return bcast_row<2>(v);
+    case 3: return bcast_row<3>(v);
+    case 4: return bcast_row<4>(v);
+    case 5: return bcast_row<5>(v);
+    case 6: return bcast_row<6>(v);
+    case 7: return bcast_row<7>(v);
+    default: return bcast_row<8>(v);
+  }
 }
 
 // Heliocentric positions of bodies 0..NP (body 0 at the origin) from the
@@ -440,7 +475,7 @@ TPM_DEV void own_helio(const EphW<NP>& W, double jx, double jy, double jz,
 
 // Heliocentric positions of all bodies and the lane's own one, from the Jacobi
 // positions held by lanes 1..NP (see helio_all).
-template <int NP>
+template <int NP, bool ROWB>
 TPM_DEV void helio_step(const EphConst& E, const EphW<NP>& W, double jx, double jy, double jz,
                         double (&hx)[NP + 1], double (&hy)[NP + 1], double (&hz)[NP + 1],
                         double& ox, double& oy, double& oz) {
@@ -450,7 +485,7 @@ TPM_DEV void helio_step(const EphConst& E, const EphW<NP>& W, double jx, double 
   px[0] = 0.0; py[0] = 0.0; pz[0] = 0.0;
 #pragma unroll
   for (int b = 1; b <= NP; ++b) {
-    px[b] = bcast(jx, b); py[b] = bcast(jy, b); pz[b] = bcast(jz, b);
+    px[b] = eph_bcast<ROWB>(jx, b); py[b] = eph_bcast<ROWB>(jy, b); pz[b] = eph_bcast<ROWB>(jz, b);
     hx[b] = px[b] + Rx; hy[b] = py[b] + Ry; hz[b] = pz[b] + Rz;
     Rx = fma_(E.cj[b], px[b], Rx);
     Ry = fma_(E.cj[b], py[b], Ry);
@@ -470,7 +505,7 @@ TPM_DEV void helio_step(const EphConst& E, const EphW<NP>& W, double jx, double 
 // central term from the lane's own sum.  The two terms would otherwise cancel
 // to about mu_1/mu_0 of their size and amplify their rounding by mu_0/mu_1.
 // The broadcast a_1 keeps its central term.
-template <int NP>
+template <int NP, bool ROWB>
 TPM_DEV void eph_accel(const EphConst& E, const EphLane& L, const EphW<NP>& W, double jx,
                        double jy, double jz, const double (&hx)[NP + 1],
                        const double (&hy)[NP + 1], const double (&hz)[NP + 1], double ox,
@@ -492,9 +527,9 @@ TPM_DEV void eph_accel(const EphConst& E, const EphLane& L, const EphW<NP>& W, d
   double sx = 0.0, sy = 0.0, sz = 0.0;
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    sx = fma_(W.wa[k], bcast(nx, k), sx);
-    sy = fma_(W.wa[k], bcast(ny, k), sy);
-    sz = fma_(W.wa[k], bcast(nz, k), sz);
+    sx = fma_(W.wa[k], eph_bcast<ROWB>(nx, k), sx);
+    sy = fma_(W.wa[k], eph_bcast<ROWB>(ny, k), sy);
+    sz = fma_(W.wa[k], eph_bcast<ROWB>(nz, k), sz);
   }
   double r2 = fma_(jx, jx, fma_(jy, jy, jz * jz));
   double kk = mul_rsqrt3(L.kc, r2 + L.nb);
@@ -530,7 +565,7 @@ TPM_DEV bool hill_violation(const EphW<NP>& W, double ox, double oy, double oz,
 #define TPM_PLANET_KERNEL
 #endif
 
-template <int NP>
+template <int NP, bool ROWB>
 TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* __restrict__ vj,
                             double* __restrict__ rows, int nsteps, double dt, int64_t step0,
                             int64_t* __restrict__ flag) {
@@ -564,8 +599,8 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
   }
   double hx[NP + 1], hy[NP + 1], hz[NP + 1];
   double ox, oy, oz, ax, ay, az;
-  helio_step<NP>(E, W, jx, jy, jz, hx, hy, hz, ox, oy, oz);
-  eph_accel<NP>(E, L, W, jx, jy, jz, hx, hy, hz, ox, oy, oz, ax, ay, az);
+  helio_step<NP, ROWB>(E, W, jx, jy, jz, hx, hy, hz, ox, oy, oz);
+  eph_accel<NP, ROWB>(E, L, W, jx, jy, jz, hx, hy, hz, ox, oy, oz, ax, ay, az);
   // row 0: current state; lane b writes planet b, lane 0 writes h0 = -a_0
   if (L.body) {
     rows[3 * (L.lane - 1) + 0] = ox;
@@ -587,8 +622,8 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
     bool bound = drift_converged(L.K, dt, L.body, jx, jy, jz, wx, wy, wz);
     const uint32_t k1 = 2u * (uint32_t)(s + 1);
     first_ev = __builtin_elementwise_min(first_ev, (L.body && !bound) ? k1 : UINT32_MAX);
-    helio_step<NP>(E, W, jx, jy, jz, hx, hy, hz, ox, oy, oz);
-    eph_accel<NP>(E, L, W, jx, jy, jz, hx, hy, hz, ox, oy, oz, ax, ay, az);
+    helio_step<NP, ROWB>(E, W, jx, jy, jz, hx, hy, hz, ox, oy, oz);
+    eph_accel<NP, ROWB>(E, L, W, jx, jy, jz, hx, hy, hz, ox, oy, oz, ax, ay, az);
     wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
     double* row = rows + (size_t)(s + 1) * ROW;
     if (L.body) {
@@ -623,7 +658,7 @@ __global__ void __launch_bounds__(64) TPM_PLANET_KERNEL
 ephemeris_chunk(EphConst E, double* __restrict__ rj, double* __restrict__ vj,
                 double* __restrict__ rows, int nsteps, double dt, int64_t step0,
                 int64_t* __restrict__ flag) {
-  ephemeris_body<NP>(E, rj, vj, rows, nsteps, dt, step0, flag);
+  ephemeris_body<NP, false>(E, rj, vj, rows, nsteps, dt, step0, flag);
 }
 
 // Many systems at once: workgroup b runs system b (its constants, Jacobi
@@ -639,15 +674,15 @@ ephemeris_batch(const EphConst* __restrict__ E, double* __restrict__ rj, double*
   double* r = rj + 3 * MAX_NP * b;
   double* v = vj + 3 * MAX_NP * b;
   switch (e.np) {
-    case 1: ephemeris_body<1>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
-    case 2: ephemeris_body<2>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
-    case 3: ephemeris_body<3>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
-    case 4: ephemeris_body<4>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
-    case 5: ephemeris_body<5>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
-    case 6: ephemeris_body<6>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
-    case 7: ephemeris_body<7>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
-    case 8: ephemeris_body<8>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
-    default: ephemeris_body<0>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 1: ephemeris_body<1, true>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 2: ephemeris_body<2, true>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 3: ephemeris_body<3, true>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 4: ephemeris_body<4, true>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 5: ephemeris_body<5, true>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 6: ephemeris_body<6, true>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 7: ephemeris_body<7, true>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    case 8: ephemeris_body<8, true>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
+    default: ephemeris_body<0, true>(e, r, v, rows, nsteps, dt[b], step0, flag + b); break;
   }
 }
 
