@@ -362,7 +362,9 @@ TPM_DEV double bcast(double v, int src) {
 
 // Value of v on lane SRC (below 16) on every lane of each row of 16, by a DPP
 // row broadcast (row_newbcast) into a VGPR.  The planet map's bodies sit in
-// lanes 0..8, and its other lanes' values are never used.
+// lanes 0..8, and its other lanes' values are never used: lanes 16..63 then
+// carry garbage (NaN included), which every wave-wide test of the planet map
+// masks by the lane's idle flag.
 template <int SRC>
 TPM_DEV double bcast_row(double v) {
   static_assert(SRC >= 0 && SRC < 16, "row broadcast source");
