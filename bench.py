@@ -43,13 +43,19 @@ PMC_BENCH_ARGS = ("--nsteps 20000 --steps 1 --warmup 0 --no-cpu --no-adjoint --n
 
 
 def kernel_source_hash() -> str:
-    """Fingerprint of the HIP sources (counter figures apply to one version)."""
+    """Fingerprint of the HIP sources' code (counter figures apply to one
+    version): comments and whitespace are left out, so that only a change of
+    the code itself invalidates them."""
     import hashlib
+    import re
     h = hashlib.sha1()
     csrc = os.path.join(ROOT, "paper_2011_03484_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith((".hip", ".hpp", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+            text = open(os.path.join(csrc, f)).read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
+            h.update(f.encode() + b"\0" + " ".join(text.split()).encode())
     return h.hexdigest()
 
 
