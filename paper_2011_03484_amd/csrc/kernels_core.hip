@@ -603,13 +603,17 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
   double ox, oy, oz, ax, ay, az;
   helio_step<NP, ROWB>(E, W, jx, jy, jz, hx, hy, hz, ox, oy, oz);
   eph_accel<NP, ROWB>(E, L, W, jx, jy, jz, hx, hy, hz, ox, oy, oz, ax, ay, az);
-  // row 0: current state; lane b writes planet b, lane 0 writes h0 = -a_0
-  if (L.body) {
-    rows[3 * (L.lane - 1) + 0] = ox;
-    rows[3 * (L.lane - 1) + 1] = oy;
-    rows[3 * (L.lane - 1) + 2] = oz;
-  } else if (L.lane == 0) {
-    rows[3 * NP + 0] = -ax; rows[3 * NP + 1] = -ay; rows[3 * NP + 2] = -az;
+  // Row entries: lane b writes planet b's heliocentric position, lane 0 (the
+  // central body, whose own position is the origin) writes h0 = -a_0, both as
+  // fma(rsign, a, o) with rsign = 0 on body lanes and -1 on lane 0.
+  const bool writer = L.lane <= NP;
+  const int roff = L.body ? 3 * (L.lane - 1) : 3 * NP;
+  const double rsign = L.body ? 0.0 : -1.0;
+  // row 0: the current state
+  if (writer) {
+    rows[roff + 0] = fma_(rsign, ax, ox);
+    rows[roff + 1] = fma_(rsign, ay, oy);
+    rows[roff + 2] = fma_(rsign, az, oz);
   }
   const double h = 0.5 * dt;
   // Per lane, the first event as a key ordered in time, counted from step0: a
@@ -627,13 +631,11 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
     helio_step<NP, ROWB>(E, W, jx, jy, jz, hx, hy, hz, ox, oy, oz);
     eph_accel<NP, ROWB>(E, L, W, jx, jy, jz, hx, hy, hz, ox, oy, oz, ax, ay, az);
     wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
-    double* row = rows + (size_t)(s + 1) * ROW;
-    if (L.body) {
-      row[3 * (L.lane - 1) + 0] = ox;
-      row[3 * (L.lane - 1) + 1] = oy;
-      row[3 * (L.lane - 1) + 2] = oz;
-    } else if (L.lane == 0) {
-      row[3 * NP + 0] = -ax; row[3 * NP + 1] = -ay; row[3 * NP + 2] = -az;
+    if (writer) {
+      double* row = rows + (size_t)(s + 1) * ROW + roff;
+      row[0] = fma_(rsign, ax, ox);
+      row[1] = fma_(rsign, ay, oy);
+      row[2] = fma_(rsign, az, oz);
     }
     if (NP > 1) {
       bool bad = hill_violation<NP>(W, ox, oy, oz, hx, hy, hz);
