@@ -110,7 +110,9 @@ TPM_DEV double kepler_newton(double ec, double es, double dM, int kiters, bool d
 // until the last step of each non-idle lane was a correction of at most
 // 2^-30 |x|, and its sin/cos come from that last step's rotation (as in
 // kepler_newton); at most 40 steps, after which sin/cos are evaluated afresh.
-// Idle lanes (dM = 0, x = 0) stay at x = 0.
+// Idle lanes (dM = 0, x = 0) stay at x = 0.  Lanes beyond the bodies may
+// carry NaN (their central-body term sits at zero distance), so idle lanes
+// enter every wave-wide test through their idle flag.
 template <bool SHORT>
 TPM_DEV double planet_newton(double ec, double es, double dM, bool idle, double xk, double& s,
                              double& c) {
