@@ -123,7 +123,10 @@ int tpm_set_particles(tpm_sim* sim, int64_t n, const double* r, const double* v)
 /* Advance planets and particles by nsteps steps of dt (dt < 0 integrates
  * backwards).  Checks run at every step boundary, including the first and last.
  * Calling it twice with T1 and T2 steps gives bit-identical results to one call
- * with T1 + T2 steps. */
+ * with T1 + T2 steps.  TPM_EINVAL and TPM_ESTATE are returned before any work is
+ * enqueued and leave the simulation as it was; after TPM_ENOMEM or TPM_EDEVICE
+ * the integration stopped part-way and the simulation's state is undefined
+ * (destroy it). */
 int tpm_integrate(tpm_sim* sim, int64_t nsteps, double dt);
 
 /* Particle results in the caller's order (any pointer may be NULL): r, v [n][3]
