@@ -574,3 +574,46 @@ def test_eight_planets_single_system(tpm, orc):
     g = s.particles()
     res, near, spread = _oracle_reference(orc, w, T, eph.table)
     _compare(g, res, near, spread, "eight_planets")
+
+
+def test_planet_order_is_the_callers(tpm):
+    """Planets handed over in any order are integrated in the Jacobi order
+    (sorted by semi-major axis) and reported in the caller's: the same system
+    with its planets shuffled gives bit-identical particles, encounter planet
+    indices mapped through the shuffle, and planet states and planet-table
+    columns in the shuffled order; the many-system call gives the same
+    results for both systems."""
+    w = W.adjoint_16k(n=4000, seed=41)
+    T = 2000
+    perm = np.array([2, 0, 3, 1])                 # caller index k holds sorted planet perm[k]
+    inv = np.argsort(perm)
+
+    def run(mu, rp, vp, rcrit):
+        s = tpm.Simulation(r_escape=w.rmax, kepler_iters=w.kepler_iters)
+        s.set_central(w.mu0)
+        s.set_planets(mu, rp, vp, rcrit)
+        table = s.planet_table(200, w.dt)
+        s.set_particles(w.r, w.v)
+        s.integrate(T, w.dt)
+        return s.particles(), s.planets(), table
+
+    a, (ar, av), at = run(w.mu, w.rp, w.vp, w.rcrit)
+    b, (br, bv), bt = run(w.mu[perm], w.rp[perm], w.vp[perm], w.rcrit[perm])
+    for k in ("r", "v", "deact_step", "reason"):
+        assert np.array_equal(a[k], b[k]), k
+    enc = a["planet"] >= 0
+    assert len(np.unique(a["planet"][enc])) >= 2, np.unique(a["planet"][enc])
+    assert np.array_equal(b["planet"][enc], inv[a["planet"][enc]])
+    assert np.all(b["planet"][~enc] == -1)
+    assert np.array_equal(br, ar[perm]) and np.array_equal(bv, av[perm])
+    cols = np.concatenate([np.arange(3 * j, 3 * j + 3) for j in perm] + [np.arange(12, 15)])
+    assert np.array_equal(bt, at[:, cols])
+    print(f"removed {np.sum(a['reason'] != 0)}, by planet {np.bincount(a['planet'][enc], minlength=4)}",
+          flush=True)
+    # the many-system call maps each system's planets the same way
+    ws = w.subset(nsteps=T)
+    wp = W.Workload("shuffled", w.mu0, w.mu[perm].copy(), w.rp[perm].copy(), w.vp[perm].copy(),
+                    w.rcrit[perm].copy(), w.rmax, w.r.copy(), w.v.copy(), w.dt, T)
+    (ga, gb), _ = tpm.batch_integrate([ws, wp], nsteps=T)
+    for k in ("r", "v", "deact_step", "reason", "planet"):
+        assert np.array_equal(ga[k], a[k]) and np.array_equal(gb[k], b[k]), k
