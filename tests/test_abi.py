@@ -67,3 +67,12 @@ def test_invalid_arguments_refused_before_device_work():
     with pytest.raises(_lib.TpmError) as e:
         _lib.Simulation(waves_per_simd=9)
     assert e.value.code == _lib.TPM_EINVAL
+    with pytest.raises(_lib.TpmError) as e:
+        _lib.Simulation(kepler_iters=65)
+    assert e.value.code == _lib.TPM_EINVAL
+    from paper_2011_03484_amd import workloads as W
+    w = W.single_planet(n=4, seed=1)
+    for kw in ({"kepler_iters": 65}, {"chunk_steps": (1 << 30) + 1}, {"block_threads": 96}):
+        with pytest.raises(_lib.TpmError) as e:
+            _lib.batch_integrate([w], nsteps=10, **kw)
+        assert e.value.code == _lib.TPM_EINVAL, kw
