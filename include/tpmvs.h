@@ -123,7 +123,10 @@ int tpm_set_particles(tpm_sim* sim, int64_t n, const double* r, const double* v)
 /* Advance planets and particles by nsteps steps of dt (dt < 0 integrates
  * backwards).  Checks run at every step boundary, including the first and last.
  * Calling it twice with T1 and T2 steps gives bit-identical results to one call
- * with T1 + T2 steps.  TPM_EINVAL and TPM_ESTATE are returned before any work is
+ * with T1 + T2 steps.  Resuming in a new simulation from tpm_get_planets and the
+ * still-active particles of tpm_get_particles (step count restarting at 0)
+ * agrees with the uninterrupted run to rounding: the planets' internal Jacobi
+ * state passes through heliocentric coordinates once more.  TPM_EINVAL and TPM_ESTATE are returned before any work is
  * enqueued and leave the simulation as it was; after TPM_ENOMEM or TPM_EDEVICE
  * the integration stopped part-way and the simulation's state is undefined
  * (destroy it). */
