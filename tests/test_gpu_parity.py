@@ -63,11 +63,11 @@ def _oracle_reference(orc, w, T, table, planet_sensitivity=True):
     return res, near, spread
 
 
-def _compare(gpu, res, near, spread, label, extra=0.0):
+def _compare(gpu, res, near, spread, label, extra=0.0, plain_frac=0.5):
     """Removal records identical (outside the near-threshold set); every
     particle within max(1e-11, 100 x its one-ulp spread in the oracle) plus
-    `extra` (a per-particle allowance, zero unless stated), and at least half
-    of the particles within the plain 1e-11 bar."""
+    `extra` (a per-particle allowance, zero unless stated), and at least
+    `plain_frac` of the particles within the plain 1e-11 bar."""
     ok = ~near
     assert np.array_equal(gpu["reason"][ok], res.reason[ok]), label
     assert np.array_equal(gpu["deact_step"][ok], res.deact_step[ok]), label
@@ -84,7 +84,7 @@ def _compare(gpu, res, near, spread, label, extra=0.0):
           f"max rel r {err[cmp_].max():.3e} v {verr[cmp_].max():.3e}  "
           f"max err/bound {(worst[cmp_] / bound[cmp_]).max():.3f}", flush=True)
     assert cmp_.sum() > 0
-    assert plain.sum() >= 0.5 * len(err), label
+    assert plain.sum() >= plain_frac * len(err), label
     assert np.all(worst[cmp_] <= bound[cmp_]), label
 
 
@@ -497,6 +497,23 @@ def test_full_size_giants_sampled(tpm, orc):
     res, near, spread = _oracle_reference(orc, sub, T, eph.table)
     gs = {k: g[k][idx] for k in ("r", "v", "deact_step", "reason", "planet")}
     _compare(gs, res, near, spread, "giants_100k/full")
+
+
+def test_single_planet_full_length(tpm, orc):
+    """The single-planet workload at its full length, 1,024 particles for
+    10,000 steps of 0.5 yr (about 420 orbits of the planet), end to end.  By
+    then most orbits near the planet have amplified a one-ulp change of their
+    initial state far beyond 1e-12 (up to 1e-4), so positions are held only to
+    max(1e-11, 100 x that spread) and the plain-bar fraction is not required.
+    The removal records stay unique (no record of the oracle's run moves
+    under those one-ulp changes) and must be identical."""
+    w = W.single_planet()
+    T = 10_000
+    g = _run(tpm, w, T)
+    eph = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, T, w.dt)
+    res, near, spread = _oracle_reference(orc, w, T, eph.table)
+    assert np.sum(res.reason != 0) > 100
+    _compare(g, res, near, spread, "single_planet/full", plain_frac=0.0)
 
 
 def test_full_size_resonant_sampled(tpm, orc):
