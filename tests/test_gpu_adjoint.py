@@ -50,15 +50,21 @@ def test_ad_forward_matches_integrate(env):
     assert err < 1e-13, err
 
 
-def test_tangent_and_adjoint_match_oracle(env, orc):
+@pytest.mark.parametrize("k", [5, 8])
+def test_tangent_and_adjoint_match_oracle(env, orc, k):
+    """Tangent and adjoint against the oracle's complex-step state-transition
+    matrices, with the default five Newton steps and with eight (the general
+    count of the derivative kernels)."""
     torch, P, AG = env
     w = _case(n=128, T=600)
+    w.kepler_iters = k
     s = _sim(P, w)
     rT, vT, step, reason = AG.integrate(s, _t(torch, w.r), _t(torch, w.v), w.nsteps, w.dt, 100)
     eph = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, w.nsteps, w.dt)
-    ref = orc.particles(w.mu0, w.mu, w.rcrit, w.rmax, eph.table, w.dt, w.r, w.v, w.nsteps)
+    ref = orc.particles(w.mu0, w.mu, w.rcrit, w.rmax, eph.table, w.dt, w.r, w.v, w.nsteps,
+                        kepler_iters=k)
     same = ref.deact_step == step.cpu().numpy()
-    M = orc.stm(w.mu0, w.mu, w.rcrit, w.rmax, eph.table, w.dt, w.r, w.v, w.nsteps)
+    M = orc.stm(w.mu0, w.mu, w.rcrit, w.rmax, eph.table, w.dt, w.r, w.v, w.nsteps, kepler_iters=k)
     rng = np.random.default_rng(3)
     dr, dv = rng.normal(size=(w.n, 3)), rng.normal(size=(w.n, 3))
     tr, tv = AG.tangent(s, _t(torch, dr), _t(torch, dv))
