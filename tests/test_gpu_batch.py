@@ -146,3 +146,21 @@ def test_batched_edge_systems(P, orc):
     _compare(res[1], ref, near, spread, "batched/noplanet")
     with pytest.raises(P.PlanetEncounterError):
         P.batch_integrate(systems, nsteps=T)
+
+
+def test_batched_backwards_equals_per_system_runs(P):
+    """Negative steps (integration backwards in time) in the many-system call,
+    mixed with forward systems: every system bit-identical to its own
+    single-system run."""
+    base = _systems(nsys=6, nmax=250, seed=13)
+    T = 500
+    systems = []
+    for i, w in enumerate(base):
+        dt = -w.dt if i % 2 == 0 else w.dt
+        systems.append(W.Workload(w.name, w.mu0, w.mu.copy(), w.rp.copy(), w.vp.copy(), w.rcrit.copy(),
+                                  w.rmax, w.r.copy(), w.v.copy(), dt, T))
+    res, _ = P.batch_integrate(systems, nsteps=T)
+    for w, g in zip(systems, res):
+        ref = _single(P, w, T)
+        for k in ("r", "v", "deact_step", "reason", "planet"):
+            assert np.array_equal(g[k], ref[k]), (w.name, w.dt, k)

@@ -316,6 +316,16 @@ def test_removal_special_cases(tpm, orc):
     assert list(g["planet"]) == list(ref.planet)
     assert list(g["deact_step"]) == list(ref.deact_step)
     assert np.array_equal(g["r"][:4], r[:4]) and np.array_equal(g["v"][:4], v[:4])
+    # r_escape <= 0 disables the escape test: the two escapes stay active
+    s = tpm.Simulation(r_escape=0.0)
+    s.set_central(mu0)
+    s.set_planets(mu, rp, vp, rcrit)
+    s.set_particles(r, v)
+    s.integrate(4, 0.1)
+    g = s.particles()
+    ref = orc.particles(mu0, mu, rcrit, 0.0, eph.table, 0.1, r, v, 4)
+    assert list(g["reason"]) == list(ref.reason) == [1, 1, 0, 3, 0]
+    assert list(g["deact_step"]) == list(ref.deact_step)
 
 
 def test_kepler_failure_removal(tpm, orc):
