@@ -535,3 +535,64 @@ def test_adjoint_dot_product(orc):
     lhs = (tr * gr).sum(1) + (tv * gv).sum(1)
     rhs = (dr * ar).sum(1) + (dv * av).sum(1)
     assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-12 * np.abs(lhs).max())
+
+
+def _kepler_mp(mu, r, v, t):
+    """Two-body propagation in 40-digit arithmetic by a route independent of
+    f and g: the perifocal frame of the eccentricity vector and the angular
+    momentum, and the classical Kepler equation E - e sin E = M."""
+    import mpmath as mp
+    dot = lambda a, b: a[0] * b[0] + a[1] * b[1] + a[2] * b[2]
+    cross = lambda a, b: [a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]]
+    rn = mp.sqrt(dot(r, r))
+    h = cross(r, v)
+    vxh = cross(v, h)
+    ev = [vxh[k] / mu - r[k] / rn for k in range(3)]
+    e = mp.sqrt(dot(ev, ev))
+    a = 1 / (2 / rn - dot(v, v) / mu)
+    hn = mp.sqrt(dot(h, h))
+    P = [ev[k] / e for k in range(3)]
+    Q = cross([h[k] / hn for k in range(3)], P)
+    E0 = mp.atan2(dot(r, v) / mp.sqrt(mu * a), 1 - rn / a)   # e sin E0, e cos E0
+    n = mp.sqrt(mu / a ** 3)
+    M = E0 - e * mp.sin(E0) + n * t
+    E = M
+    for _ in range(100):
+        dE = (E - e * mp.sin(E) - M) / (1 - e * mp.cos(E))
+        E -= dE
+        if abs(dE) < mp.mpf(10) ** -38:
+            break
+    b = a * mp.sqrt(1 - e * e)
+    x, y = a * (mp.cos(E) - e), b * mp.sin(E)
+    edot = n / (1 - e * mp.cos(E))
+    vx, vy = -a * mp.sin(E) * edot, b * mp.cos(E) * edot
+    return [x * P[k] + y * Q[k] for k in range(3)] + [vx * P[k] + vy * Q[k] for k in range(3)]
+
+
+def test_planetless_stm_matches_extended_precision_differences(orc):
+    """With no planets the kicks vanish and T steps of the map are the exact
+    two-body flow for T dt, so the oracle's complex-step state-transition
+    matrix must equal the Jacobian of an independent 40-digit Kepler
+    propagation, taken by central differences (h = 1e-15, truncation ~1e-30)."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    mu0 = W.MU_SUN
+    r, v = W.elements_to_cartesian(mu0, np.array([7.0, 25.0, 2.0]), np.array([0.3, 0.05, 0.7]),
+                                   np.array([0.5, 1.1, 0.2]), np.array([0.3, 2.0, 4.0]),
+                                   np.array([1.0, 5.0, 2.5]), np.array([0.2, 3.0, 6.0]))
+    T, dt = 200, 0.1
+    eph = orc.ephemeris(mu0, np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)), T, dt)
+    M = orc.stm(mu0, np.zeros(0), np.zeros(0), 0.0, eph.table, dt, r, v, T)
+    h = mp.mpf(10) ** -15
+    for i in range(len(r)):
+        X = [mp.mpf(float(x)) for x in np.concatenate([r[i], v[i]])]
+        ref = np.zeros((6, 6))
+        for c in range(6):
+            Xp, Xm = list(X), list(X)
+            Xp[c] += h
+            Xm[c] -= h
+            fp = _kepler_mp(mu0, Xp[:3], Xp[3:], T * dt)
+            fm = _kepler_mp(mu0, Xm[:3], Xm[3:], T * dt)
+            ref[:, c] = [float((fp[k] - fm[k]) / (2 * h)) for k in range(6)]
+        err = np.max(np.abs(M[i] - ref)) / np.max(np.abs(ref))
+        assert err < 1e-11, (i, err)
