@@ -1,14 +1,18 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
 
 Bars (see the oracle's header for what is computed):
-  * positions within 1e-11 relative after 1,000 steps, identical removal step,
-    reason and planet;
+  * positions and velocities within 1e-11 relative after 1,000 steps,
+    identical removal step, reason and planet;
   * particles whose removal flips when the oracle's thresholds move by 1e-9
     are excluded from the removal comparison (near-threshold);
-  * every particle is held to max(1e-11, 100 x its own one-ulp spread) --
-    the response of the oracle's trajectory to a one-ulp change of the initial
-    position, its conditioning (the chaos floor) -- and at least half of the
-    particles of every workload to the plain 1e-11.
+  * spread is a particle's conditioning: how far the oracle's own trajectory
+    moves under a one-ulp change of its initial position (and, end to end, of
+    the first planet's).  Every particle with spread <= 1e-12 (regular) is
+    held to the plain 1e-11.  Particles with spread > 1e-12 (chaotic) are
+    reported separately and held to max(1e-11, 100 x spread): a change of the
+    rounding sequence alone (the oracle rebuilt with FMA contraction) moves
+    them by at most 12 x spread over 1,000 steps and 42 x over 10,000, which
+    tests/test_oracle_pins.py::test_chaos_multiplier measures on the CPU.
 """
 import math
 
@@ -63,11 +67,15 @@ def _oracle_reference(orc, w, T, table, planet_sensitivity=True):
     return res, near, spread
 
 
-def _compare(gpu, res, near, spread, label, extra=0.0, plain_frac=0.5):
+REGULAR_SPREAD = 1e-12     # spread at or below which a particle counts as regular
+CHAOS_FACTOR = 100.0       # bound of a chaotic particle, in units of its spread
+
+
+def _compare(gpu, res, near, spread, label, extra=0.0):
     """Removal records identical (outside the near-threshold set); every
-    particle within max(1e-11, 100 x its one-ulp spread in the oracle) plus
-    `extra` (a per-particle allowance, zero unless stated), and at least
-    `plain_frac` of the particles within the plain 1e-11 bar."""
+    regular particle (spread <= 1e-12) within the plain 1e-11 in position and
+    velocity, every chaotic one within max(1e-11, 100 x spread); `extra` is a
+    per-particle allowance added to both bars (zero unless stated)."""
     ok = ~near
     assert np.array_equal(gpu["reason"][ok], res.reason[ok]), label
     assert np.array_equal(gpu["deact_step"][ok], res.deact_step[ok]), label
@@ -75,17 +83,21 @@ def _compare(gpu, res, near, spread, label, extra=0.0, plain_frac=0.5):
     same = ok & (gpu["deact_step"] == res.deact_step)
     err = np.linalg.norm(gpu["r"] - res.r, axis=1) / np.linalg.norm(res.r, axis=1)
     verr = np.linalg.norm(gpu["v"] - res.v, axis=1) / np.linalg.norm(res.v, axis=1)
-    cmp_ = same & np.isfinite(spread)
-    bound = np.maximum(POS_TOL, 100 * spread) + extra
     worst = np.maximum(err, verr)
+    cmp_ = same & np.isfinite(spread)
+    regular = cmp_ & (spread <= REGULAR_SPREAD)
+    chaotic = cmp_ & (spread > REGULAR_SPREAD)
     plain = cmp_ & (worst <= POS_TOL)
+    bound = np.where(regular, POS_TOL, np.maximum(POS_TOL, CHAOS_FACTOR * spread)) + extra
     print(f"[{label}] n={len(err)} near={near.sum()} removed={np.sum(res.reason != 0)} "
-          f"within 1e-11: {plain.sum()}/{cmp_.sum()}  spread>1e-12: {np.sum(cmp_ & (spread > 1e-12))}  "
-          f"max rel r {err[cmp_].max():.3e} v {verr[cmp_].max():.3e}  "
-          f"max err/bound {(worst[cmp_] / bound[cmp_]).max():.3f}", flush=True)
-    assert cmp_.sum() > 0
-    assert plain.sum() >= plain_frac * len(err), label
-    assert np.all(worst[cmp_] <= bound[cmp_]), label
+          f"regular {regular.sum()} (max rel r {err[regular].max() if regular.any() else 0:.3e} "
+          f"v {verr[regular].max() if regular.any() else 0:.3e}); chaotic {chaotic.sum()} "
+          f"(max err/spread {(worst[chaotic] / spread[chaotic]).max() if chaotic.any() else 0:.2f}); "
+          f"within 1e-11: {plain.sum()}/{cmp_.sum()}; max err/bound "
+          f"{(worst[cmp_] / bound[cmp_]).max():.3f}", flush=True)
+    assert cmp_.sum() > 0, label
+    assert np.all(worst[regular] <= bound[regular]), (label, "regular")
+    assert np.all(worst[chaotic] <= bound[chaotic]), (label, "chaotic")
 
 
 def _sim(tpm, w, **opts):
@@ -403,9 +415,11 @@ def test_resume_in_a_new_simulation(tpm, orc):
     planets' internal Jacobi state passes through heliocentric coordinates
     once more, which may round, so the continuation is held to the parity bar
     rather than to bit equality: identical removal steps (offset by the first
-    leg) and positions within max(1e-11, 100 x the oracle's one-ulp spread of
-    the whole run).  (Here the round trip happens to be exact and the results
-    are bit-identical.)"""
+    leg) and states within the parity bar of the whole run (plain 1e-11 for
+    regular particles, 100 x the oracle's one-ulp spread for chaotic ones).
+    (Here the round trip happens to be exact and the results are
+    bit-identical.)  tpm_get_state / tpm_set_state carry the internal state
+    itself and resume bit for bit."""
     w = W.giants_100k(n=2000, seed=5)
     T1, T2 = 400, 600
     full = _run(tpm, w, T1 + T2)
@@ -437,7 +451,8 @@ def test_time_reversal(tpm, orc):
     planets back to their initial states.  The oracle's own there-and-back run
     from the same initial state agrees with the GPU's, particle by particle,
     within max(1e-11, 100 x the oracle's response to one-ulp changes of the
-    particle's and the first planet's initial positions)."""
+    particle's and the first planet's initial positions), and within the plain
+    1e-11 wherever that response is at most 1e-12."""
     w = W.giants_100k(n=2048, seed=9)
     T = 1000
     s = _sim(tpm, w)
@@ -473,10 +488,13 @@ def test_time_reversal(tpm, orc):
         spread = np.maximum(spread, sp)
     rel = np.linalg.norm(back["r"] - ref, axis=1) / np.linalg.norm(ref, axis=1)
     cmp_ = ok & np.isfinite(spread)
-    bound = np.maximum(POS_TOL, 100 * spread)
-    print(f"reversal vs oracle: max rel {rel[cmp_].max():.2e}, max err/bound "
+    regular = cmp_ & (spread <= REGULAR_SPREAD)
+    bound = np.where(regular, POS_TOL, np.maximum(POS_TOL, CHAOS_FACTOR * spread))
+    print(f"reversal vs oracle: max rel {rel[cmp_].max():.2e}, regular {regular.sum()} "
+          f"(max rel {rel[regular].max():.2e}), chaotic {np.sum(cmp_ & ~regular)}, max err/bound "
           f"{(rel[cmp_] / bound[cmp_]).max():.3f} over {cmp_.sum()} particles", flush=True)
     assert cmp_.sum() > 0.9 * ok.sum()
+    assert np.all(rel[regular] <= POS_TOL)
     assert np.all(rel[cmp_] <= bound[cmp_])
 
 
@@ -513,8 +531,8 @@ def test_single_planet_full_length(tpm, orc):
     """The single-planet workload at its full length, 1,024 particles for
     10,000 steps of 0.5 yr (about 420 orbits of the planet), end to end.  By
     then most orbits near the planet have amplified a one-ulp change of their
-    initial state far beyond 1e-12 (up to 1e-4), so positions are held only to
-    max(1e-11, 100 x that spread) and the plain-bar fraction is not required.
+    initial state far beyond 1e-12 (up to 1e-4): those are held to
+    max(1e-11, 100 x that spread), the regular rest to the plain 1e-11.
     The removal records stay unique (no record of the oracle's run moves
     under those one-ulp changes) and must be identical."""
     w = W.single_planet()
@@ -523,7 +541,7 @@ def test_single_planet_full_length(tpm, orc):
     eph = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, T, w.dt)
     res, near, spread = _oracle_reference(orc, w, T, eph.table)
     assert np.sum(res.reason != 0) > 100
-    _compare(g, res, near, spread, "single_planet/full", plain_frac=0.0)
+    _compare(g, res, near, spread, "single_planet/full")
 
 
 def test_full_size_resonant_sampled(tpm, orc):
