@@ -18,6 +18,9 @@ Entry points (each cites the passage of Zhang & Gladman 2021 it follows):
 * :func:`tangent`, :func:`stm`, :func:`adjoint` - the exact derivative of the
   discrete particle map by the complex-step method (Squire & Trapp 1998).
 * :func:`kepler_solve`, :func:`kepler_fixedk`, :func:`drift` - unit pieces.
+* :func:`count_ops`, :func:`flops_per_step` - the FP64 operation count of one
+  particle step of the method (the algorithmic work of the throughput
+  roofline), tallied on the oracle's own step.
 """
 from __future__ import annotations
 
@@ -73,6 +76,8 @@ def _load():
         lib.orc_max_threads.restype = i
         lib.orc_tangent.argtypes = [d, i, P, P, d, P, i64, d, i, d, i64, P, P, P, P, P, P, i]
         lib.orc_tangent.restype = None
+        lib.orc_count_ops.argtypes = [d, i, P, P, d, P, d, i, d, i64, P, P, P]
+        lib.orc_count_ops.restype = i64
         _lib = lib
     return _lib
 
@@ -225,6 +230,43 @@ def adjoint(mu0, mu, rcrit, rmax, table, dt, r, v, gr, gv, nsteps=None, kepler_i
     lam = np.concatenate([_f64(gr).reshape(-1, 3), _f64(gv).reshape(-1, 3)], axis=1)
     g = np.einsum("nij,ni->nj", M, lam)
     return g[:, :3], g[:, 3:]
+
+
+# ------------------------------------------------------- operation count
+# FP64 flops per counted operation (the rule of the throughput roofline):
+# add, subtract and multiply 1; a reciprocal 9 (a hardware estimate and two
+# Newton steps y + y (1 - b y) of two FMAs each); a square root 12 (a
+# reciprocal-square-root estimate, two Newton steps of one multiply and two
+# FMAs, one multiply by x); a sine-cosine pair 39 (a two-constant reduction by
+# pi/2 of one multiply and two FMAs, x^2, two degree-8 polynomials in x^2 by
+# Horner's rule, one multiply by x).  FMA = 2 flops.
+OP_WEIGHTS = {"add": 1, "mul": 1, "rcp": 9, "sqrt": 12, "sincos": 39}
+
+
+def count_ops(mu0, mu, rcrit, rmax, table, dt, r, v, kepler_iters=5, ftol=KEPLER_FTOL):
+    """Operations of one step of the method's particle map, per particle
+    (adds, multiplies, reciprocals, square roots, sine-cosine pairs; rows of -1
+    for particles removed within two steps), tallied by running the oracle's
+    own particle step on a counting number type.  table needs three rows."""
+    mu = _f64(mu).reshape(-1)
+    npl = mu.shape[0]
+    rcrit = _f64(rcrit).reshape(-1)
+    table = _f64(table)
+    assert table.shape[0] >= 3 and table.shape[1] == 3 * npl + 3
+    r, v = _f64(r).reshape(-1, 3), _f64(v).reshape(-1, 3)
+    n = r.shape[0]
+    out = np.zeros((n, 5), np.int64)
+    _load().orc_count_ops(float(mu0), npl, _ptr(mu), _ptr(rcrit), float(rmax), _ptr(table),
+                          float(dt), int(kepler_iters), float(ftol), n, _ptr(r), _ptr(v), _ptr(out))
+    return out
+
+
+def flops_per_step(counts) -> float:
+    """Mean FP64 flops of one particle step from count_ops rows (OP_WEIGHTS)."""
+    c = np.asarray(counts)
+    c = c[c[:, 0] >= 0]
+    w = np.array([OP_WEIGHTS[k] for k in ("add", "mul", "rcp", "sqrt", "sincos")])
+    return float((c @ w).mean())
 
 
 # ----------------------------------------------------- textbook element helpers

@@ -53,6 +53,101 @@ inline double re(const cplx& x) { return x.real(); }
 
 const double kTwoPi = 2.0 * M_PI;
 
+// ---------------------------------------------------------------------------
+// Operation count of the method's particle step (for the throughput roofline;
+// nothing here changes a computed value).  Counted carries a double; while a
+// count is on, each add, subtract and multiply is tallied, and each distinct
+// reciprocal (x / y counts one reciprocal of y and one multiply), square root
+// and sine-cosine pair once per stretch between restarts (count_boundary), so that
+// values this plain source evaluates more than once (the three components of
+// one force divided by one |d|^3; sin and cos of one Newton iterate in both F
+// and F'; 1/mu in v^2/mu and alpha/mu) count once.  Negation and comparisons
+// are free.
+// ---------------------------------------------------------------------------
+struct OpTally {
+  int64_t add = 0, mul = 0, rcp = 0, sqrt = 0, sincos = 0;
+  std::vector<double> rcp_seen, sqrt_seen, sc_seen;
+  bool on = false;
+  bool first(std::vector<double>& seen, double v) {
+    for (double x : seen)
+      if (x == v) return false;
+    seen.push_back(v);
+    return true;
+  }
+};
+thread_local OpTally g_tally;
+
+struct Counted {
+  double v;
+  Counted(double x = 0.0) : v(x) {}
+};
+inline double re(const Counted& x) { return x.v; }
+inline Counted operator+(const Counted& a, const Counted& b) {
+  if (g_tally.on) g_tally.add++;
+  return a.v + b.v;
+}
+inline Counted operator-(const Counted& a, const Counted& b) {
+  if (g_tally.on) g_tally.add++;
+  return a.v - b.v;
+}
+inline Counted operator-(const Counted& a) { return -a.v; }
+inline Counted operator*(const Counted& a, const Counted& b) {
+  if (g_tally.on) g_tally.mul++;
+  return a.v * b.v;
+}
+inline Counted operator/(const Counted& a, const Counted& b) {
+  if (g_tally.on) {
+    g_tally.mul++;
+    if (g_tally.first(g_tally.rcp_seen, b.v)) g_tally.rcp++;
+  }
+  return a.v / b.v;
+}
+inline Counted& operator+=(Counted& a, const Counted& b) { return a = a + b; }
+
+// sqrt, sin and cos of the templates below: the library routines for double
+// and complex, the tallied forms for Counted.
+template <class T>
+inline T tsqrt(const T& x) { return std::sqrt(x); }
+template <class T>
+inline T tsin(const T& x) { return std::sin(x); }
+template <class T>
+inline T tcos(const T& x) { return std::cos(x); }
+inline Counted tsqrt(const Counted& x) {
+  if (g_tally.on && g_tally.first(g_tally.sqrt_seen, x.v)) g_tally.sqrt++;
+  return std::sqrt(x.v);
+}
+inline Counted tsin(const Counted& x) {
+  if (g_tally.on && g_tally.first(g_tally.sc_seen, x.v)) g_tally.sincos++;
+  return std::sin(x.v);
+}
+inline Counted tcos(const Counted& x) {
+  if (g_tally.on && g_tally.first(g_tally.sc_seen, x.v)) g_tally.sincos++;
+  return std::cos(x.v);
+}
+
+// Each step, and each Newton iterate within it, is a new evaluation of the
+// method, even where rounding repeats a value: the repeat tally restarts at
+// each of them (a no-op for the other number types).
+inline void count_boundary(const double&) {}
+inline void count_boundary(const cplx&) {}
+inline void count_boundary(const Counted&) {
+  g_tally.rcp_seen.clear();
+  g_tally.sqrt_seen.clear();
+  g_tally.sc_seen.clear();
+}
+
+// The count follows the method, whose drift takes its state from the fixed-k
+// iterate x_k; this oracle's own converged re-solve (kep_solve) is left out of
+// it and the counted drift continues from x_k.
+template <class T>
+struct MethodOnly {
+  static constexpr bool value = false;
+};
+template <>
+struct MethodOnly<Counted> {
+  static constexpr bool value = true;
+};
+
 enum { ACTIVE = 0, ENCOUNTER = 1, ESCAPE = 2, KEPLER = 3 };
 
 // ---------------------------------------------------------------------------
@@ -63,11 +158,11 @@ enum { ACTIVE = 0, ENCOUNTER = 1, ESCAPE = 2, KEPLER = 3 };
 // ---------------------------------------------------------------------------
 template <class T>
 inline T kep_F(const T& x, const T& ec, const T& es, const T& dM) {
-  return x - ec * std::sin(x) + es * (1.0 - std::cos(x)) - dM;
+  return x - ec * tsin(x) + es * (1.0 - tcos(x)) - dM;
 }
 template <class T>
 inline T kep_dF(const T& x, const T& ec, const T& es) {
-  return 1.0 - ec * std::cos(x) + es * std::sin(x);
+  return 1.0 - ec * tcos(x) + es * tsin(x);
 }
 
 // Fixed-k reference iteration (sec. 2.2: a fixed number of Newton iterations,
@@ -81,7 +176,11 @@ T kep_fixedk(const T& ec, const T& es, const T& dM, int k) {
   double w = 2.0 * (std::fabs(re(ec)) + std::fabs(re(es)));
   if (re(x) > re(dM) + w) x = dM + w;
   if (re(x) < re(dM) - w) x = dM - w;
-  for (int i = 0; i < k; ++i) x = x - kep_F(x, ec, es, dM) / kep_dF(x, ec, es);
+  for (int i = 0; i < k; ++i) {
+    count_boundary(x);
+    x = x - kep_F(x, ec, es, dM) / kep_dF(x, ec, es);
+  }
+  count_boundary(x);
   return x;
 }
 
@@ -125,15 +224,15 @@ struct KepOut {
 // iteration leaves |F(x_k)| > ftol (kfix < 0 skips that test).
 template <class T>
 int drift(double mu, T r[3], T v[3], double dt, int kfix, double ftol, KepOut* dbg = nullptr) {
-  T r0 = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  T r0 = tsqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
   T v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
   T u = r[0] * v[0] + r[1] * v[1] + r[2] * v[2];
   T alpha = 2.0 / r0 - v2 / mu;            // 1/a
   if (!(re(alpha) > 0.0)) return 0;
   T a = 1.0 / alpha;
-  T n = std::sqrt(mu * alpha) * alpha;     // sqrt(mu / a^3)
+  T n = tsqrt(mu * alpha) * alpha;         // sqrt(mu / a^3)
   T ec = 1.0 - r0 * alpha;                 // e cos E0
-  T es = u * std::sqrt(alpha / mu);        // e sin E0
+  T es = u * tsqrt(alpha / mu);            // e sin E0
   T dM = n * dt;
   T dte = dt;
   double q = std::rint(re(dM) / kTwoPi);
@@ -141,12 +240,13 @@ int drift(double mu, T r[3], T v[3], double dt, int kfix, double ftol, KepOut* d
     dM = dM - q * kTwoPi;
     dte = dM / n;
   }
+  T xk = dM;
   if (kfix >= 0) {
-    T xk = kep_fixedk(ec, es, dM, kfix);
+    xk = kep_fixedk(ec, es, dM, kfix);
     if (!(std::fabs(re(kep_F(xk, ec, es, dM))) <= ftol)) return 0;
   }
-  T x = kep_solve(ec, es, dM, nullptr);
-  T s = std::sin(x), c = std::cos(x);
+  T x = MethodOnly<T>::value ? xk : kep_solve(ec, es, dM, nullptr);
+  T s = tsin(x), c = tcos(x);
   T r1 = a * (1.0 - ec * c + es * s);
   T f = 1.0 + (a / r0) * (c - 1.0);
   T g = dte + (s - x) / n;
@@ -178,7 +278,7 @@ int kick_accel(const double* row, int np, const double* mu, const double* rcrit,
     T d[3];
     for (int k = 0; k < 3; ++k) d[k] = r[k] - row[3 * j + k];
     T d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    T dist = std::sqrt(d2);
+    T dist = tsqrt(d2);
     if (hit < 0 && re(dist) < rcrit[j]) hit = j;
     T d3 = d2 * dist;
     for (int k = 0; k < 3; ++k) acc[k] = acc[k] - mu[j] * d[k] / d3;
@@ -205,11 +305,12 @@ Deact run_particle(double mu0, int np, const double* mu, const double* rcrit, do
   int hit = kick_accel(table, np, mu, rcrit, r, acc);
   auto escaped = [&](const T* rr) {
     T r2 = rr[0] * rr[0] + rr[1] * rr[1] + rr[2] * rr[2];
-    return rmax > 0.0 && re(std::sqrt(r2)) > rmax;
+    return rmax > 0.0 && re(tsqrt(r2)) > rmax;
   };
   if (hit >= 0) return {step0, ENCOUNTER, hit};
   if (escaped(r)) return {step0, ESCAPE, -1};
   for (int64_t i = 0; i < nsteps; ++i) {
+    count_boundary(r[0]);
     T rn[3], vn[3];
     for (int k = 0; k < 3; ++k) { rn[k] = r[k]; vn[k] = v[k] + h * acc[k]; }
     if (!drift(mu0, rn, vn, dt, kfix, ftol)) return {step0 + i, KEPLER, -1};
@@ -414,6 +515,40 @@ double orc_particles(double mu0, int np, const double* mu, const double* rcrit, 
   }
   auto t1 = std::chrono::steady_clock::now();
   return std::chrono::duration<double>(t1 - t0).count();
+}
+
+// Operations of one particle step of the method, per particle: the tally of
+// run_particle over two steps less that over one (the steady state, in which
+// the acceleration that ends a step also opens the next), for particles that
+// stay active through both (Counted above says what is tallied).  out[5 i ..]
+// = adds, multiplies, reciprocals, square roots, sine-cosine pairs; returns
+// the number of particles counted (the others get -1).
+int64_t orc_count_ops(double mu0, int np, const double* mu, const double* rcrit, double rmax,
+                      const double* table, double dt, int kfix, double ftol, int64_t n,
+                      const double* r, const double* v, int64_t* out) {
+  int64_t counted = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t t[2][5];
+    bool ok = true;
+    for (int steps = 1; steps <= 2; ++steps) {
+      Counted rc[3], vc[3];
+      for (int k = 0; k < 3; ++k) { rc[k] = r[3 * i + k]; vc[k] = v[3 * i + k]; }
+      g_tally = OpTally();
+      g_tally.on = true;
+      Deact d = run_particle<Counted>(mu0, np, mu, rcrit, rmax, table, steps, dt, 0, kfix, ftol,
+                                      rc, vc);
+      g_tally.on = false;
+      ok = ok && d.reason == ACTIVE;
+      t[steps - 1][0] = g_tally.add;
+      t[steps - 1][1] = g_tally.mul;
+      t[steps - 1][2] = g_tally.rcp;
+      t[steps - 1][3] = g_tally.sqrt;
+      t[steps - 1][4] = g_tally.sincos;
+    }
+    for (int k = 0; k < 5; ++k) out[5 * i + k] = ok ? t[1][k] - t[0][k] : -1;
+    counted += ok ? 1 : 0;
+  }
+  return counted;
 }
 
 // Number of OpenMP threads a parallel region would use.

@@ -28,3 +28,14 @@ def test_default_chunk_layout():
     assert bench.default_chunks(20000) == [1024, 8192, 8192, 2592]
     chunks = bench.default_chunks(1_000_000)
     assert sum(chunks) == 1_000_000 and len(chunks) == 123 and chunks[0] == 1024
+
+
+def test_algorithmic_flops_match_the_oracle_tally(orc):
+    """The roofline's algorithmic flops per particle-step are the oracle's own
+    step tallied and weighted (oracle.count_ops / flops_per_step)."""
+    from paper_2011_03484_amd import workloads as W
+    w = W.giants_100k(n=200, seed=8)
+    eph = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, 2, w.dt)
+    c = orc.count_ops(w.mu0, w.mu, w.rcrit, w.rmax, eph.table, w.dt, w.r, w.v,
+                      kepler_iters=w.kepler_iters)
+    assert bench.ALGORITHMIC_FLOPS_PER_PARTICLE_STEP[w.np_] == orc.flops_per_step(c)

@@ -596,3 +596,35 @@ def test_planetless_stm_matches_extended_precision_differences(orc):
             ref[:, c] = [float((fp[k] - fm[k]) / (2 * h)) for k in range(6)]
         err = np.max(np.abs(M[i] - ref)) / np.max(np.abs(ref))
         assert err < 1e-11, (i, err)
+
+
+# ------------------------------------------------------------ operation count
+def test_operation_count_per_planet_and_newton_step(orc):
+    """The tally behind the throughput roofline's algorithmic flops follows
+    the source of the step (sec. 2.2 kick equation and Kepler drift): each
+    planet term costs 8 adds, 10 multiplies, one reciprocal and one square
+    root; each Newton step of the fixed-count solve 7 adds, 5 multiplies, one
+    reciprocal and one sine-cosine pair (F and F' of one iterate share it);
+    the drift outside its Newton steps one more sine-cosine pair (the residual
+    test and f, g at x_k).  Checked as differences: one planet fewer, one
+    Newton step more, and k -> 0."""
+    w = W.giants_100k(n=300, seed=4)
+    eph = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, 2, w.dt)
+    base = orc.count_ops(w.mu0, w.mu, w.rcrit, w.rmax, eph.table, w.dt, w.r, w.v)
+    ok = base[:, 0] >= 0
+    assert ok.sum() > 250
+    more = orc.count_ops(w.mu0, w.mu, w.rcrit, w.rmax, eph.table, w.dt, w.r, w.v, kepler_iters=6)
+    assert np.all(more[ok] - base[ok] == [7, 5, 1, 0, 1])
+    zero = orc.count_ops(w.mu0, w.mu, w.rcrit, w.rmax, eph.table, w.dt, w.r, w.v, kepler_iters=0,
+                         ftol=1.0)
+    assert np.all(base[ok] - zero[ok] == [35, 25, 5, 0, 5])
+    # the outermost planet's column dropped from the same table
+    t3 = np.concatenate([eph.table[:, :9], eph.table[:, 12:]], axis=1)
+    fewer = orc.count_ops(w.mu0, w.mu[:3], w.rcrit[:3], w.rmax, t3, w.dt, w.r, w.v)
+    both = ok & (fewer[:, 0] >= 0)
+    assert np.all(base[both] - fewer[both] == [8, 10, 1, 1, 0])
+    assert np.all(zero[ok][:, 4] == 1)
+    flops = orc.flops_per_step(base)
+    print(f"giants_100k, 4 planets, 5 Newton steps: {base[ok][0].tolist()} -> {flops:.0f} flops",
+          flush=True)
+    assert flops == 721.0
