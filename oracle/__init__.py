@@ -18,6 +18,10 @@ Entry points (each cites the passage of Zhang & Gladman 2021 it follows):
 * :func:`tangent`, :func:`stm`, :func:`adjoint` - the exact derivative of the
   discrete particle map by the complex-step method (Squire & Trapp 1998).
 * :func:`kepler_solve`, :func:`kepler_fixedk`, :func:`drift` - unit pieces.
+* :func:`elements`, :func:`mean_longitudes`, :func:`diagnostics` - osculating
+  elements and the sampled diagnostics of the applications: e_max and its
+  step (sec. 3.3), resonant angles and the 10-degree libration criterion
+  (sec. 4.1, 4.2).
 * :func:`count_ops`, :func:`flops_per_step` - the FP64 operation count of one
   particle step of the method (the algorithmic work of the throughput
   roofline), tallied on the oracle's own step.
@@ -68,7 +72,7 @@ def _load():
         lib.orc_kepler_fixedk.restype = d
         lib.orc_drift.argtypes = [d, P, P, d, i, d, P]
         lib.orc_drift.restype = i
-        lib.orc_ephemeris.argtypes = [d, i, P, P, P, i64, d, P, P, P]
+        lib.orc_ephemeris.argtypes = [d, i, P, P, P, i64, d, P, P, P, P]
         lib.orc_ephemeris.restype = i64
         lib.orc_particles.argtypes = [d, i, P, P, d, P, i64, d, i64, i, d, i64, P, P, P, P, P, i]
         lib.orc_particles.restype = d
@@ -78,6 +82,13 @@ def _load():
         lib.orc_tangent.restype = None
         lib.orc_count_ops.argtypes = [d, i, P, P, d, P, d, i, d, i64, P, P, P]
         lib.orc_count_ops.restype = i64
+        lib.orc_particles_diag.argtypes = [d, i, P, P, d, P, i64, d, i64, i, d, i64, P, P, P, P, P,
+                                           i, i64, P, i, P, P, P, P, P, P, P]
+        lib.orc_particles_diag.restype = d
+        lib.orc_elements.argtypes = [d, i64, P, P, P]
+        lib.orc_elements.restype = None
+        lib.orc_mean_longitudes.argtypes = [d, i64, P, P, P]
+        lib.orc_mean_longitudes.restype = None
         _lib = lib
     return _lib
 
@@ -124,21 +135,24 @@ class Ephemeris:
     r_final: np.ndarray     # (np, 3)
     v_final: np.ndarray     # (np, 3)
     flag: int               # -1 ok; >= 0 first step with a planet pair inside a mutual Hill radius; -2 drift failure
+    vtable: np.ndarray | None = None   # (nsteps+1, 3np) heliocentric planet velocities, if asked for
 
 
-def ephemeris(mu0: float, mu, rp, vp, nsteps: int, dt: float, keep_table: bool = True) -> Ephemeris:
+def ephemeris(mu0: float, mu, rp, vp, nsteps: int, dt: float, keep_table: bool = True,
+              keep_velocities: bool = False) -> Ephemeris:
     """Planet table by the Jacobi Wisdom-Holman map (sec. 2.2)."""
     mu = _f64(mu).reshape(-1)
     npl = mu.shape[0]
     rp = _f64(rp, (npl, 3))
     vp = _f64(vp, (npl, 3))
     table = np.zeros((nsteps + 1, 3 * npl + 3)) if keep_table else None
+    vtable = np.zeros((nsteps + 1, 3 * npl)) if keep_velocities else None
     rf = np.zeros((npl, 3))
     vf = np.zeros((npl, 3))
     flag = _load().orc_ephemeris(float(mu0), npl, _ptr(mu), _ptr(rp), _ptr(vp), int(nsteps),
                                  float(dt), _ptr(table) if table is not None else None,
-                                 _ptr(rf), _ptr(vf))
-    return Ephemeris(table, rf, vf, int(flag))
+                                 _ptr(rf), _ptr(vf), _ptr(vtable) if vtable is not None else None)
+    return Ephemeris(table, rf, vf, int(flag), vtable)
 
 
 # ------------------------------------------------------------------ particles
@@ -230,6 +244,75 @@ def adjoint(mu0, mu, rcrit, rmax, table, dt, r, v, gr, gv, nsteps=None, kepler_i
     lam = np.concatenate([_f64(gr).reshape(-1, 3), _f64(gv).reshape(-1, 3)], axis=1)
     g = np.einsum("nij,ni->nj", M, lam)
     return g[:, :3], g[:, 3:]
+
+
+# ------------------------------------------------------------- diagnostics
+def elements(mu: float, r, v) -> np.ndarray:
+    """Osculating heliocentric elements (a, e, inc, node, peri, M) of states
+    about mu, (n, 6), by the textbook two-body relations."""
+    r, v = _f64(r).reshape(-1, 3), _f64(v).reshape(-1, 3)
+    out = np.zeros((r.shape[0], 6))
+    _load().orc_elements(float(mu), r.shape[0], _ptr(r), _ptr(v), _ptr(out))
+    return out
+
+
+def mean_longitudes(mu: float, r, v) -> np.ndarray:
+    """Mean longitudes node + peri + M of states about mu."""
+    r, v = _f64(r).reshape(-1, 3), _f64(v).reshape(-1, 3)
+    out = np.zeros(r.shape[0])
+    _load().orc_mean_longitudes(float(mu), r.shape[0], _ptr(r), _ptr(v), _ptr(out))
+    return out
+
+
+@dataclass
+class Diagnostics:
+    result: Result
+    emax: np.ndarray        # largest sampled osculating e (-1 if never sampled)
+    emax_step: np.ndarray   # first sample step reaching it (-1)
+    flags: np.ndarray       # (n, nres): bit 0 phi within 10 deg of 0, bit 1 within 10 deg of 180
+    lo: np.ndarray          # (n, nres): range of phi - 180 deg over the samples, radians
+    hi: np.ndarray
+
+
+def diagnostics(mu0, mu, rcrit, rmax, eph: Ephemeris, dt, r, v, nsteps, every, ref=None,
+                resonances=(), kepler_iters=5, ftol=KEPLER_FTOL, nthreads=0) -> Diagnostics:
+    """Particles through eph.table with the sampled diagnostics of the
+    applications: e_max and its step (sec. 3.3), and for each resonance (p, q)
+    with planet `ref` the resonant angle p lambda - q lambda_ref - (p - q) varpi
+    (sec. 4.1) against the 10-degree libration criterion (sec. 4.2).  Samples
+    at step boundaries that are multiples of `every`; the planet's elements use
+    mu0 + mu_ref and need eph made with keep_velocities."""
+    mu = _f64(mu).reshape(-1)
+    npl = mu.shape[0]
+    rcrit = _f64(rcrit).reshape(-1)
+    table = _f64(eph.table)
+    r = _f64(r).reshape(-1, 3).copy()
+    v = _f64(v).reshape(-1, 3).copy()
+    n = r.shape[0]
+    nres = len(resonances)
+    assert nres <= 2 and every > 0
+    lam_rows = None
+    if nres:
+        j = int(ref)
+        lam_rows = mean_longitudes(mu0 + mu[j], table[:nsteps + 1, 3 * j:3 * j + 3],
+                                   eph.vtable[:nsteps + 1, 3 * j:3 * j + 3])
+    pq = np.array([x for x, _ in resonances] or [0], np.int32)
+    qq = np.array([y for _, y in resonances] or [0], np.int32)
+    ds = np.zeros(n, np.int64)
+    rs = np.zeros(n, np.int32)
+    pl = np.zeros(n, np.int32)
+    emax = np.zeros(n)
+    estep = np.zeros(n, np.int64)
+    flags = np.zeros((n, max(nres, 1)), np.int32)
+    lo = np.zeros((n, max(nres, 1)))
+    hi = np.zeros((n, max(nres, 1)))
+    secs = _load().orc_particles_diag(
+        float(mu0), npl, _ptr(mu), _ptr(rcrit), float(rmax), _ptr(table), int(nsteps), float(dt),
+        0, int(kepler_iters), float(ftol), n, _ptr(r), _ptr(v), _ptr(ds), _ptr(rs), _ptr(pl),
+        int(nthreads), int(every), _ptr(lam_rows) if lam_rows is not None else None, nres,
+        _ptr(pq), _ptr(qq), _ptr(emax), _ptr(estep), _ptr(flags), _ptr(lo), _ptr(hi))
+    return Diagnostics(Result(r, v, ds, rs, pl, secs), emax, estep, flags[:, :nres], lo[:, :nres],
+                       hi[:, :nres])
 
 
 # ------------------------------------------------------- operation count

@@ -295,10 +295,17 @@ struct Deact {
 // One particle through rows 0..nsteps of a table that starts at global step
 // step0.  Checks run at every boundary on the synchronised state; on a hit the
 // state of that boundary is kept.
-template <class T>
+// smp(n, row, r, v) is called at every boundary n = step0 + row that the
+// particle passes while active (the diagnostics below; nothing by default).
+struct NoSample {
+  template <class T>
+  void operator()(int64_t, int64_t, const T*, const T*) const {}
+};
+
+template <class T, class S = NoSample>
 Deact run_particle(double mu0, int np, const double* mu, const double* rcrit, double rmax,
                    const double* table, int64_t nsteps, double dt, int64_t step0,
-                   int kfix, double ftol, T r[3], T v[3]) {
+                   int kfix, double ftol, T r[3], T v[3], S&& smp = S()) {
   const int rowlen = 3 * np + 3;
   const double h = 0.5 * dt;
   T acc[3];
@@ -309,6 +316,7 @@ Deact run_particle(double mu0, int np, const double* mu, const double* rcrit, do
   };
   if (hit >= 0) return {step0, ENCOUNTER, hit};
   if (escaped(r)) return {step0, ESCAPE, -1};
+  smp(step0, 0, r, v);
   for (int64_t i = 0; i < nsteps; ++i) {
     count_boundary(r[0]);
     T rn[3], vn[3];
@@ -318,9 +326,110 @@ Deact run_particle(double mu0, int np, const double* mu, const double* rcrit, do
     for (int k = 0; k < 3; ++k) { r[k] = rn[k]; v[k] = vn[k] + h * acc[k]; }
     if (hit >= 0) return {step0 + i + 1, ENCOUNTER, hit};
     if (escaped(r)) return {step0 + i + 1, ESCAPE, -1};
+    smp(step0 + i + 1, i + 1, r, v);
   }
   return {-1, ACTIVE, -1};
 }
+
+// ---------------------------------------------------------------------------
+// Osculating heliocentric elements of (r, v) about mu by the textbook
+// two-body relations: a = 1/(2/r - v^2/mu); e from the eccentricity vector
+// ((v^2 - mu/r) r - (r.v) v)/mu; h = r x v gives the inclination and the
+// ascending node; the argument of latitude u (node to position, in the orbit
+// plane); e cos E = 1 - r/a and e sin E = r.v / sqrt(mu a) give the eccentric
+// anomaly E and the mean anomaly M = E - e sin E; the true anomaly f follows
+// from E by f - E = 2 atan(beta sin E / (1 - beta cos E)), beta =
+// e / (1 + sqrt(1 - e^2)), and the argument of pericentre is u - f.  Written
+// this way the mean longitude node + (u - f) + M stays accurate on a circular
+// orbit, where the pericentre itself is undefined.
+// ---------------------------------------------------------------------------
+struct Elements {
+  double a, e, inc, node, peri, M;
+};
+
+Elements elements_of(double mu, const double* r, const double* v) {
+  const double rn = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const double rv = r[0] * v[0] + r[1] * v[1] + r[2] * v[2];
+  Elements el;
+  el.a = 1.0 / (2.0 / rn - v2 / mu);
+  const double h[3] = {r[1] * v[2] - r[2] * v[1], r[2] * v[0] - r[0] * v[2],
+                       r[0] * v[1] - r[1] * v[0]};
+  double ev[3];
+  for (int k = 0; k < 3; ++k) ev[k] = ((v2 - mu / rn) * r[k] - rv * v[k]) / mu;
+  el.e = std::sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
+  const double hn = std::sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+  el.inc = std::atan2(std::sqrt(h[0] * h[0] + h[1] * h[1]), h[2]);
+  el.node = std::atan2(h[0], -h[1]);
+  const double n[3] = {std::cos(el.node), std::sin(el.node), 0.0};
+  // in the orbit plane, 90 degrees ahead of the node: (h/|h|) x n
+  const double m[3] = {(h[1] * n[2] - h[2] * n[1]) / hn, (h[2] * n[0] - h[0] * n[2]) / hn,
+                       (h[0] * n[1] - h[1] * n[0]) / hn};
+  const double u = std::atan2(r[0] * m[0] + r[1] * m[1] + r[2] * m[2],
+                              r[0] * n[0] + r[1] * n[1] + r[2] * n[2]);
+  const double es = rv / std::sqrt(mu * el.a), ec = 1.0 - rn / el.a;
+  const double E = std::atan2(es, ec);
+  const double b = 1.0 + std::sqrt(1.0 - (ec * ec + es * es));
+  const double f = E + 2.0 * std::atan2(es / b, 1.0 - ec / b);
+  el.peri = u - f;
+  el.M = E - es;
+  return el;
+}
+
+// Mean longitude varpi + M (varpi = node + peri, the longitude of pericentre).
+double mean_longitude(const Elements& el) { return el.node + el.peri + el.M; }
+
+// ---------------------------------------------------------------------------
+// Diagnostics of the paper's applications, sampled at every step boundary that
+// is a multiple of `every` and that the particle reaches while active (the
+// synchronised state (r_n, v_n), after that boundary's checks):
+//  * the largest osculating eccentricity and the first sample that reached it
+//    (sec. 3.3, maximum-eccentricity figure);
+//  * for resonances (p, q) with a reference planet, the resonant angle
+//      phi = p lambda - q lambda_ref - (p - q) varpi       (sec. 4.1),
+//    with lambda the mean longitude and varpi the longitude of pericentre;
+//    bit 0 of the flags records a sample with phi within 10 degrees of 0,
+//    bit 1 one within 10 degrees of 180 degrees, so the paper's libration
+//    criterion (sec. 4.2: phi never within 10 degrees of 0, or never within 10
+//    degrees of 180) holds when the flags are not both set; lo and hi track
+//    the range of phi - 180 degrees, taken in (-180, 180] degrees.
+// ---------------------------------------------------------------------------
+const double kTenDeg = M_PI / 18.0;
+
+double wrap_angle(double x) { return std::remainder(x, kTwoPi); }
+
+struct DiagSampler {
+  double mu0;
+  int64_t every;
+  const double* lam_rows;      // lambda of the reference planet per table row (may be null)
+  int nres;
+  const int* p;
+  const int* q;
+  double* emax;
+  int64_t* emax_step;
+  int32_t* flags;
+  double* lo;
+  double* hi;
+  void operator()(int64_t n, int64_t row, const double* r, const double* v) const {
+    if (n % every != 0) return;
+    const Elements el = elements_of(mu0, r, v);
+    if (el.e > *emax) {
+      *emax = el.e;
+      *emax_step = n;
+    }
+    if (!lam_rows) return;
+    const double varpi = el.node + el.peri;
+    const double lam = varpi + el.M;
+    for (int k = 0; k < nres; ++k) {
+      const double phi = p[k] * lam - q[k] * lam_rows[row] - (p[k] - q[k]) * varpi;
+      const double w0 = wrap_angle(phi), w180 = wrap_angle(phi - M_PI);
+      if (std::fabs(w0) < kTenDeg) flags[k] |= 1;
+      if (std::fabs(w180) < kTenDeg) flags[k] |= 2;
+      lo[k] = std::fmin(lo[k], w180);
+      hi[k] = std::fmax(hi[k], w180);
+    }
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Planet ephemeris: Wisdom-Holman map in Jacobi coordinates (sec. 2.2; Jacobi
@@ -439,11 +548,13 @@ int orc_drift(double mu, double* r, double* v, double dt, int kfix, double ftol,
 
 // ----------------------------- planet ephemeris -----------------------------
 // mu0; np planets with mu[np], heliocentric r[np*3], v[np*3] (sorted by a).
-// Writes table[(nsteps+1) * (3np+3)] (row n = state at t_n) and the final
-// heliocentric r_out, v_out.  Returns the first step at which two planets were
+// Writes table[(nsteps+1) * (3np+3)] (row n = state at t_n), the final
+// heliocentric r_out, v_out and, if vtable is not null, the heliocentric
+// planet velocities vtable[(nsteps+1) * 3np].  Returns the first step at which two planets were
 // within a mutual Hill radius, -2 if a planet's drift failed, else -1.
 int64_t orc_ephemeris(double mu0, int np, const double* mu, const double* r, const double* v,
-                      int64_t nsteps, double dt, double* table, double* r_out, double* v_out) {
+                      int64_t nsteps, double dt, double* table, double* r_out, double* v_out,
+                      double* vtable) {
   Planets P;
   P.np = np;
   P.mu0 = mu0;
@@ -467,6 +578,7 @@ int64_t orc_ephemeris(double mu0, int np, const double* mu, const double* r, con
   const int rowlen = 3 * np + 3;
   int64_t flag = -1;
   if (table) write_row(P, table);
+  if (vtable) jacobi_to_helio(P, P.vj.data(), vtable);
   {
     std::vector<double> rh(3 * np);
     jacobi_to_helio(P, P.rj.data(), rh.data());
@@ -485,6 +597,7 @@ int64_t orc_ephemeris(double mu0, int np, const double* mu, const double* r, con
     jacobi_int_accel(P, P.rj.data(), aj.data());
     for (int i = 0; i < 3 * np; ++i) P.vj[i] = P.vj[i] + h * aj[i];
     if (table) write_row(P, table + (s + 1) * rowlen);
+    if (vtable) jacobi_to_helio(P, P.vj.data(), vtable + (s + 1) * 3 * np);
     jacobi_to_helio(P, P.rj.data(), rh.data());
     if (flag == -1 && np > 1 && planets_too_close(P, rh.data())) flag = s + 1;
   }
@@ -549,6 +662,57 @@ int64_t orc_count_ops(double mu0, int np, const double* mu, const double* rcrit,
     counted += ok ? 1 : 0;
   }
   return counted;
+}
+
+// orc_particles with the diagnostics above: every > 0; lam_rows[nsteps + 1]
+// (mean longitude of the reference planet at each table row, read at sample
+// rows; null for e_max only); nres <= 2 resonances p[k]:q[k].  Outputs per
+// particle: emax (-1 without a sample), emax_step (-1), flags[n][nres],
+// lo[n][nres], hi[n][nres] (radians; +inf / -inf without a sample).
+double orc_particles_diag(double mu0, int np, const double* mu, const double* rcrit, double rmax,
+                          const double* table, int64_t nsteps, double dt, int64_t step0, int kfix,
+                          double ftol, int64_t n, double* r, double* v, int64_t* deact_step,
+                          int32_t* reason, int32_t* planet, int nthreads, int64_t every,
+                          const double* lam_rows, int nres, const int* p, const int* q,
+                          double* emax, int64_t* emax_step, int32_t* flags, double* lo,
+                          double* hi) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  auto t0 = std::chrono::steady_clock::now();
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; ++i) {
+    emax[i] = -1.0;
+    emax_step[i] = -1;
+    for (int k = 0; k < nres; ++k) {
+      flags[nres * i + k] = 0;
+      lo[nres * i + k] = INFINITY;
+      hi[nres * i + k] = -INFINITY;
+    }
+    DiagSampler smp{mu0, every, lam_rows, nres, p, q, emax + i, emax_step + i, flags + nres * i,
+                    lo + nres * i, hi + nres * i};
+    Deact d = run_particle<double>(mu0, np, mu, rcrit, rmax, table, nsteps, dt, step0, kfix,
+                                   ftol, r + 3 * i, v + 3 * i, smp);
+    deact_step[i] = d.step;
+    reason[i] = d.reason;
+    planet[i] = d.planet;
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  return std::chrono::duration<double>(t1 - t0).count();
+}
+
+// Osculating elements (a, e, inc, node, peri, M) of n states about mu: out[n][6].
+void orc_elements(double mu, int64_t n, const double* r, const double* v, double* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    const Elements el = elements_of(mu, r + 3 * i, v + 3 * i);
+    const double e6[6] = {el.a, el.e, el.inc, el.node, el.peri, el.M};
+    for (int k = 0; k < 6; ++k) out[6 * i + k] = e6[k];
+  }
+}
+
+// Mean longitudes of n states about mu.
+void orc_mean_longitudes(double mu, int64_t n, const double* r, const double* v, double* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = mean_longitude(elements_of(mu, r + 3 * i, v + 3 * i));
 }
 
 // Number of OpenMP threads a parallel region would use.

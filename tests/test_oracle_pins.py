@@ -628,3 +628,170 @@ def test_operation_count_per_planet_and_newton_step(orc):
     print(f"giants_100k, 4 planets, 5 Newton steps: {base[ok][0].tolist()} -> {flops:.0f} flops",
           flush=True)
     assert flops == 721.0
+
+
+# ---------------------------------------------------------------- diagnostics
+def _wrap(x):
+    return (np.asarray(x) + math.pi) % (2 * math.pi) - math.pi
+
+
+def test_elements_invert_the_textbook_map(orc):
+    """Osculating elements (used by the applications' diagnostics, sec. 3.3
+    and 4.1) recover the elements that the generators' textbook map turned
+    into states: a and e to 1e-13 relative, the angles to 1e-10 rad (e and i
+    kept away from zero, where node and pericentre are undefined)."""
+    rng = np.random.default_rng(31)
+    n = 3000
+    a = rng.uniform(1, 100, n)
+    e = rng.uniform(0.01, 0.9, n)
+    inc = rng.uniform(0.01, 3.1, n)
+    node, peri, M = (rng.uniform(-math.pi, math.pi, n) for _ in range(3))
+    for mu in (W.MU_SUN, W.MU_SUN * 1.001):
+        r, v = W.elements_to_cartesian(mu, a, e, inc, node, peri, M)
+        el = orc.elements(mu, r, v)
+        assert np.max(np.abs(el[:, 0] / a - 1)) < 1e-13
+        assert np.max(np.abs(el[:, 1] - e)) < 1e-13
+        assert np.max(np.abs(el[:, 2] - inc)) < 1e-10
+        for k, ref in ((3, node), (4, peri), (5, M)):
+            assert np.max(np.abs(_wrap(el[:, k] - ref))) < 1e-9, k
+        lam = orc.mean_longitudes(mu, r, v)
+        assert np.max(np.abs(_wrap(lam - (node + peri + M)))) < 1e-9
+
+
+def test_resonant_angle_flags_match_the_closed_form(orc):
+    """sec. 4.1-4.2: with a planet of negligible mass (1e-13 of the star) on a
+    circular orbit both orbits are two-body ones, so phi = p lambda - q
+    lambda_p - (p - q) varpi advances linearly, (p n - q n_p) per unit time,
+    from its initial value, and whether a sample falls within 10 degrees of 0
+    or of 180 degrees, and the range of phi - 180 degrees, follow in closed
+    form.  Particles on and around the 3:1 and 5:2 commensurabilities,
+    sampled every 40 steps of 300 steps; e_max equals the constant e."""
+    rng = np.random.default_rng(32)
+    mu0 = W.MU_SUN
+    ap = 30.0
+    mup = np.array([1e-13 * mu0])
+    rp, vp = W.elements_to_cartesian(mu0 + mup, np.array([ap]), np.zeros(1), np.zeros(1),
+                                     np.zeros(1), np.zeros(1), np.array([0.3]))
+    n = 400
+    a = np.concatenate([ap * 3 ** (2 / 3) * (1 + rng.uniform(-2e-3, 2e-3, n // 2)),
+                        ap * 2.5 ** (2 / 3) * (1 + rng.uniform(-2e-3, 2e-3, n // 2))])
+    e = rng.uniform(0.05, 0.4, n)
+    inc = rng.uniform(0.01, 0.3, n)
+    node, peri, M = (rng.uniform(-math.pi, math.pi, n) for _ in range(3))
+    r, v = W.elements_to_cartesian(mu0, a, e, inc, node, peri, M)
+    T, every, dt = 300 * 40, 40, 0.5
+    eph = orc.ephemeris(mu0, mup, rp, vp, T, dt, keep_velocities=True)
+    res = [(3, 1), (5, 2)]
+    d = orc.diagnostics(mu0, mup, np.zeros(1), 0.0, eph, dt, r, v, T, every, ref=0, resonances=res)
+    assert np.all(d.result.reason == 0)
+    assert np.max(np.abs(d.emax - e)) < 1e-10
+    t = np.arange(0, T + 1, every) * dt
+    nn = np.sqrt(mu0 / a ** 3)
+    npl = math.sqrt((mu0 + mup[0]) / ap ** 3)
+    lam0, lamp0, varpi = node + peri + M, 0.3, node + peri
+    checked = 0
+    for k, (p, q) in enumerate(res):
+        phi = (p * (lam0[:, None] + nn[:, None] * t) - q * (lamp0 + npl * t)
+               - (p - q) * varpi[:, None])
+        w0, w180 = _wrap(phi), _wrap(phi - math.pi)
+        clear = (np.min(np.abs(np.abs(w0) - math.radians(10)), axis=1) > 1e-6) & \
+                (np.min(np.abs(np.abs(w180) - math.radians(10)), axis=1) > 1e-6)
+        flags = (np.any(np.abs(w0) < math.radians(10), axis=1) * 1
+                 + np.any(np.abs(w180) < math.radians(10), axis=1) * 2)
+        assert np.array_equal(d.flags[clear, k], flags[clear]), (p, q)
+        ok = clear & (flags != 3) & (flags != 1)     # phi never near 0: its range is continuous
+        assert np.max(np.abs(d.lo[ok, k] - w180[ok].min(axis=1))) < 1e-7
+        assert np.max(np.abs(d.hi[ok, k] - w180[ok].max(axis=1))) < 1e-7
+        checked += clear.sum()
+        print(f"{p}:{q}: flags {np.bincount(flags[clear], minlength=4).tolist()} "
+              f"(0 none, 1 near 0, 2 near 180, 3 both) over {clear.sum()} particles", flush=True)
+        assert len(set(flags[clear])) >= 3
+    assert checked > 0.95 * 2 * n
+
+
+def test_diagnostics_match_segmented_runs(orc):
+    """Brute force: the in-loop samples equal samples taken from separate runs
+    of `every` steps each (resumed bit for bit), with the elements of their
+    states computed by the numpy textbook relations and the planet's from the
+    planet map's own end states: e_max to 1e-14 and its step (where no two
+    samples tie within 1e-12), the flags (away from the 10-degree
+    thresholds) and the range of phi - 180 degrees.  Removed particles stop
+    being sampled at their removal step."""
+    w = W.resonant_200k(n=400, seed=61)
+    every, nseg = 150, 40
+    T = every * nseg
+    eph = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, T, w.dt, keep_velocities=True)
+    res = [(3, 1), (5, 2)]
+    d = orc.diagnostics(w.mu0, w.mu, w.rcrit, w.rmax, eph, w.dt, w.r, w.v, T, every, ref=3,
+                        resonances=res)
+    r, v = w.r.copy(), w.v.copy()
+    rp, vp = w.rp.copy(), w.vp.copy()
+    alive = np.ones(w.n, bool)
+    es, lams, varpis, pl_lam = [], [], [], []
+    for k in range(nseg + 1):
+        a, e, inc, node, peri, M = orc.cartesian_to_elements(w.mu0, r, v)
+        pa = orc.cartesian_to_elements(w.mu0 + w.mu[3], rp[3], vp[3])
+        es.append(np.where(alive, e, -1.0))
+        lams.append(node + peri + M)
+        varpis.append(node + peri)
+        pl_lam.append((pa[3] + pa[4] + pa[5])[0])
+        if k == nseg:
+            break
+        seg = orc.ephemeris(w.mu0, w.mu, rp, vp, every, w.dt)
+        out = orc.particles(w.mu0, w.mu, w.rcrit, w.rmax, seg.table, w.dt, r, v, every,
+                            step0=k * every)
+        alive &= out.reason == 0
+        r, v, rp, vp = out.r, out.v, seg.r_final, seg.v_final
+    es = np.array(es)
+    assert np.array_equal(alive, d.result.reason == 0)
+    assert (~alive).sum() > 0
+    emax = es.max(axis=0)
+    assert np.max(np.abs(d.emax - emax)) < 1e-14
+    srt = np.sort(es, axis=0)
+    untied = (srt[-1] - srt[-2]) > 1e-12
+    assert np.array_equal(d.emax_step[untied], (np.argmax(es, axis=0) * every)[untied])
+    lams, varpis, pl_lam = np.array(lams), np.array(varpis), np.array(pl_lam)
+    sampled = es >= 0
+    for k, (p, q) in enumerate(res):
+        phi = p * lams - q * pl_lam[:, None] - (p - q) * varpis
+        w0, w180 = _wrap(phi), _wrap(phi - math.pi)
+        near0 = np.any(sampled & (np.abs(w0) < math.radians(10)), axis=0)
+        near180 = np.any(sampled & (np.abs(w180) < math.radians(10)), axis=0)
+        dist = np.minimum(np.abs(np.abs(w0) - math.radians(10)), np.abs(np.abs(w180) - math.radians(10)))
+        clear = np.all(~sampled | (dist > 1e-9), axis=0)
+        assert clear.mean() > 0.99
+        assert np.array_equal(d.flags[clear, k], (near0 * 1 + near180 * 2)[clear])
+        lo = np.where(sampled, w180, np.inf).min(axis=0)
+        hi = np.where(sampled, w180, -np.inf).max(axis=0)
+        ok = clear & ~near0
+        assert np.max(np.abs(d.lo[ok, k] - lo[ok])) < 1e-9
+        assert np.max(np.abs(d.hi[ok, k] - hi[ok])) < 1e-9
+
+
+def test_resonant_particle_librates_and_neighbour_circulates(orc):
+    """sec. 4.1-4.2 with the four giant planets: a particle started at the 3:1
+    resonance centre (a = 62.6 au, e = 0.25) with phi_31 = 180 degrees keeps
+    phi_31 away from 0 (librating by the 10-degree criterion) over 200,000
+    steps of 120 d (about 66,000 years, several libration periods), with its
+    range about 180 degrees well under 180 degrees; one at 58 au with the same
+    angles circulates (phi_31 passes both 0 and 180 degrees).  A sign error in
+    the resonant angle or the wrong planet would leave both circulating."""
+    w = W.giants_100k(n=1, seed=62)
+    pa = orc.cartesian_to_elements(w.mu0 + w.mu[3], w.rp[3], w.vp[3])
+    lam_n = float((pa[3] + pa[4] + pa[5])[0])
+    node, peri = 0.4, 1.1
+    varpi = node + peri
+    lam = (math.pi + lam_n + 2 * varpi) / 3.0
+    a = np.array([62.6, 58.0])
+    r, v = W.elements_to_cartesian(w.mu0, a, np.full(2, 0.25), np.full(2, 0.05), np.full(2, node),
+                                   np.full(2, peri), np.full(2, lam - varpi))
+    T = 200_000
+    eph = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, T, w.dt, keep_velocities=True)
+    rc = W.hill_radius(w.mu0, w.mu, np.array([5.2, 9.55, 19.2, 30.1]))
+    d = orc.diagnostics(w.mu0, w.mu, rc, 1000.0, eph, w.dt, r, v, T, every=100, ref=3,
+                        resonances=[(3, 1)])
+    assert np.all(d.result.reason == 0)
+    print(f"flags {d.flags[:, 0].tolist()}, phi - 180 deg range "
+          f"[{math.degrees(d.lo[0, 0]):.1f}, {math.degrees(d.hi[0, 0]):.1f}] deg", flush=True)
+    assert d.flags[0, 0] == 2 and d.flags[1, 0] == 3
+    assert d.hi[0, 0] - d.lo[0, 0] < math.radians(150)
