@@ -123,11 +123,13 @@ int tpm_set_particles(tpm_sim* sim, int64_t n, const double* r, const double* v)
 /* Advance planets and particles by nsteps steps of dt (dt < 0 integrates
  * backwards).  Checks run at every step boundary, including the first and last.
  * Calling it twice with T1 and T2 steps gives bit-identical results to one call
- * with T1 + T2 steps.  Resuming in a new simulation from tpm_get_planets and the
- * still-active particles of tpm_get_particles (step count restarting at 0)
- * agrees with the uninterrupted run to rounding: the planets' internal Jacobi
- * state passes through heliocentric coordinates once more.  TPM_EINVAL and TPM_ESTATE are returned before any work is
- * enqueued and leave the simulation as it was; after TPM_ENOMEM or TPM_EDEVICE
+ * with T1 + T2 steps, and so does a new simulation set from tpm_get_state
+ * (tpm_set_state).  Resuming instead from tpm_get_planets and the still-active
+ * particles of tpm_get_particles (step count restarting at 0) agrees with the
+ * uninterrupted run to rounding: the planets' Jacobi state passes through
+ * heliocentric coordinates once more.  TPM_EINVAL and TPM_ESTATE are returned
+ * before any work is enqueued and leave the simulation as it was; after
+ * TPM_ENOMEM or TPM_EDEVICE
  * the integration stopped part-way and the simulation's state is undefined
  * (destroy it). */
 int tpm_integrate(tpm_sim* sim, int64_t nsteps, double dt);
@@ -143,6 +145,26 @@ int tpm_get_particles(tpm_sim* sim, double* r, double* v, int64_t* deact_step,
 int tpm_get_planets(tpm_sim* sim, double* r, double* v);
 
 int tpm_get_stats(tpm_sim* sim, tpm_stats* out);
+
+/* ---- state of a simulation, for checkpoints and continuation runs ----------
+ * The paper continues integrations from their output states (sec. 4.2); these
+ * carry the whole internal state, so a continuation is bit-identical to the
+ * uninterrupted run.  tpm_get_state writes an opaque blob into caller memory:
+ * the central mass, the planets (constants, their integration order and the
+ * Jacobi state the planet map carries), the global step count, the first
+ * planet event so far, and every particle's state and removal record.  With
+ * buf NULL it only stores the blob's size in *size; otherwise *size is the
+ * buffer's capacity on entry (TPM_EINVAL if too small) and the blob's size on
+ * return.  TPM_ESTATE before planets and particles are set.
+ * tpm_set_state replaces the central mass, planets, particles, step count and
+ * planet event of sim (created with any options) by those of a blob of exactly
+ * `size` bytes from this library version (TPM_EINVAL otherwise, before
+ * anything changes).  Integrating after it continues the run: removal steps
+ * stay absolute, and the results equal those of one uninterrupted run bit for
+ * bit.  A caller-supplied planet table and the derivative context are
+ * dropped.  The blob is native-endian and meant for the same library. */
+int tpm_get_state(tpm_sim* sim, void* buf, int64_t* size);
+int tpm_set_state(tpm_sim* sim, const void* buf, int64_t size);
 
 /* Hill radius a_p (mu_p / (3 mu0))^(1/3) (sec. 2.2, encounter criterion). */
 double tpm_hill_radius(double mu0, double mu_p, double a_p);

@@ -80,6 +80,8 @@ SIGNATURES = {
     "tpm_ad_tangent": (C.c_int, [_P] * 6),
     "tpm_batch_integrate": (C.c_int, [C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_int64,
                                       _P, _P, _P, _P, _P, _P, _P, _P]),
+    "tpm_get_state": (C.c_int, [_P, _P, _P]),
+    "tpm_set_state": (C.c_int, [_P, _P, C.c_int64]),
 }
 
 _lib = None
@@ -208,6 +210,23 @@ class Simulation:
         s = Stats()
         _check(load().tpm_get_stats(self._h, C.byref(s)))
         return s.as_dict()
+
+    def get_state(self) -> bytes:
+        """The simulation's whole state as an opaque blob (tpm_get_state)."""
+        size = C.c_int64(0)
+        _check(load().tpm_get_state(self._h, None, C.byref(size)))
+        buf = C.create_string_buffer(size.value)
+        _check(load().tpm_get_state(self._h, buf, C.byref(size)))
+        return buf.raw[:size.value]
+
+    def set_state(self, blob: bytes):
+        """Replace central mass, planets, particles and step count by a blob of
+        get_state (tpm_set_state); integrating then continues that run."""
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        _check(load().tpm_set_state(self._h, buf, len(blob)))
+        hdr = np.frombuffer(bytes(blob[:32]), dtype=np.int64)
+        self.np = int(np.frombuffer(bytes(blob[12:16]), dtype=np.int32)[0])
+        self.n = int(hdr[2])
 
     def planet_table(self, nsteps: int, dt: float):
         t = np.zeros((nsteps + 1, 3 * self.np + 3))

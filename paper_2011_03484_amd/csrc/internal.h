@@ -7,6 +7,9 @@ namespace tpm {
 
 constexpr int MAX_NP = 8;
 
+// Records msg as this thread's last error (tpm_last_error) and returns code.
+int set_error(int code, const char* msg);
+
 // Working set of active particles, structure of arrays (coalesced per lane).
 struct Work {
   double* x;

@@ -160,6 +160,8 @@ bool sort_planets(double mu0, int np, const double* mu, const double* r, const d
 
 }  // namespace
 
+int tpm::set_error(int code, const char* msg) { return fail(code, msg); }
+
 struct tpm_sim {
   tpm_options opt{};
   hipStream_t sP = nullptr, sE = nullptr;
@@ -313,6 +315,67 @@ void permute_table(const tpm_sim* s, const double* src, double* dst, int64_t row
     }
     for (int k = 0; k < 3; ++k) b[3 * np + k] = a[3 * np + k];
   }
+}
+
+// Particle arrays of a simulation from caller-order states and (optionally)
+// removal records: results hold every particle, the working set the active
+// ones (record reason 0) in caller order.  The device lock is held.
+int load_particles(tpm_sim* s, int64_t n, const double* r, const double* v, const int64_t* step,
+                   const int32_t* reason, const int32_t* planet) {
+  TPM_HIP(hipStreamSynchronize(s->sP));
+  s->release_particles();
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  for (auto& w : s->work) {
+    TPM_HIP(hipMalloc(&w.x, nn * 8)); TPM_HIP(hipMalloc(&w.y, nn * 8)); TPM_HIP(hipMalloc(&w.z, nn * 8));
+    TPM_HIP(hipMalloc(&w.vx, nn * 8)); TPM_HIP(hipMalloc(&w.vy, nn * 8)); TPM_HIP(hipMalloc(&w.vz, nn * 8));
+    TPM_HIP(hipMalloc(&w.slot, nn * 4)); TPM_HIP(hipMalloc(&w.status, nn * 4));
+  }
+  TPM_HIP(hipMalloc(&s->out.r, nn * 24)); TPM_HIP(hipMalloc(&s->out.v, nn * 24));
+  TPM_HIP(hipMalloc(&s->out.step, nn * 8)); TPM_HIP(hipMalloc(&s->out.reason, nn * 4));
+  TPM_HIP(hipMalloc(&s->out.planet, nn * 4));
+  TPM_HIP(hipMalloc(&s->d_scratch, sizeof(int32_t) * compact_scratch_ints((int)nn)));
+  const size_t ntiles = (nn + 63) / 64;
+  TPM_HIP(hipMalloc(&s->d_qctr, sizeof(unsigned long long)));
+  TPM_HIP(hipMalloc(&s->d_progress, sizeof(uint32_t) * ntiles));
+  TPM_HIP(hipMalloc(&s->d_qerr, sizeof(int32_t)));
+  TPM_HIP(hipMemset(s->d_qctr, 0, sizeof(unsigned long long)));
+  TPM_HIP(hipMemset(s->d_progress, 0, sizeof(uint32_t) * ntiles));
+  TPM_HIP(hipMemset(s->d_qerr, 0, sizeof(int32_t)));
+  TPM_HIP(hipDeviceSynchronize());   // null-stream set-up before work on the non-blocking streams
+  // the working set: active particles in caller order, structure of arrays
+  std::vector<int32_t> idx;
+  idx.reserve(n);
+  for (int64_t i = 0; i < n; ++i)
+    if (!reason || reason[i] == TPM_ACTIVE) idx.push_back((int32_t)i);
+  const int64_t na = (int64_t)idx.size();
+  std::vector<double> col(na);
+  Work& w = s->work[0];
+  double* dst[6] = {w.x, w.y, w.z, w.vx, w.vy, w.vz};
+  for (int c = 0; c < 6; ++c) {
+    const double* src = c < 3 ? r : v;
+    for (int64_t k = 0; k < na; ++k) col[k] = src[3 * (int64_t)idx[k] + (c % 3)];
+    if (na) TPM_HIP(hipMemcpy(dst[c], col.data(), na * 8, hipMemcpyHostToDevice));
+  }
+  std::vector<int32_t> zero(n, 0), m1(n, -1);
+  std::vector<int64_t> m1l(n, -1);
+  if (na) {
+    TPM_HIP(hipMemcpy(w.slot, idx.data(), na * 4, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(w.status, zero.data(), na * 4, hipMemcpyHostToDevice));
+  }
+  if (n) {
+    TPM_HIP(hipMemcpy(s->out.step, step ? step : m1l.data(), n * 8, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(s->out.reason, reason ? reason : zero.data(), n * 4, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(s->out.planet, planet ? planet : m1.data(), n * 4, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(s->out.r, r, n * 24, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(s->out.v, v, n * 24, hipMemcpyHostToDevice));
+  }
+  int32_t na32 = (int32_t)na;
+  TPM_HIP(hipMemcpy(s->d_nactive, &na32, 4, hipMemcpyHostToDevice));
+  s->cur = 0;
+  s->n = n;
+  s->n_active = (int)na;
+  s->particles_set = true;
+  return TPM_OK;
 }
 
 int check_eplanet(tpm_sim* s, int rc) {
@@ -510,54 +573,7 @@ int tpm_set_particles(tpm_sim* s, int64_t n, const double* r, const double* v) {
     return fail(TPM_EINVAL, "particle input not finite");
   TPM_HIP(hipSetDevice(s->opt.device));
   std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
-  TPM_HIP(hipStreamSynchronize(s->sP));
-  s->release_particles();
-  const size_t nn = (size_t)std::max<int64_t>(n, 1);
-  for (auto& w : s->work) {
-    TPM_HIP(hipMalloc(&w.x, nn * 8)); TPM_HIP(hipMalloc(&w.y, nn * 8)); TPM_HIP(hipMalloc(&w.z, nn * 8));
-    TPM_HIP(hipMalloc(&w.vx, nn * 8)); TPM_HIP(hipMalloc(&w.vy, nn * 8)); TPM_HIP(hipMalloc(&w.vz, nn * 8));
-    TPM_HIP(hipMalloc(&w.slot, nn * 4)); TPM_HIP(hipMalloc(&w.status, nn * 4));
-  }
-  TPM_HIP(hipMalloc(&s->out.r, nn * 24)); TPM_HIP(hipMalloc(&s->out.v, nn * 24));
-  TPM_HIP(hipMalloc(&s->out.step, nn * 8)); TPM_HIP(hipMalloc(&s->out.reason, nn * 4));
-  TPM_HIP(hipMalloc(&s->out.planet, nn * 4));
-  TPM_HIP(hipMalloc(&s->d_scratch, sizeof(int32_t) * compact_scratch_ints((int)nn)));
-  const size_t ntiles = (nn + 63) / 64;
-  TPM_HIP(hipMalloc(&s->d_qctr, sizeof(unsigned long long)));
-  TPM_HIP(hipMalloc(&s->d_progress, sizeof(uint32_t) * ntiles));
-  TPM_HIP(hipMalloc(&s->d_qerr, sizeof(int32_t)));
-  TPM_HIP(hipMemset(s->d_qctr, 0, sizeof(unsigned long long)));
-  TPM_HIP(hipMemset(s->d_progress, 0, sizeof(uint32_t) * ntiles));
-  TPM_HIP(hipMemset(s->d_qerr, 0, sizeof(int32_t)));
-  TPM_HIP(hipDeviceSynchronize());   // null-stream set-up before work on the non-blocking streams
-  // structure-of-arrays layout for the kernels
-  std::vector<double> col(n);
-  Work& w = s->work[0];
-  double* dst[6] = {w.x, w.y, w.z, w.vx, w.vy, w.vz};
-  for (int c = 0; c < 6; ++c) {
-    const double* src = c < 3 ? r : v;
-    for (int64_t i = 0; i < n; ++i) col[i] = src[3 * i + (c % 3)];
-    if (n) TPM_HIP(hipMemcpy(dst[c], col.data(), n * 8, hipMemcpyHostToDevice));
-  }
-  std::vector<int32_t> idx(n), zero(n, 0), m1(n, -1);
-  std::vector<int64_t> m1l(n, -1);
-  std::iota(idx.begin(), idx.end(), 0);
-  if (n) {
-    TPM_HIP(hipMemcpy(w.slot, idx.data(), n * 4, hipMemcpyHostToDevice));
-    TPM_HIP(hipMemcpy(w.status, zero.data(), n * 4, hipMemcpyHostToDevice));
-    TPM_HIP(hipMemcpy(s->out.step, m1l.data(), n * 8, hipMemcpyHostToDevice));
-    TPM_HIP(hipMemcpy(s->out.reason, zero.data(), n * 4, hipMemcpyHostToDevice));
-    TPM_HIP(hipMemcpy(s->out.planet, m1.data(), n * 4, hipMemcpyHostToDevice));
-    TPM_HIP(hipMemcpy(s->out.r, r, n * 24, hipMemcpyHostToDevice));
-    TPM_HIP(hipMemcpy(s->out.v, v, n * 24, hipMemcpyHostToDevice));
-  }
-  int32_t nn32 = (int32_t)n;
-  TPM_HIP(hipMemcpy(s->d_nactive, &nn32, 4, hipMemcpyHostToDevice));
-  s->cur = 0;
-  s->n = n;
-  s->n_active = (int)n;
-  s->particles_set = true;
-  return TPM_OK;
+  return load_particles(s, n, r, v, nullptr, nullptr, nullptr);
 }
 
 int tpm_set_planet_table(tpm_sim* s, const double* table, int64_t nrows) {
@@ -798,6 +814,153 @@ int tpm_get_planets(tpm_sim* s, double* r, double* v) {
     }
   }
   return TPM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Layout of the state blob of tpm_get_state / tpm_set_state: this header, then
+// r[n][3], v[n][3] (f64), step[n] (i64), reason[n], planet[n] (i32, planet in
+// the integration's sorted order), all native-endian.
+struct StateHeader {
+  char magic[8];
+  int32_t version;
+  int32_t np;
+  int64_t n;
+  int64_t step;
+  int64_t flag;                  // first planet event so far (-1 none)
+  double mu0;
+  int32_t perm[MAX_NP];          // sorted planet index -> caller index
+  double mu[MAX_NP], rcrit[MAX_NP], a[MAX_NP];   // sorted order
+  double rj[3 * MAX_NP], vj[3 * MAX_NP];         // Jacobi planet state
+};
+constexpr char STATE_MAGIC[8] = {'t', 'p', 'm', 's', 't', 'a', 't', 'e'};
+constexpr int32_t STATE_VERSION = 1;
+
+int64_t state_bytes(int64_t n) { return (int64_t)sizeof(StateHeader) + 64 * n; }
+
+}  // namespace
+
+extern "C" {
+
+int tpm_get_state(tpm_sim* s, void* buf, int64_t* size) {
+  if (!s || !size) return fail(TPM_EINVAL, "NULL argument");
+  if (!s->planets_set || !s->particles_set)
+    return fail(TPM_ESTATE, "set central mass, planets and particles first");
+  const int64_t n = s->n, need = state_bytes(n);
+  if (!buf) {
+    *size = need;
+    return TPM_OK;
+  }
+  if (*size < need) return fail(TPM_EINVAL, "state buffer too small");
+  TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
+  TPM_HIP(hipStreamSynchronize(s->sE));
+  TPM_HIP(hipStreamSynchronize(s->sP));
+  StateHeader h{};
+  std::memcpy(h.magic, STATE_MAGIC, 8);
+  h.version = STATE_VERSION;
+  h.np = s->np;
+  h.n = n;
+  h.step = s->step;
+  h.mu0 = s->mu0;
+  TPM_HIP(hipMemcpy(&h.flag, s->d_flag, sizeof(int64_t), hipMemcpyDeviceToHost));
+  for (int j = 0; j < s->np; ++j) {
+    h.perm[j] = s->perm[j];
+    h.mu[j] = s->mu_s[j];
+    h.rcrit[j] = s->rcrit_s[j];
+    h.a[j] = s->a_s[j];
+  }
+  if (s->np > 0) {
+    TPM_HIP(hipMemcpy(h.rj, s->d_rj, sizeof(double) * 3 * s->np, hipMemcpyDeviceToHost));
+    TPM_HIP(hipMemcpy(h.vj, s->d_vj, sizeof(double) * 3 * s->np, hipMemcpyDeviceToHost));
+  }
+  char* p = static_cast<char*>(buf);
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  if (n > 0) {
+    TPM_HIP(launch_finalize(s->work[s->cur], s->d_nactive, s->n_active, s->out, s->sP));
+    TPM_HIP(hipStreamSynchronize(s->sP));
+    TPM_HIP(hipMemcpy(p, s->out.r, n * 24, hipMemcpyDeviceToHost)); p += n * 24;
+    TPM_HIP(hipMemcpy(p, s->out.v, n * 24, hipMemcpyDeviceToHost)); p += n * 24;
+    TPM_HIP(hipMemcpy(p, s->out.step, n * 8, hipMemcpyDeviceToHost)); p += n * 8;
+    TPM_HIP(hipMemcpy(p, s->out.reason, n * 4, hipMemcpyDeviceToHost)); p += n * 4;
+    TPM_HIP(hipMemcpy(p, s->out.planet, n * 4, hipMemcpyDeviceToHost));
+  }
+  *size = need;
+  return TPM_OK;
+}
+
+int tpm_set_state(tpm_sim* s, const void* buf, int64_t size) {
+  if (!s || !buf) return fail(TPM_EINVAL, "NULL argument");
+  if (size < (int64_t)sizeof(StateHeader)) return fail(TPM_EINVAL, "state blob too short");
+  StateHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, STATE_MAGIC, 8) != 0 || h.version != STATE_VERSION)
+    return fail(TPM_EINVAL, "not a state blob of this library version");
+  if (h.np < 0 || h.np > MAX_NP || h.n < 0 || h.n >= (int64_t(1) << 31) ||
+      size != state_bytes(h.n))
+    return fail(TPM_EINVAL, "state blob sizes inconsistent");
+  const int np = h.np;
+  const int64_t n = h.n;
+  if (!(std::isfinite(h.mu0) && h.mu0 > 0.0)) return fail(TPM_EINVAL, "state: bad mu0");
+  {
+    std::vector<int> seen(np, 0);
+    for (int j = 0; j < np; ++j) {
+      if (h.perm[j] < 0 || h.perm[j] >= np || seen[h.perm[j]]++)
+        return fail(TPM_EINVAL, "state: bad planet order");
+      if (!(h.mu[j] > 0.0 && std::isfinite(h.mu[j]) && h.rcrit[j] >= 0.0 &&
+            std::isfinite(h.rcrit[j]) && h.a[j] > 0.0 && std::isfinite(h.a[j])))
+        return fail(TPM_EINVAL, "state: bad planet constants");
+    }
+    if (!finite_all(h.rj, 3 * np) || !finite_all(h.vj, 3 * np))
+      return fail(TPM_EINVAL, "state: planet state not finite");
+  }
+  const char* p = static_cast<const char*>(buf) + sizeof(StateHeader);
+  std::vector<double> r(3 * n), v(3 * n);
+  std::vector<int64_t> step(n);
+  std::vector<int32_t> reason(n), planet(n);
+  if (n > 0) {
+    std::memcpy(r.data(), p, n * 24); p += n * 24;
+    std::memcpy(v.data(), p, n * 24); p += n * 24;
+    std::memcpy(step.data(), p, n * 8); p += n * 8;
+    std::memcpy(reason.data(), p, n * 4); p += n * 4;
+    std::memcpy(planet.data(), p, n * 4);
+  }
+  if (!finite_all(r.data(), 3 * n) || !finite_all(v.data(), 3 * n))
+    return fail(TPM_EINVAL, "state: particle state not finite");
+  for (int64_t i = 0; i < n; ++i)
+    if (reason[i] < TPM_ACTIVE || reason[i] > TPM_KEPLER || planet[i] < -1 || planet[i] >= np)
+      return fail(TPM_EINVAL, "state: bad removal record");
+  TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
+  TPM_HIP(hipStreamSynchronize(s->sP));
+  TPM_HIP(hipStreamSynchronize(s->sE));
+  s->release_planets();
+  s->release_ring();
+  s->ad.valid = false;
+  s->mu0 = h.mu0;
+  s->central_set = true;
+  s->planets_set = false;
+  s->particles_set = false;
+  s->np = np;
+  s->perm.assign(h.perm, h.perm + np);
+  s->mu_s.assign(h.mu, h.mu + np);
+  s->rcrit_s.assign(h.rcrit, h.rcrit + np);
+  s->a_s.assign(h.a, h.a + np);
+  const size_t b = sizeof(double) * 3 * std::max(np, 1);
+  TPM_HIP(hipMalloc(&s->d_rj, b));
+  TPM_HIP(hipMalloc(&s->d_vj, b));
+  TPM_HIP(hipMalloc(&s->d_tmp, 4 * b));
+  if (np > 0) {
+    TPM_HIP(hipMemcpy(s->d_rj, h.rj, sizeof(double) * 3 * np, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(s->d_vj, h.vj, sizeof(double) * 3 * np, hipMemcpyHostToDevice));
+  }
+  TPM_HIP(hipMemcpy(s->d_flag, &h.flag, sizeof(int64_t), hipMemcpyHostToDevice));
+  s->step = h.step;
+  s->planets_set = true;
+  return load_particles(s, n, r.data(), v.data(), step.data(), reason.data(), planet.data());
 }
 
 int tpm_get_stats(tpm_sim* s, tpm_stats* o) {
