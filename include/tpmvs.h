@@ -243,6 +243,36 @@ int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_t* planet_o
                         int32_t* reason_out, int32_t* planet_out, tpm_stats* stats,
                         int64_t* planet_flag);
 
+/* ---- one run without allocation ---------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  One call does
+ * what tpm_set_central, tpm_set_planets, tpm_set_particles, tpm_integrate and
+ * tpm_get_particles do on a new simulation, with the same kernels and bit-
+ * identical results, but it allocates nothing: every buffer the kernels need
+ * beyond the inputs and outputs (working set, planet-table rows, work-queue
+ * counters, compaction scratch, planet state) lies in one fixed device array
+ * of the library (about 30 MiB, held by each GPU the library runs on until the
+ * process ends).  Limits: n <= 262,144 particles, chunk_steps <= 8192 (0 =
+ * 8192), np <= 8; larger requests return TPM_EINVAL before any work.
+ * Planets (mu[np], rp[np][3], vp[np][3], rcrit[np]) are host arrays, read
+ * before the call returns.  d_r, d_v [n][3] (input) and d_r_out, d_v_out
+ * [n][3], d_step[n] (int64), d_reason[n], d_planet[n] (int32) (outputs, as in
+ * tpm_get_particles) are caller-owned device memory; d_info (device, 2 int64,
+ * may be NULL) receives the planet event (-1 none, t >= 0 two planets within a
+ * mutual Hill radius at step t, -2 a planet orbit found unbound) and the
+ * work-queue error flag (0 = none).  Work is enqueued on the caller's stream
+ * (NULL = null stream) without synchronising; options as in tpm_create (NULL =
+ * defaults; time_kernels is ignored).  The planet map and the particles run one
+ * after the other on that one stream, so a run takes about the sum of the two
+ * stages rather than the larger.  Every call on one GPU uses that GPU's array,
+ * which keeps the last call's contents (each call initialises what it uses):
+ * calls that overlap on one GPU, from any stream or thread, race. */
+int tpm_integrate_static(const tpm_options* opt, double mu0, int32_t np, const double* mu,
+                         const double* rp, const double* vp, const double* rcrit, int64_t n,
+                         const double* d_r, const double* d_v, int64_t nsteps, double dt,
+                         double* d_r_out, double* d_v_out, int64_t* d_step, int32_t* d_reason,
+                         int32_t* d_planet, int64_t* d_info, void* stream);
+
 /* ---- unit entry points of the device math (host arrays) -------------------- */
 /* sin and cos of x[n] by the library's branch-free FP64 routine. */
 int tpm_debug_sincos(int64_t n, const double* x, double* s, double* c);

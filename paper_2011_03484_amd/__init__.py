@@ -6,9 +6,9 @@ this package is its ctypes binding plus seeded input generators
 built library every entry point raises.
 """
 from ._lib import (ACTIVE, ENCOUNTER, ESCAPE, KEPLER, PlanetEncounterError, Simulation, TpmError,
-                   batch_integrate, debug_drift, debug_rsqrt, debug_sincos, hill_radius, load,
-                   run_workload)
+                   batch_integrate, debug_drift, debug_rsqrt, debug_sincos, hill_radius,
+                   integrate_static, load, run_workload)
 
 __all__ = ["ACTIVE", "ENCOUNTER", "ESCAPE", "KEPLER", "PlanetEncounterError", "Simulation",
            "TpmError", "batch_integrate", "debug_drift", "debug_rsqrt", "debug_sincos", "hill_radius",
-           "load", "run_workload"]
+           "integrate_static", "load", "run_workload"]

@@ -82,6 +82,8 @@ SIGNATURES = {
                                       _P, _P, _P, _P, _P, _P, _P, _P]),
     "tpm_get_state": (C.c_int, [_P, _P, _P]),
     "tpm_set_state": (C.c_int, [_P, _P, C.c_int64]),
+    "tpm_integrate_static": (C.c_int, [_P, C.c_double, C.c_int32, _P, _P, _P, _P, C.c_int64, _P, _P,
+                                       C.c_int64, C.c_double, _P, _P, _P, _P, _P, _P, _P]),
 }
 
 _lib = None
@@ -312,6 +314,28 @@ def batch_integrate(systems, nsteps=None, r_escape=None, kepler_iters=5, chunk_s
     if strict or rc_ != TPM_EPLANET:
         _check(rc_)
     return out, sd
+
+
+def integrate_static(mu0, mu, rp, vp, rcrit, d_r, d_v, nsteps, dt, d_r_out, d_v_out, d_step,
+                     d_reason, d_planet, d_info=None, stream=None, r_escape=0.0, kepler_iters=5,
+                     chunk_steps=0, resync_chunks=0, block_threads=0, sub_chunks=0,
+                     waves_per_simd=0, device=0, n=None):
+    """One run without allocation (tpm_integrate_static).  Planets are host
+    arrays; d_* are device addresses (ints, e.g. a torch tensor's data_ptr())
+    of [n][3] float64 inputs and of the outputs; stream is a HIP stream handle
+    (int) or None.  Returns once the work is enqueued."""
+    mu = _f64(mu, (-1,))
+    npl = mu.shape[0]
+    rp, vp, rc = _f64(rp, (npl, 3)), _f64(vp, (npl, 3)), _f64(rcrit, (npl,))
+    o = default_options()
+    o.kepler_iters, o.chunk_steps, o.resync_chunks = kepler_iters, chunk_steps, resync_chunks
+    o.block_threads, o.sub_chunks, o.waves_per_simd = block_threads, sub_chunks, waves_per_simd
+    o.r_escape, o.device = r_escape, device
+    vp_ = lambda x: None if x is None else C.c_void_p(int(x))
+    _check(load().tpm_integrate_static(C.byref(o), float(mu0), npl, _p(mu), _p(rp), _p(vp), _p(rc),
+                                       int(n), vp_(d_r), vp_(d_v), int(nsteps), float(dt),
+                                       vp_(d_r_out), vp_(d_v_out), vp_(d_step), vp_(d_reason),
+                                       vp_(d_planet), vp_(d_info), vp_(stream)))
 
 
 def run_workload(w, nsteps=None, **opts):

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpmvs.so")
-SOURCES = ["kernels_core.hip", "ad_kernels.hip", "runtime.hip"]
+SOURCES = ["kernels_core.hip", "ad_kernels.hip", "runtime.hip", "static_run.hip"]
 HEADERS = ["dmath.hpp", "kepler.hpp", "particle.hpp", "ad.hpp", "internal.h", "ad_internal.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
