@@ -109,6 +109,8 @@ def summarize_counters(pmc_dir: str) -> None:
         k = r["Kernel_Name"]
         if "particle_queue" in k:
             return "particle_queue<4,5>"
+        if "ephemeris_chunk" in k:
+            return "ephemeris_chunk<4>"
         if "copyBuffer" in k and int(r["Grid_Size"]) == 131072:
             return "device copy 256 MiB"
         return None
@@ -197,6 +199,63 @@ def summarize_counters(pmc_dir: str) -> None:
                "active_particle_steps_per_launch": aps / launches, "summary": os.path.basename(COUNTERS_MD)},
               open(COUNTERS_JSON, "w"), indent=1)
     print("\n".join(out[-6:]))
+    summarize_ephemeris(pmc_dir, tot, cnt, steps, src)
+
+
+def summarize_ephemeris(pmc_dir: str, tot, cnt, steps: int, src: str) -> None:
+    """The planet map's part of the same counter passes (one wavefront, serial
+    in time), per step, and its kernel-trace time beside the particle kernel
+    (pass 2) and alone (`python3 bench.py --ephemeris-only --nsteps 100000`
+    under `rocprofv3 --kernel-trace -f csv -d <pmc_dir>/alone -o run`)."""
+    import csv
+    eph = "ephemeris_chunk<4>"
+    g = lambda p, c: tot[(p, eph, c)]
+
+    def trace(path):
+        t, k, n = 0.0, 0, 0
+        for r in csv.DictReader(open(path)):
+            if "ephemeris_chunk" in r["Kernel_Name"]:
+                t += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+                k += 1
+        return t, k
+
+    beside, nb = trace(os.path.join(pmc_dir, "p2", "run_kernel_trace.csv"))
+    alone_csv = os.path.join(pmc_dir, "alone", "run_kernel_trace.csv")
+    alone_steps = 100_000
+    alone, na = trace(alone_csv) if os.path.exists(alone_csv) else (None, 0)
+    per = lambda p, c: g(p, c) / steps
+    flops = 64 * per("p1", "SQ_INSTS_VALU_FLOPS_FP64")
+    out = [f"# ephemeris_chunk<4> counters -- the planet map of giants_100k (4 planets), {steps:,} steps "
+           f"({cnt[('p1', eph, 'SQ_WAVES')]} launches, one wavefront each)", "",
+           "From the same four counter passes as `particle_queue_giants_100k_counters.md` (commands "
+           "there), which run the planet map beside the particle kernel; its time alone from "
+           "`cd /tmp && export TMPDIR=/tmp; rocprofv3 --kernel-trace -f csv -d <out>/alone -o run -- "
+           f"python3 <repo>/bench.py --ephemeris-only --nsteps {alone_steps}`; then "
+           "`python3 bench.py --summarize-counters <out>`.", "",
+           f"Kernel sources of the counted runs: `bench.kernel_source_hash()` = `{src}`.", "",
+           "| counter | sum | per step |", "|---|---|---|"]
+    for (p, lab, c), v in sorted(tot.items()):
+        if lab == eph:
+            out.append(f"| {c} | {v:.6g} | {v / steps:.1f} |")
+    out += ["", "Derived, per step of the map (one wavefront; SQ cycle counters in units of 4 cycles):", "",
+            f"* VALU instructions {per('p1', 'SQ_INSTS_VALU'):.0f}, of them FP64 FMA "
+            f"{per('p1', 'SQ_INSTS_VALU_FMA_F64'):.0f}, mul {per('p1', 'SQ_INSTS_VALU_MUL_F64'):.0f}, "
+            f"add {per('p1', 'SQ_INSTS_VALU_ADD_F64'):.0f}, transcendental "
+            f"{per('p1', 'SQ_INSTS_VALU_TRANS_F64'):.0f}; SALU {per('p2', 'SQ_INSTS_SALU'):.0f}, SMEM "
+            f"{per('p2', 'SQ_INSTS_SMEM'):.0f}; executed FP64 flops (all 64 lanes) {flops:.0f}.",
+            f"* Wave cycles {4 * per('p2', 'SQ_WAVE_CYCLES'):.0f}: VALU issuing "
+            f"{4 * per('p2', 'SQ_ACTIVE_INST_VALU'):.0f}, any instruction issuing "
+            f"{4 * per('p2', 'SQ_ACTIVE_INST_ANY'):.0f}, waiting on a dependency or memory "
+            f"{4 * per('p2', 'SQ_WAIT_ANY'):.0f}, waiting to issue "
+            f"{4 * per('p2', 'SQ_WAIT_INST_ANY'):.0f}.",
+            f"* Kernel-trace time beside the particle kernel (pass 2): {beside * 1e3:.2f} ms for "
+            f"{steps:,} steps in {nb} launches = {beside / steps * 1e6:.3f} us per step."]
+    if alone is not None:
+        out.append(f"* Alone (no particle kernel): {alone * 1e3:.2f} ms for {alone_steps:,} steps in "
+                   f"{na} launches = {alone / alone_steps * 1e6:.3f} us per step.")
+    path = os.path.join(ROOT, "profiles", "ephemeris_chunk_giants_100k_counters.md")
+    open(path, "w").write("\n".join(out) + "\n")
+    print("\n".join(out[-4:]))
 
 
 def cpu_model() -> str:
@@ -314,6 +373,9 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device with a plain copy "
                          "kernel (the reference for scaling HBM byte counters)")
+    ap.add_argument("--ephemeris-only", action="store_true",
+                    help="run only the planet map of the workload for --nsteps steps (its time "
+                         "alone) and print one JSON line")
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="write the counter summary under profiles/ from rocprofv3 --pmc passes "
                          "p1..p4 in DIR, then exit (no GPU use)")
@@ -335,6 +397,17 @@ def main():
     torch.cuda.init()
     w = W.giants_100k(n=args.n)
     T = args.nsteps
+    if args.ephemeris_only:
+        s = P.Simulation(r_escape=w.rmax, kepler_iters=w.kepler_iters, chunk_steps=args.chunk)
+        s.set_central(w.mu0)
+        s.set_planets(w.mu, w.rp, w.vp, w.rcrit)
+        s.planet_table(1024, w.dt)
+        t0 = time.perf_counter()
+        s.planet_table(T, w.dt)
+        t1 = time.perf_counter()
+        print(json.dumps({"mode": "ephemeris-only", "workload": "giants_100k planets", "steps": T,
+                          "call_s_incl_table_copy": t1 - t0}))
+        return
     sims = []
     for _ in range(args.warmup + args.steps):
         s = P.Simulation(r_escape=w.rmax, kepler_iters=w.kepler_iters, chunk_steps=args.chunk,
