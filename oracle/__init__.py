@@ -15,6 +15,9 @@ Entry points (each cites the passage of Zhang & Gladman 2021 it follows):
   the difference form of Kepler's equation with f and g functions, half kick,
   and the encounter / escape / Kepler-failure deactivation (sec. 2.2).
 * :func:`run`        - both of the above.
+* :func:`history_table` - the planet table interpolated from a history of
+  planet states instead of the planet map (sec. 2.2, planet positions from
+  any source).
 * :func:`tangent`, :func:`stm`, :func:`adjoint` - the exact derivative of the
   discrete particle map by the complex-step method (Squire & Trapp 1998).
 * :func:`kepler_solve`, :func:`kepler_fixedk`, :func:`drift` - unit pieces.
@@ -74,7 +77,9 @@ def _load():
         lib.orc_drift.restype = i
         lib.orc_ephemeris.argtypes = [d, i, P, P, P, i64, d, P, P, P, P]
         lib.orc_ephemeris.restype = i64
-        lib.orc_particles.argtypes = [d, i, P, P, d, P, i64, d, i64, i, d, i64, P, P, P, P, P, i]
+        lib.orc_particles.argtypes = [d, i, P, P, d, P, i64, d, i64, i, d, i64, P, P, P, P, P, i, i]
+        lib.orc_drift_universal.argtypes = [d, P, P, d]
+        lib.orc_drift_universal.restype = i
         lib.orc_particles.restype = d
         lib.orc_max_threads.argtypes = [i]
         lib.orc_max_threads.restype = i
@@ -85,6 +90,8 @@ def _load():
         lib.orc_particles_diag.argtypes = [d, i, P, P, d, P, i64, d, i64, i, d, i64, P, P, P, P, P,
                                            i, i64, P, i, P, P, P, P, P, P, P]
         lib.orc_particles_diag.restype = d
+        lib.orc_history_table.argtypes = [i, P, i64, P, P, P, d, d, i64, P, P]
+        lib.orc_history_table.restype = i64
         lib.orc_elements.argtypes = [d, i64, P, P, P]
         lib.orc_elements.restype = None
         lib.orc_mean_longitudes.argtypes = [d, i64, P, P, P]
@@ -128,6 +135,14 @@ def drift(mu: float, r, v, dt: float, kfix: int = -1, ftol: float = KEPLER_FTOL)
     return bool(ok), r, v, fg
 
 
+def drift_universal(mu: float, r, v, dt: float):
+    """Universal-variable two-body drift; returns (ok, r, v)."""
+    r = _f64(r, (3,)).copy()
+    v = _f64(v, (3,)).copy()
+    ok = _load().orc_drift_universal(float(mu), _ptr(r), _ptr(v), float(dt))
+    return bool(ok), r, v
+
+
 # ------------------------------------------------------------------- planets
 @dataclass
 class Ephemeris:
@@ -155,6 +170,26 @@ def ephemeris(mu0: float, mu, rp, vp, nsteps: int, dt: float, keep_table: bool =
     return Ephemeris(table, rf, vf, int(flag), vtable)
 
 
+def history_table(mu, t, hr, hv, t0: float, dt: float, nsteps: int, keep_velocities=False):
+    """Planet table (and optionally velocities) at times t0 + n dt, n = 0..nsteps,
+    by cubic Hermite interpolation of a history of planet states: t[nrec],
+    hr, hv [nrec][np][3] heliocentric (sec. 2.2: planet positions from any
+    source, such as a history file).  Raises if a row lies outside the
+    history."""
+    mu = _f64(mu).reshape(-1)
+    npl = mu.shape[0]
+    t = _f64(t).reshape(-1)
+    hr, hv = _f64(hr, (t.shape[0], npl, 3)), _f64(hv, (t.shape[0], npl, 3))
+    table = np.zeros((nsteps + 1, 3 * npl + 3))
+    vt = np.zeros((nsteps + 1, npl, 3)) if keep_velocities else None
+    bad = _load().orc_history_table(npl, _ptr(mu), t.shape[0], _ptr(t), _ptr(hr), _ptr(hv),
+                                    float(t0), float(dt), int(nsteps), _ptr(table),
+                                    _ptr(vt) if vt is not None else None)
+    if bad >= 0:
+        raise ValueError(f"row {bad} lies outside the planet history")
+    return (table, vt.reshape(nsteps + 1, 3 * npl)) if keep_velocities else table
+
+
 # ------------------------------------------------------------------ particles
 @dataclass
 class Result:
@@ -168,8 +203,10 @@ class Result:
 
 def particles(mu0: float, mu, rcrit, rmax: float, table, dt: float, r, v, nsteps: int | None = None,
               step0: int = 0, kepler_iters: int = 5, ftol: float = KEPLER_FTOL,
-              nthreads: int = 0) -> Result:
-    """Particles through the given planet table (sec. 2.2 leapfrog + deactivation)."""
+              nthreads: int = 0, universal: bool = False) -> Result:
+    """Particles through the given planet table (sec. 2.2 leapfrog + deactivation);
+    with universal, drifts the elliptic solve refuses use universal variables
+    instead of removing the particle."""
     mu = _f64(mu).reshape(-1)
     npl = mu.shape[0]
     rcrit = _f64(rcrit).reshape(-1)
@@ -185,7 +222,8 @@ def particles(mu0: float, mu, rcrit, rmax: float, table, dt: float, r, v, nsteps
     pl = np.zeros(n, dtype=np.int32)
     secs = _load().orc_particles(float(mu0), npl, _ptr(mu), _ptr(rcrit), float(rmax), _ptr(table),
                                  int(nsteps), float(dt), int(step0), int(kepler_iters), float(ftol),
-                                 n, _ptr(r), _ptr(v), _ptr(ds), _ptr(rs), _ptr(pl), int(nthreads))
+                                 n, _ptr(r), _ptr(v), _ptr(ds), _ptr(rs), _ptr(pl), int(nthreads),
+                                 int(bool(universal)))
     return Result(r, v, ds, rs, pl, secs)
 
 

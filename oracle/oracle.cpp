@@ -263,6 +263,107 @@ int drift(double mu, T r[3], T v[3], double dt, int kfix, double ftol, KepOut* d
 }
 
 // ---------------------------------------------------------------------------
+// Drift in universal variables, for orbits the elliptic solve above refuses
+// (unbound, or not converged by the fixed-k iteration: near-parabolic); the
+// paper names the high-eccentricity case as future work (sec. 2.2, Kepler
+// solver paragraph).  Textbook two-body propagation valid for every conic:
+// with sigma0 = r0.v0/sqrt(mu), alpha = 2/r0 - v0^2/mu and psi = alpha chi^2,
+// the universal anomaly chi solves
+//   F(chi) = r0 chi (1 - psi c3) + sigma0 chi^2 c2 + chi^3 c3 - sqrt(mu) dt = 0
+// (equivalently r0 chi + sigma0 chi^2 c2 + (1 - alpha r0) chi^3 c3), whose
+// derivative is the radius r(chi) = chi^2 c2 + sigma0 chi (1 - psi c3) +
+// r0 (1 - psi c2) > 0; c2, c3 are the Stumpff functions.  Then f = 1 -
+// chi^2 c2 / r0, g = dt - chi^3 c3 / sqrt(mu) (evaluated as (r0 chi (1 -
+// psi c3) + sigma0 chi^2 c2) / sqrt(mu), the same by F = 0), fdot = sqrt(mu)
+// chi (psi c3 - 1) / (r r0), gdot = 1 - chi^2 c2 / r.  F is increasing in chi, so the root
+// is bracketed and found by Newton steps safeguarded by bisection.
+// ---------------------------------------------------------------------------
+// c2(psi) = (1 - cos sqrt psi)/psi, c3(psi) = (sqrt psi - sin sqrt psi)/psi^(3/2)
+// (hyperbolic forms for psi < 0; their power series for |psi| < 1).
+void stumpff(double psi, double& c2, double& c3) {
+  if (std::fabs(psi) < 1.0) {
+    double t2 = 0.5, t3 = 1.0 / 6.0;   // k = 0 terms 1/2!, 1/3!
+    c2 = t2;
+    c3 = t3;
+    for (int k = 1; k <= 16; ++k) {
+      t2 *= -psi / ((2.0 * k + 1.0) * (2.0 * k + 2.0));
+      t3 *= -psi / ((2.0 * k + 2.0) * (2.0 * k + 3.0));
+      c2 += t2;
+      c3 += t3;
+    }
+  } else if (psi > 0.0) {
+    const double sp = std::sqrt(psi);
+    c2 = (1.0 - std::cos(sp)) / psi;
+    c3 = (sp - std::sin(sp)) / (psi * sp);
+  } else {
+    const double sp = std::sqrt(-psi);
+    c2 = (std::cosh(sp) - 1.0) / (-psi);
+    c3 = (std::sinh(sp) - sp) / (-psi * sp);
+  }
+}
+
+int drift_universal(double mu, double r[3], double v[3], double dt) {
+  const double r0 = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const double smu = std::sqrt(mu);
+  const double sigma0 = (r[0] * v[0] + r[1] * v[1] + r[2] * v[2]) / smu;
+  const double alpha = 2.0 / r0 - v2 / mu;
+  const double target = smu * dt;
+  auto F = [&](double chi, double& rr, double& c2, double& c3) {
+    const double psi = alpha * chi * chi;
+    stumpff(psi, c2, c3);
+    rr = chi * chi * c2 + sigma0 * chi * (1.0 - psi * c3) + r0 * (1.0 - psi * c2);
+    return r0 * chi + sigma0 * chi * chi * c2 + (1.0 - alpha * r0) * chi * chi * chi * c3 - target;
+  };
+  if (dt == 0.0) return 1;
+  double rr, c2, c3;
+  // bracket: F(0) = -target; step outwards from chi = target / r0
+  double lo = 0.0, hi = target / r0;
+  for (int i = 0; i < 200 && (dt > 0 ? F(hi, rr, c2, c3) < 0.0 : F(hi, rr, c2, c3) > 0.0); ++i) {
+    lo = hi;
+    hi *= 2.0;
+  }
+  if (!std::isfinite(F(hi, rr, c2, c3))) return 0;
+  if (dt < 0) std::swap(lo, hi);     // now F(lo) <= 0 <= F(hi), lo < hi
+  double chi = 0.5 * (lo + hi);
+  for (int it = 0; it < 200; ++it) {
+    const double Fv = F(chi, rr, c2, c3);
+    if (Fv == 0.0) break;
+    if (Fv < 0.0) lo = chi; else hi = chi;
+    double cn = chi - Fv / rr;
+    if (!(cn > lo && cn < hi)) cn = 0.5 * (lo + hi);
+    const double d = std::fabs(cn - chi);
+    chi = cn;
+    if (d <= 2.0 * std::ldexp(std::fabs(chi), -52) || hi - lo <= 2.0 * std::ldexp(std::fabs(chi), -52))
+      break;
+  }
+  F(chi, rr, c2, c3);
+  const double psi = alpha * chi * chi;
+  const double f = 1.0 - chi * chi * c2 / r0;
+  // g = dt - chi^3 c3 / sqrt(mu), with dt replaced by its value from F = 0
+  // (no cancellation near pericentre of a near-parabolic orbit)
+  const double g = (r0 * chi * (1.0 - psi * c3) + sigma0 * chi * chi * c2) / smu;
+  const double fd = smu * chi * (psi * c3 - 1.0) / (rr * r0);
+  const double gd = 1.0 - chi * chi * c2 / rr;
+  if (!(std::isfinite(f) && std::isfinite(g) && std::isfinite(fd) && std::isfinite(gd))) return 0;
+  double rn[3], vn[3];
+  for (int k = 0; k < 3; ++k) {
+    rn[k] = f * r[k] + g * v[k];
+    vn[k] = fd * r[k] + gd * v[k];
+  }
+  for (int k = 0; k < 3; ++k) { r[k] = rn[k]; v[k] = vn[k]; }
+  return 1;
+}
+
+// The universal drift as the fallback of the particle step (double only; the
+// derivative and operation-count instantiations never take it).
+inline int universal_fallback(double mu, double* r, double* v, double dt) {
+  return drift_universal(mu, r, v, dt);
+}
+template <class T>
+int universal_fallback(double, T*, T*, double) { return 0; }
+
+// ---------------------------------------------------------------------------
 // Particle kick acceleration from one planet-table row (sec. 2.2 kick equation):
 //   a = h0 - sum_j mu_j (r - r_j) / |r - r_j|^3.
 // Also returns the lowest planet index j with |r - r_j| < rcrit_j, or -1.
@@ -305,7 +406,7 @@ struct NoSample {
 template <class T, class S = NoSample>
 Deact run_particle(double mu0, int np, const double* mu, const double* rcrit, double rmax,
                    const double* table, int64_t nsteps, double dt, int64_t step0,
-                   int kfix, double ftol, T r[3], T v[3], S&& smp = S()) {
+                   int kfix, double ftol, T r[3], T v[3], S&& smp = S(), bool universal = false) {
   const int rowlen = 3 * np + 3;
   const double h = 0.5 * dt;
   T acc[3];
@@ -321,7 +422,9 @@ Deact run_particle(double mu0, int np, const double* mu, const double* rcrit, do
     count_boundary(r[0]);
     T rn[3], vn[3];
     for (int k = 0; k < 3; ++k) { rn[k] = r[k]; vn[k] = v[k] + h * acc[k]; }
-    if (!drift(mu0, rn, vn, dt, kfix, ftol)) return {step0 + i, KEPLER, -1};
+    if (!drift(mu0, rn, vn, dt, kfix, ftol) &&
+        !(universal && universal_fallback(mu0, rn, vn, dt)))
+      return {step0 + i, KEPLER, -1};
     hit = kick_accel(table + (i + 1) * rowlen, np, mu, rcrit, rn, acc);
     for (int k = 0; k < 3; ++k) { r[k] = rn[k]; v[k] = vn[k] + h * acc[k]; }
     if (hit >= 0) return {step0 + i + 1, ENCOUNTER, hit};
@@ -539,6 +642,10 @@ double orc_kepler_fixedk(double ec, double es, double dM, int k, double* F) {
 }
 // Drift of a single two-body orbit (kfix < 0: no fixed-k decision).  fg[4] gets
 // f, g, fdot, gdot when non-null.  Returns 1 on success, 0 on Kepler failure.
+// Universal-variable drift of one state; returns 0 if it failed.
+int orc_drift_universal(double mu, double* r, double* v, double dt) {
+  return drift_universal(mu, r, v, dt);
+}
 int orc_drift(double mu, double* r, double* v, double dt, int kfix, double ftol, double* fg) {
   KepOut o{};
   int ok = drift<double>(mu, r, v, dt, kfix, ftol, &o);
@@ -609,11 +716,14 @@ int64_t orc_ephemeris(double mu0, int np, const double* mu, const double* r, con
 // ----------------------------- test particles -------------------------------
 // Advances n particles (AoS r[n*3], v[n*3], in/out) through the table rows
 // 0..nsteps (row 0 = global step step0).  Writes deact_step (-1 = survived),
-// reason and planet (-1 if none).  Returns wall seconds of the particle loop.
+// reason and planet (-1 if none).  With universal != 0 a drift the elliptic
+// solve refuses is taken in universal variables instead of removing the
+// particle.  Returns wall seconds of the particle loop.
 double orc_particles(double mu0, int np, const double* mu, const double* rcrit, double rmax,
                      const double* table, int64_t nsteps, double dt, int64_t step0,
                      int kfix, double ftol, int64_t n, double* r, double* v,
-                     int64_t* deact_step, int32_t* reason, int32_t* planet, int nthreads) {
+                     int64_t* deact_step, int32_t* reason, int32_t* planet, int nthreads,
+                     int universal) {
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -621,13 +731,70 @@ double orc_particles(double mu0, int np, const double* mu, const double* rcrit, 
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t i = 0; i < n; ++i) {
     Deact d = run_particle<double>(mu0, np, mu, rcrit, rmax, table, nsteps, dt, step0, kfix,
-                                   ftol, r + 3 * i, v + 3 * i);
+                                   ftol, r + 3 * i, v + 3 * i, NoSample(), universal != 0);
     deact_step[i] = d.step;
     reason[i] = d.reason;
     planet[i] = d.planet;
   }
   auto t1 = std::chrono::steady_clock::now();
   return std::chrono::duration<double>(t1 - t0).count();
+}
+
+// Planet table from a history of planet states (sec. 2.2: the planet
+// positions shared by the particles may come from any source, such as
+// interpolation from a history file).  Records k = 0..nrec-1 at strictly
+// increasing times t[k] hold heliocentric positions hr[k][np][3] and
+// velocities hv[k][np][3].  Row n of the table is the time t0 + n dt: each
+// planet's position there is the cubic Hermite interpolant of the two records
+// around it (the cubic matching both positions and both velocities), and h0 =
+// -sum_j mu_j r_j / |r_j|^3 from those positions.  When vtable is not null it
+// receives the interpolant's derivative (the velocities), [nsteps+1][np][3].
+// Returns -1, or the first row whose time lies outside [t[0], t[nrec-1]]
+// (that row and the rest are left unwritten).
+int64_t orc_history_table(int np, const double* mu, int64_t nrec, const double* t,
+                          const double* hr, const double* hv, double t0, double dt,
+                          int64_t nsteps, double* table, double* vtable) {
+  const int rowlen = 3 * np + 3;
+  int64_t k = 0;
+  for (int64_t n = 0; n <= nsteps; ++n) {
+    const double tn = t0 + (double)n * dt;
+    if (!(tn >= t[0] && tn <= t[nrec - 1])) return n;
+    // the record interval [t[k], t[k+1]] containing tn (rows may run either way)
+    while (k > 0 && tn < t[k]) --k;
+    while (k + 1 < nrec - 1 && tn > t[k + 1]) ++k;
+    const int64_t k1 = nrec > 1 ? k + 1 : k;
+    const double h = t[k1] - t[k];
+    const double s = h > 0.0 ? (tn - t[k]) / h : 0.0;
+    // Hermite basis on [0, 1] and its derivative
+    const double h00 = 2.0 * s * s * s - 3.0 * s * s + 1.0;
+    const double h10 = s * s * s - 2.0 * s * s + s;
+    const double h01 = -2.0 * s * s * s + 3.0 * s * s;
+    const double h11 = s * s * s - s * s;
+    const double d00 = 6.0 * s * s - 6.0 * s;
+    const double d10 = 3.0 * s * s - 4.0 * s + 1.0;
+    const double d01 = -6.0 * s * s + 6.0 * s;
+    const double d11 = 3.0 * s * s - 2.0 * s;
+    double* row = table + n * rowlen;
+    double h0[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < np; ++j) {
+      const double* pa = hr + (k * np + j) * 3;
+      const double* pb = hr + (k1 * np + j) * 3;
+      const double* va = hv + (k * np + j) * 3;
+      const double* vb = hv + (k1 * np + j) * 3;
+      for (int c = 0; c < 3; ++c) {
+        row[3 * j + c] = h00 * pa[c] + h10 * h * va[c] + h01 * pb[c] + h11 * h * vb[c];
+        if (vtable)
+          vtable[(n * np + j) * 3 + c] =
+              h > 0.0 ? (d00 * pa[c] + d01 * pb[c]) / h + d10 * va[c] + d11 * vb[c] : va[c];
+      }
+      const double* r = row + 3 * j;
+      const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+      const double r3 = r2 * std::sqrt(r2);
+      for (int c = 0; c < 3; ++c) h0[c] -= mu[j] * r[c] / r3;
+    }
+    for (int c = 0; c < 3; ++c) row[3 * np + c] = h0[c];
+  }
+  return -1;
 }
 
 // Operations of one particle step of the method, per particle: the tally of

@@ -795,3 +795,191 @@ def test_resonant_particle_librates_and_neighbour_circulates(orc):
           f"[{math.degrees(d.lo[0, 0]):.1f}, {math.degrees(d.hi[0, 0]):.1f}] deg", flush=True)
     assert d.flags[0, 0] == 2 and d.flags[1, 0] == 3
     assert d.hi[0, 0] - d.lo[0, 0] < math.radians(150)
+
+
+# ------------------------------------------------------------ planet histories
+def test_history_interpolation_is_exact_for_cubics_and_at_records(orc):
+    """sec. 2.2 (planet positions from any source, such as interpolation of a
+    history): the cubic Hermite interpolant reproduces any cubic trajectory
+    (positions to 1e-15, velocities to 1e-13 relative) between unevenly
+    spaced records, and the records themselves at their own times; h0 is
+    -sum_j mu_j r_j / |r_j|^3 of the interpolated positions."""
+    rng = np.random.default_rng(81)
+    mu = np.array([1e-3, 2e-4, 5e-5]) * W.MU_SUN
+    t = np.sort(np.concatenate([[0.0, 10.0], rng.uniform(0, 10, 15)]))
+    coef = rng.normal(size=(4, 3, 3))
+    coef[0] += np.array([25.0, -3.0, 1.0])
+    pos = lambda x: coef[0] + coef[1] * x + coef[2] * x ** 2 + coef[3] * x ** 3
+    vel = lambda x: coef[1] + 2 * coef[2] * x + 3 * coef[3] * x ** 2
+    hr, hv = np.array([pos(x) for x in t]), np.array([vel(x) for x in t])
+    n, t0, dt = 900, 0.03, 0.011
+    tab, vt = orc.history_table(mu, t, hr, hv, t0, dt, n, keep_velocities=True)
+    times = t0 + np.arange(n + 1) * dt
+    ref = np.array([pos(x) for x in times]).reshape(n + 1, 9)
+    refv = np.array([vel(x) for x in times]).reshape(n + 1, 9)
+    assert np.max(np.abs(tab[:, :9] - ref)) < 1e-15 * np.abs(ref).max() * 8
+    assert np.max(np.abs(vt - refv)) < 1e-13 * np.abs(refv).max()
+    r = ref.reshape(n + 1, 3, 3)
+    h0 = -np.einsum("j,njc->nc", mu, r / np.linalg.norm(r, axis=2, keepdims=True) ** 3)
+    assert np.max(np.abs(tab[:, 9:] - h0)) < 1e-13 * np.abs(h0).max()
+    # at the records' own times (backwards through the history as well)
+    at = orc.history_table(mu, t[::-1][:1], hr[::-1][:1], hv[::-1][:1], t[-1], -1.0, 0)
+    assert np.array_equal(at[0, :9], hr[-1].ravel())
+    even = np.linspace(0, 10, 11)
+    tab2 = orc.history_table(mu, even, np.array([pos(x) for x in even]),
+                             np.array([vel(x) for x in even]), 10.0, -1.0, 10)
+    assert np.allclose(tab2[:, :9], np.array([pos(x) for x in even[::-1]]).reshape(11, 9),
+                       rtol=0, atol=1e-13)
+    with pytest.raises(ValueError):
+        orc.history_table(mu, t, hr, hv, 9.0, 0.5, 10)
+
+
+def test_history_interpolation_converges_at_fourth_order(orc):
+    """Interpolating two-body planet orbits (closed-form states from the
+    textbook element map) sampled every H: the largest position error falls
+    about 16x when H halves."""
+    mu0 = W.MU_SUN
+    mu = np.array([9.55e-4, 5.15e-5]) * mu0
+    a, e = np.array([5.2, 30.1]), np.array([0.05, 0.01])
+    n_mean = np.sqrt((mu0 + mu) / a ** 3)
+
+    def states(times):
+        M = 0.3 + n_mean[None, :] * times[:, None]
+        r, v = W.elements_to_cartesian(mu0 + mu[None, :], a[None, :].repeat(len(times), 0),
+                                       e[None, :].repeat(len(times), 0), np.full(M.shape, 0.02),
+                                       np.full(M.shape, 0.5), np.full(M.shape, 1.0), M)
+        return r, v
+
+    fine = np.linspace(0.0, 40.0, 4001)
+    rf, _ = states(fine)
+    errs = []
+    for H in (0.8, 0.4, 0.2):
+        t = np.arange(0.0, 40.0 + H / 2, H)
+        hr, hv = states(t)
+        tab = orc.history_table(mu, t, hr, hv, 0.0, 0.01, 4000)
+        errs.append(np.max(np.abs(tab[:, :6] - rf.reshape(4001, 6))))
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    print(f"max errors {errs}, ratios {ratios}", flush=True)
+    assert all(12 < q < 20 for q in ratios), ratios
+
+
+# ---------------------------------------------------------- universal variables
+def _hyperbolic_state(mu, a, e, inc, node, peri, H):
+    """Textbook hyperbolic orbit (a < 0, e > 1) at hyperbolic anomaly H, in
+    40-digit arithmetic: perifocal x = |a| (e - cosh H), y = |a| sqrt(e^2-1)
+    sinh H, dH/dt = n / (e cosh H - 1), n = sqrt(mu / |a|^3)."""
+    mpmath.mp.dps = 40
+    A, e, H = abs(mpmath.mpf(a)), mpmath.mpf(e), mpmath.mpf(H)
+    n = mpmath.sqrt(mpmath.mpf(mu) / A ** 3)
+    b = mpmath.sqrt(e * e - 1)
+    x, y = A * (e - mpmath.cosh(H)), A * b * mpmath.sinh(H)
+    Hd = n / (e * mpmath.cosh(H) - 1)
+    vx, vy = -A * mpmath.sinh(H) * Hd, A * b * mpmath.cosh(H) * Hd
+    cO, sO, cw, sw, ci, si = (mpmath.cos(node), mpmath.sin(node), mpmath.cos(peri),
+                              mpmath.sin(peri), mpmath.cos(inc), mpmath.sin(inc))
+    P = [cO * cw - sO * sw * ci, sO * cw + cO * sw * ci, sw * si]
+    Q = [-cO * sw - sO * cw * ci, -sO * sw + cO * cw * ci, cw * si]
+    r = np.array([float(x * P[k] + y * Q[k]) for k in range(3)])
+    v = np.array([float(vx * P[k] + vy * Q[k]) for k in range(3)])
+    return r, v, n
+
+
+def _mp_hyperbolic_anomaly(e, M):
+    """Root of e sinh H - H = M (increasing in H) by 200 bisections, 40 digits."""
+    mpmath.mp.dps = 40
+    lo, hi = mpmath.mpf(-60), mpmath.mpf(60)
+    for _ in range(200):
+        mid = (lo + hi) / 2
+        if e * mpmath.sinh(mid) - mid < M:
+            lo = mid
+        else:
+            hi = mid
+    return (lo + hi) / 2
+
+
+def test_universal_drift_matches_hyperbolic_closed_form(orc):
+    """The universal-variable drift (the high-eccentricity extension of the
+    Kepler step, sec. 2.2) carries hyperbolic orbits (e from 1.001 to 5)
+    along the textbook closed form: from hyperbolic anomaly H0 to H1 with
+    e sinh H - H advanced by n dt (40-digit roots), within 1e-13 relative;
+    it also reproduces the elliptic drift to 1e-13."""
+    rng = np.random.default_rng(101)
+    mu = W.MU_SUN
+    worst = 0.0
+    for _ in range(60):
+        e = float(rng.choice([1.001, 1.05, 1.5, 2.0, 5.0]))
+        a = -float(rng.uniform(1.0, 80.0))
+        inc, node, peri = rng.uniform(0, 3.0), rng.uniform(0, 6.2), rng.uniform(0, 6.2)
+        H0 = float(rng.uniform(-2.0, 2.0))
+        r0, v0, n = _hyperbolic_state(mu, a, e, inc, node, peri, H0)
+        dt = float(rng.uniform(-0.5, 0.5)) / float(n)
+        mpmath.mp.dps = 40
+        M1 = e * mpmath.sinh(H0) - H0 + n * mpmath.mpf(dt)
+        H1 = _mp_hyperbolic_anomaly(mpmath.mpf(e), M1)
+        r1, v1, _ = _hyperbolic_state(mu, a, e, inc, node, peri, H1)
+        ok, rg, vg = orc.drift_universal(mu, r0, v0, dt)
+        assert ok
+        err = max(np.linalg.norm(rg - r1) / np.linalg.norm(r1),
+                  np.linalg.norm(vg - v1) / np.linalg.norm(v1))
+        worst = max(worst, err)
+    print(f"hyperbolic worst relative error {worst:.2e}", flush=True)
+    assert worst < 1e-13
+    for e in (0.0, 0.3, 0.9, 0.99):
+        r, v = W.elements_to_cartesian(mu, np.array([7.0]), np.array([e]), np.array([0.2]),
+                                       np.array([1.0]), np.array([2.0]), np.array([0.5]))
+        ok1, ra, va, _ = orc.drift(mu, r[0], v[0], 0.7)
+        ok2, rb, vb = orc.drift_universal(mu, r[0], v[0], 0.7)
+        assert ok1 and ok2
+        assert np.linalg.norm(ra - rb) < 1e-13 * np.linalg.norm(ra)
+        assert np.linalg.norm(va - vb) < 1e-13 * np.linalg.norm(va)
+
+
+def test_universal_fallback_keeps_unbound_and_near_parabolic_particles(orc):
+    """With the universal fallback the particles the paper's step removes as
+    Kepler failures (an unbound orbit; e = 0.999 whose fixed five Newton steps
+    do not converge) stay active: with no planets their orbits are two-body
+    ones, checked after 50 steps against the closed form (hyperbolic: 40-digit
+    roots; near-parabolic bound orbit: the elliptic closed form), and without
+    the fallback both are removed at step 0."""
+    mu = W.MU_SUN
+    r_h, v_h, n_h = _hyperbolic_state(mu, -20.0, 1.3, 0.1, 0.4, 0.8, -0.5)
+    dt = 0.01 / float(n_h)
+    re_, ve_ = W.elements_to_cartesian(mu, np.array([10.0]), np.array([0.999]), np.zeros(1),
+                                       np.zeros(1), np.zeros(1), np.array([0.0]))
+    dt_e = 0.05 / math.sqrt(mu / 1000.0)
+    none = np.zeros(0)
+    T = 50
+    for r0, v0, step in ((r_h, v_h, dt), (re_[0], ve_[0], dt_e)):
+        table = np.zeros((T + 1, 3))
+        off = orc.particles(mu, none, none, 0.0, table, step, r0[None], v0[None], T)
+        assert off.reason[0] == orc.KEPLER and off.deact_step[0] == 0
+        on = orc.particles(mu, none, none, 0.0, table, step, r0[None], v0[None], T, universal=True)
+        assert on.reason[0] == orc.ACTIVE
+        if r0 is r_h:
+            mpmath.mp.dps = 40
+            e = mpmath.mpf(1.3)
+            M1 = e * mpmath.sinh(mpmath.mpf(-0.5)) + 0.5 + n_h * mpmath.mpf(step) * T
+            H1 = _mp_hyperbolic_anomaly(e, M1)
+            ref, _, _ = _hyperbolic_state(mu, -20.0, 1.3, 0.1, 0.4, 0.8, H1)
+        else:
+            # the elliptic closed form in 40 digits from the start state itself (a planar
+            # orbit at pericentre: r0 = (q, 0, 0), v0 = (0, v, 0), whose a and e the
+            # near-parabolic cancellation in 2/r - v^2/mu makes sensitive to the start's
+            # rounding): E - e sin E = n t by bisection
+            mpmath.mp.dps = 40
+            assert r0[1] == r0[2] == v0[0] == v0[2] == 0.0
+            q, vq = mpmath.mpf(r0[0]), mpmath.mpf(v0[1])
+            alpha = 2 / q - vq * vq / mpmath.mpf(mu)
+            A, e = 1 / alpha, 1 - q * alpha
+            M = mpmath.sqrt(mpmath.mpf(mu) * alpha ** 3) * mpmath.mpf(step) * T
+            lo, hi = mpmath.mpf(0), mpmath.mpf(2 * math.pi)
+            for _ in range(200):
+                mid = (lo + hi) / 2
+                lo, hi = (mid, hi) if mid - e * mpmath.sin(mid) < M else (lo, mid)
+            E = (lo + hi) / 2
+            ref = np.array([float(A * (mpmath.cos(E) - e)),
+                            float(A * mpmath.sqrt(1 - e * e) * mpmath.sin(E)), 0.0])
+
+        err = np.linalg.norm(on.r[0] - ref) / np.linalg.norm(ref)
+        print(f"two-body after {T} universal drifts: relative error {err:.2e}", flush=True)
+        assert err < 1e-11
