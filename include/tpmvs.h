@@ -77,6 +77,17 @@ typedef struct {
   double kepler_ftol;     /* Kepler-failure threshold on |F(x_k)|; 0 = 1e-13         */
   int32_t device;         /* HIP device ordinal                                      */
   int32_t time_kernels;   /* 1: bracket every particle launch with HIP events        */
+  /* High-eccentricity extensions of the Kepler step (sec. 2.2, Kepler-solver
+   * paragraph, where the paper proposes them as future work):             */
+  int32_t universal_drift;/* 1: a drift the fixed-iteration solve refuses (unbound or
+                             near-parabolic orbit, |F(x_k)| > kepler_ftol) is taken in
+                             universal variables instead, and the particle is removed
+                             as TPM_KEPLER only if that gives no finite result; 0 = off */
+  int32_t sort_by_e;      /* 1: order the working set by decreasing osculating
+                             eccentricity bin (bins of 0.1; unbound orbits first), so
+                             wavefronts hold particles of similar Newton counts and the
+                             most eccentric tiles are taken first; never changes
+                             results; 0 = caller order                                */
 } tpm_options;
 
 typedef struct {
@@ -94,6 +105,9 @@ typedef struct {
   int64_t count_by_reason[4];     /* over all particles                           */
   int32_t sub_chunks;             /* work-queue shape used (after autotuning)     */
   int32_t waves_per_simd;
+  int32_t block_threads;          /* workgroup size, chunk length and compaction  */
+  int32_t chunk_steps;            /* interval used (after autotuning)             */
+  int32_t resync_chunks;
 } tpm_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -166,6 +180,55 @@ int tpm_get_stats(tpm_sim* sim, tpm_stats* out);
 int tpm_get_state(tpm_sim* sim, void* buf, int64_t* size);
 int tpm_set_state(tpm_sim* sim, const void* buf, int64_t size);
 
+/* ---- sampled diagnostics and snapshots ---------------------------------------
+ * The paper's applications read orbital elements logged at a fixed interval
+ * (sec. 4.2: every 2,048 yr) and its integrator copies the particle arrays
+ * back to the host after a configurable number of chunks for periodic output
+ * (sec. 2.2).  With diagnostics on, every global step boundary that is a
+ * multiple of `every` (a particle launch ends there; the first boundary of an
+ * integrate call is sampled too unless it already was) samples each particle
+ * that is active there and passes that boundary's removal test:
+ *  - its osculating heliocentric eccentricity about mu0, keeping the largest
+ *    and the first sampled step that reached it (sec. 3.3);
+ *  - for each of nres (0..2) resonances p:q with the reference planet, the
+ *    resonant angle phi = p lambda - q lambda_ref - (p - q) varpi (sec. 4.1;
+ *    lambda mean longitude, varpi longitude of pericentre, the planet's
+ *    elements about mu0 + mu_ref).  flags[i][k] bit 0 records a sample with
+ *    phi within 10 degrees of 0, bit 1 one within 10 degrees of 180 degrees;
+ *    the paper's libration criterion (sec. 4.2: never within 10 degrees of one
+ *    of them) holds unless both bits are set.  phi_lo/phi_hi[i][k] bound
+ *    phi - 180 degrees, folded into (-180, 180] degrees (radians).
+ * A snapshot callback (may be NULL) receives, at each sample, every particle
+ * in the caller's order: r, v [n][3]; deact_step, reason as in
+ * tpm_get_particles (a particle removed at the sample's own step shows its
+ * removal); its osculating elements [n][6] (a, e, inc, node, peri, M about
+ * mu0, radians; from the removal state for removed particles).  The arrays
+ * live in library memory, valid during the call only.  It runs on the thread
+ * inside tpm_integrate, in step order, at most two samples behind the GPU,
+ * and must not call the library.
+ * Resonant angles need the planets' velocities: with a supplied planet table
+ * tpm_integrate returns TPM_ESTATE.  tpm_set_diagnostics (after planets and
+ * particles; every = 0 or opt NULL turns it off) starts the accumulators
+ * afresh: e_max -1, its step -1, flags 0, phi_lo +inf, phi_hi -inf.
+ * tpm_set_planets, tpm_set_particles and tpm_set_state turn diagnostics off.
+ * The batched and no-allocation entry points do not sample. */
+typedef void (*tpm_snapshot_fn)(void* user, int64_t step, int64_t n, const double* r,
+                                const double* v, const int64_t* deact_step,
+                                const int32_t* reason, const double* elements);
+typedef struct {
+  int64_t every;          /* sample interval in steps (> 0); 0 = off                 */
+  int32_t ref_planet;     /* caller index of the resonances' planet                  */
+  int32_t nres;           /* 0..2                                                    */
+  int32_t p[2], q[2];     /* resonance k is p[k]:q[k] (e.g. 3:1, 5:2 with Neptune)   */
+  tpm_snapshot_fn snapshot;
+  void* user;             /* passed to snapshot                                      */
+} tpm_diag_options;
+int tpm_set_diagnostics(tpm_sim* sim, const tpm_diag_options* opt);
+/* emax[n], emax_step[n], flags[n][nres], phi_lo[n][nres], phi_hi[n][nres]
+ * (caller order; any may be NULL).  TPM_ESTATE when diagnostics are off. */
+int tpm_get_diagnostics(tpm_sim* sim, double* emax, int64_t* emax_step, int32_t* flags,
+                        double* phi_lo, double* phi_hi);
+
 /* Hill radius a_p (mu_p / (3 mu0))^(1/3) (sec. 2.2, encounter criterion). */
 double tpm_hill_radius(double mu0, double mu_p, double a_p);
 
@@ -183,6 +246,24 @@ int tpm_planet_table(tpm_sim* sim, int64_t nsteps, double dt, double* table);
  * global step n) instead of the on-device planet map, from now on; nrows <= 0
  * returns to the planet map.  Meant for checking the particle kernel alone. */
 int tpm_set_planet_table(tpm_sim* sim, const double* table, int64_t nrows);
+
+/* Take the planet positions from a history instead of the on-device planet map
+ * (sec. 2.2: they may come from any source, such as interpolation from a
+ * history file), from now on.  nrec records at strictly increasing times
+ * t[nrec] hold heliocentric planet positions r[nrec][np][3] and velocities
+ * v[nrec][np][3] (caller planet order, as in tpm_set_planets; host arrays,
+ * copied).  Row n of every run (global step n) lies at time t0 + n dt; each
+ * planet there follows the cubic Hermite interpolant of the two records around
+ * that time (matching both positions and both velocities), and h0 is computed
+ * from the interpolated positions.  The rows of each chunk are interpolated on
+ * the device, one thread per row.  tpm_integrate returns TPM_EINVAL (before any
+ * work) if a row's time leaves [t[0], t[nrec-1]]; tpm_get_planets returns the
+ * interpolated state at the current step; tpm_planet_table the interpolated
+ * rows.  No planet-planet test runs (the planets are not integrated).  nrec <= 0
+ * returns to the planet map (its state is where tpm_set_planets left it).  It
+ * replaces a supplied planet table and vice versa. */
+int tpm_set_planet_history(tpm_sim* sim, int64_t nrec, const double* t, const double* r,
+                           const double* v, double t0);
 
 /* ---- derivatives of the particle map ---------------------------------------
  * Device-pointer calls for autograd frameworks: every array is caller-owned
@@ -221,14 +302,20 @@ int tpm_ad_tangent(tpm_sim* sim, const double* d_dR0, const double* d_dV0, doubl
  * vp[.][3], rcrit) and particles part_off[s]..part_off[s+1]-1 (r[.][3],
  * v[.][3]); mu0[s], dt[s].  Outputs as in tpm_get_particles (planet indices
  * local to the particle's system, caller order).  r_escape, kepler_iters,
- * kepler_ftol, chunk_steps, block_threads and device come from opt (NULL =
- * defaults); sub_chunks / waves_per_simd <= 0 select them by timing a short
- * trial of each candidate (the choice is cached and never changes results).
- * The planet maps of all systems run as one launch per chunk and the
- * particles of all systems as one work queue (tiles of 64 particles of one
- * system, most planets first); the whole run is captured into one HIP graph
- * and launched once.  stats (may be NULL) receives the graph's run time and
- * the active particle-steps.  planet_flag (may be NULL) receives per system
+ * kepler_ftol and device come from opt (NULL = defaults).  block_threads,
+ * chunk_steps, sub_chunks, waves_per_simd and resync_chunks that are 0 are
+ * chosen by an autotuner: it times one chunk of each candidate (workgroup size
+ * 64 or 256, chunk length 512, 1,024 or 2,048 steps, five work-queue shapes)
+ * from the initial state, per step, and sets the compaction interval so that
+ * one compaction costs under 1% of the chunks it follows; choices are cached
+ * per (device, systems, particles, steps, planet-count histogram, fixed
+ * options) and never change results.  The planet maps of all systems run as
+ * one launch per chunk and the particles of all systems as one work queue
+ * (tiles of 64 particles of one system, most planets first); every
+ * resync_chunks chunks the working set is compacted and the tiles rebuilt on
+ * the device.  The whole run is captured into one HIP graph and launched once.
+ * stats (may be NULL) receives the graph's run time, the active
+ * particle-steps and the chosen shape.  planet_flag (may be NULL) receives per system
  * the first of these events: -1 none, t >= 0 two planets within a mutual
  * Hill radius at step t, -2 a planet orbit found unbound in a drift (before
  * any close pair; it wins a tie with a pair seen at the end of the same step).
@@ -286,6 +373,13 @@ int tpm_debug_rsqrt(int64_t n, const double* x, double* out);
  * vz) by dt; ok[n] = 0 where the drift was refused (TPM_KEPLER rule). */
 int tpm_debug_drift(double mu, int64_t n, const double* rv_in, double* rv_out, int32_t* ok,
                     double dt, int32_t kepler_iters, double kepler_ftol);
+/* The universal-variable drift (see tpm_options.universal_drift) of each
+ * rv[n][6] by dt about mu: mode 1 as the particle kernel takes it (the five-
+ * iteration solve first, the universal drift where that is refused), mode 2
+ * the universal drift alone; ok[n] = 0 where no finite result was reached
+ * (rv_out then holds the input state).  Host arrays. */
+int tpm_debug_drift_universal(double mu, int64_t n, const double* rv_in, double* rv_out,
+                              int32_t* ok, double dt, int32_t mode);
 
 #ifdef __cplusplus
 }

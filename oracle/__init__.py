@@ -88,7 +88,7 @@ def _load():
         lib.orc_count_ops.argtypes = [d, i, P, P, d, P, d, i, d, i64, P, P, P]
         lib.orc_count_ops.restype = i64
         lib.orc_particles_diag.argtypes = [d, i, P, P, d, P, i64, d, i64, i, d, i64, P, P, P, P, P,
-                                           i, i64, P, i, P, P, P, P, P, P, P]
+                                           i, i64, P, i, P, P, P, P, P, P, P, P]
         lib.orc_particles_diag.restype = d
         lib.orc_history_table.argtypes = [i, P, i64, P, P, P, d, d, i64, P, P]
         lib.orc_history_table.restype = i64
@@ -310,6 +310,7 @@ class Diagnostics:
     flags: np.ndarray       # (n, nres): bit 0 phi within 10 deg of 0, bit 1 within 10 deg of 180
     lo: np.ndarray          # (n, nres): range of phi - 180 deg over the samples, radians
     hi: np.ndarray
+    margin: np.ndarray      # (n, nres): least distance of |phi| or |phi - 180 deg| from 10 deg
 
 
 def diagnostics(mu0, mu, rcrit, rmax, eph: Ephemeris, dt, r, v, nsteps, every, ref=None,
@@ -344,13 +345,14 @@ def diagnostics(mu0, mu, rcrit, rmax, eph: Ephemeris, dt, r, v, nsteps, every, r
     flags = np.zeros((n, max(nres, 1)), np.int32)
     lo = np.zeros((n, max(nres, 1)))
     hi = np.zeros((n, max(nres, 1)))
+    margin = np.zeros((n, max(nres, 1)))
     secs = _load().orc_particles_diag(
         float(mu0), npl, _ptr(mu), _ptr(rcrit), float(rmax), _ptr(table), int(nsteps), float(dt),
         0, int(kepler_iters), float(ftol), n, _ptr(r), _ptr(v), _ptr(ds), _ptr(rs), _ptr(pl),
         int(nthreads), int(every), _ptr(lam_rows) if lam_rows is not None else None, nres,
-        _ptr(pq), _ptr(qq), _ptr(emax), _ptr(estep), _ptr(flags), _ptr(lo), _ptr(hi))
+        _ptr(pq), _ptr(qq), _ptr(emax), _ptr(estep), _ptr(flags), _ptr(lo), _ptr(hi), _ptr(margin))
     return Diagnostics(Result(r, v, ds, rs, pl, secs), emax, estep, flags[:, :nres], lo[:, :nres],
-                       hi[:, :nres])
+                       hi[:, :nres], margin[:, :nres])
 
 
 # ------------------------------------------------------- operation count

@@ -513,6 +513,7 @@ struct DiagSampler {
   int32_t* flags;
   double* lo;
   double* hi;
+  double* margin;              // nearest approach of |phi| or |phi - 180 deg| to 10 degrees
   void operator()(int64_t n, int64_t row, const double* r, const double* v) const {
     if (n % every != 0) return;
     const Elements el = elements_of(mu0, r, v);
@@ -530,6 +531,8 @@ struct DiagSampler {
       if (std::fabs(w180) < kTenDeg) flags[k] |= 2;
       lo[k] = std::fmin(lo[k], w180);
       hi[k] = std::fmax(hi[k], w180);
+      margin[k] = std::fmin(margin[k], std::fmin(std::fabs(std::fabs(w0) - kTenDeg),
+                                                 std::fabs(std::fabs(w180) - kTenDeg)));
     }
   }
 };
@@ -842,7 +845,7 @@ double orc_particles_diag(double mu0, int np, const double* mu, const double* rc
                           int32_t* reason, int32_t* planet, int nthreads, int64_t every,
                           const double* lam_rows, int nres, const int* p, const int* q,
                           double* emax, int64_t* emax_step, int32_t* flags, double* lo,
-                          double* hi) {
+                          double* hi, double* margin) {
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -855,9 +858,10 @@ double orc_particles_diag(double mu0, int np, const double* mu, const double* rc
       flags[nres * i + k] = 0;
       lo[nres * i + k] = INFINITY;
       hi[nres * i + k] = -INFINITY;
+      margin[nres * i + k] = INFINITY;
     }
     DiagSampler smp{mu0, every, lam_rows, nres, p, q, emax + i, emax_step + i, flags + nres * i,
-                    lo + nres * i, hi + nres * i};
+                    lo + nres * i, hi + nres * i, margin + nres * i};
     Deact d = run_particle<double>(mu0, np, mu, rcrit, rmax, table, nsteps, dt, step0, kfix,
                                    ftol, r + 3 * i, v + 3 * i, smp);
     deact_step[i] = d.step;

@@ -35,7 +35,8 @@ class Options(C.Structure):
                 ("resync_chunks", C.c_int32), ("block_threads", C.c_int32),
                 ("sub_chunks", C.c_int32), ("waves_per_simd", C.c_int32),
                 ("r_escape", C.c_double), ("kepler_ftol", C.c_double), ("device", C.c_int32),
-                ("time_kernels", C.c_int32)]
+                ("time_kernels", C.c_int32), ("universal_drift", C.c_int32),
+                ("sort_by_e", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -44,12 +45,23 @@ class Stats(C.Structure):
                 ("particle_ms", C.c_double), ("ephemeris_ms", C.c_double), ("chunks", C.c_int64),
                 ("particle_kernel_ms", C.c_double), ("compactions", C.c_int64),
                 ("count_by_reason", C.c_int64 * 4), ("sub_chunks", C.c_int32),
-                ("waves_per_simd", C.c_int32)]
+                ("waves_per_simd", C.c_int32), ("block_threads", C.c_int32),
+                ("chunk_steps", C.c_int32), ("resync_chunks", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "count_by_reason"}
         d["count_by_reason"] = list(self.count_by_reason)
         return d
+
+
+SNAPSHOT_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                          C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class DiagOptions(C.Structure):
+    _fields_ = [("every", C.c_int64), ("ref_planet", C.c_int32), ("nres", C.c_int32),
+                ("p", C.c_int32 * 2), ("q", C.c_int32 * 2), ("snapshot", SNAPSHOT_FN),
+                ("user", C.c_void_p)]
 
 
 # Exported symbols and their signatures; the tests check the library against this list
@@ -74,6 +86,8 @@ SIGNATURES = {
     "tpm_debug_rsqrt": (C.c_int, [C.c_int64, _P, _P]),
     "tpm_debug_drift": (C.c_int, [C.c_double, C.c_int64, _P, _P, _P, C.c_double, C.c_int32,
                                   C.c_double]),
+    "tpm_debug_drift_universal": (C.c_int, [C.c_double, C.c_int64, _P, _P, _P, C.c_double,
+                                            C.c_int32]),
     "tpm_ad_forward": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int64, C.c_double, C.c_int32, _P, _P,
                                  _P, _P, _P]),
     "tpm_ad_backward": (C.c_int, [_P] * 6),
@@ -81,6 +95,9 @@ SIGNATURES = {
     "tpm_batch_integrate": (C.c_int, [C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_int64,
                                       _P, _P, _P, _P, _P, _P, _P, _P]),
     "tpm_get_state": (C.c_int, [_P, _P, _P]),
+    "tpm_set_diagnostics": (C.c_int, [_P, _P]),
+    "tpm_set_planet_history": (C.c_int, [_P, C.c_int64, _P, _P, _P, C.c_double]),
+    "tpm_get_diagnostics": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "tpm_set_state": (C.c_int, [_P, _P, C.c_int64]),
     "tpm_integrate_static": (C.c_int, [_P, C.c_double, C.c_int32, _P, _P, _P, _P, C.c_int64, _P, _P,
                                        C.c_int64, C.c_double, _P, _P, _P, _P, _P, _P, _P]),
@@ -143,7 +160,8 @@ class Simulation:
     def __init__(self, kepler_iters: int = 5, chunk_steps: int = 0, resync_chunks: int = 0,
                  block_threads: int = 0, r_escape: float = 0.0, kepler_ftol: float = 0.0,
                  device: int = 0, time_kernels: bool = False, sub_chunks: int = 0,
-                 waves_per_simd: int = 0):
+                 waves_per_simd: int = 0, universal_drift: bool = False,
+                 sort_by_e: bool = False):
         lib = load()
         o = default_options()
         o.kepler_iters, o.chunk_steps, o.resync_chunks = kepler_iters, chunk_steps, resync_chunks
@@ -151,6 +169,7 @@ class Simulation:
                                                                 kepler_ftol, device)
         o.time_kernels = int(bool(time_kernels))
         o.sub_chunks, o.waves_per_simd = sub_chunks, waves_per_simd
+        o.universal_drift, o.sort_by_e = int(bool(universal_drift)), int(bool(sort_by_e))
         h = C.c_void_p()
         _check(lib.tpm_create(C.byref(o), C.byref(h)))
         self._h = h
@@ -230,10 +249,56 @@ class Simulation:
         self.np = int(np.frombuffer(bytes(blob[12:16]), dtype=np.int32)[0])
         self.n = int(hdr[2])
 
+    def set_diagnostics(self, every: int, ref_planet: int = -1, resonances=(), snapshot=None):
+        """Sampled diagnostics every `every` steps (tpm_set_diagnostics):
+        e_max and its step, and for each resonance (p, q) with planet
+        `ref_planet` the 10-degree flags and the range of phi - 180 degrees.
+        `snapshot(step, dict)` (optional) receives copies of r, v, deact_step,
+        reason and elements at every sample."""
+        o = DiagOptions()
+        o.every, o.ref_planet, o.nres = int(every), int(ref_planet), len(resonances)
+        for k, (p, q) in enumerate(resonances):
+            o.p[k], o.q[k] = int(p), int(q)
+        self._snap_cb = None
+        if snapshot is not None:
+            def cb(user, step, n, r, v, st, rs, el):
+                def arr(ptr, dtype, shape):
+                    count = int(np.prod(shape))
+                    buf = (C.c_char * (count * np.dtype(dtype).itemsize)).from_address(ptr)
+                    return np.frombuffer(buf, dtype=dtype).reshape(shape).copy()
+                snapshot(int(step), {"r": arr(r, np.float64, (n, 3)), "v": arr(v, np.float64, (n, 3)),
+                                     "deact_step": arr(st, np.int64, (n,)),
+                                     "reason": arr(rs, np.int32, (n,)),
+                                     "elements": arr(el, np.float64, (n, 6))})
+            self._snap_cb = SNAPSHOT_FN(cb)
+            o.snapshot = self._snap_cb
+        self._nres = len(resonances)
+        _check(load().tpm_set_diagnostics(self._h, C.byref(o)))
+
+    def diagnostics(self):
+        n, k = self.n, max(self._nres, 0)
+        emax = np.zeros(n)
+        estep = np.zeros(n, np.int64)
+        flags = np.zeros((n, k), np.int32)
+        lo, hi = np.zeros((n, k)), np.zeros((n, k))
+        _check(load().tpm_get_diagnostics(self._h, _p(emax), _p(estep), _p(flags), _p(lo), _p(hi)))
+        return {"emax": emax, "emax_step": estep, "flags": flags, "lo": lo, "hi": hi}
+
     def planet_table(self, nsteps: int, dt: float):
         t = np.zeros((nsteps + 1, 3 * self.np + 3))
         _check(load().tpm_planet_table(self._h, int(nsteps), float(dt), _p(t)))
         return t
+
+    def set_planet_history(self, t, r, v, t0: float = 0.0):
+        """Planets from a history of states (tpm_set_planet_history): times
+        t[nrec], heliocentric r, v [nrec][np][3]; row n at time t0 + n dt.
+        t None turns it off."""
+        if t is None:
+            _check(load().tpm_set_planet_history(self._h, 0, None, None, None, 0.0))
+            return
+        t = _f64(t, (-1,))
+        r, v = _f64(r, (t.shape[0], self.np, 3)), _f64(v, (t.shape[0], self.np, 3))
+        _check(load().tpm_set_planet_history(self._h, t.shape[0], _p(t), _p(r), _p(v), float(t0)))
 
     def set_planet_table(self, table):
         if table is None:
@@ -269,8 +334,21 @@ def debug_drift(mu, r, v, dt, kepler_iters=5, kepler_ftol=0.0):
     return out[:, :3], out[:, 3:], ok.astype(bool)
 
 
+def debug_drift_universal(mu, r, v, dt, mode=2):
+    """Universal-variable drift (mode 2), or the particle kernel's drift with
+    the universal fallback (mode 1); returns (r, v, ok)."""
+    r = _f64(r, (-1, 3))
+    v = _f64(v, (r.shape[0], 3))
+    rv = np.ascontiguousarray(np.concatenate([r, v], axis=1))
+    out = np.zeros_like(rv)
+    ok = np.zeros(r.shape[0], np.int32)
+    _check(load().tpm_debug_drift_universal(float(mu), r.shape[0], _p(rv), _p(out), _p(ok),
+                                            float(dt), int(mode)))
+    return out[:, :3], out[:, 3:], ok.astype(bool)
+
+
 def batch_integrate(systems, nsteps=None, r_escape=None, kepler_iters=5, chunk_steps=0,
-                    sub_chunks=0, waves_per_simd=0, block_threads=0, strict=True):
+                    sub_chunks=0, waves_per_simd=0, block_threads=0, resync_chunks=0, strict=True):
     """Integrate many independent systems (workload objects) in one launch.
 
     Returns (per-system list of result dicts, stats dict).  The stats carry
@@ -295,6 +373,7 @@ def batch_integrate(systems, nsteps=None, r_escape=None, kepler_iters=5, chunk_s
     o = default_options()
     o.kepler_iters, o.chunk_steps, o.sub_chunks = kepler_iters, chunk_steps, sub_chunks
     o.waves_per_simd, o.block_threads = waves_per_simd, block_threads
+    o.resync_chunks = resync_chunks
     o.r_escape = systems[0].rmax if r_escape is None else r_escape
     n = int(qoff[-1])
     ro, vo = np.zeros((n, 3)), np.zeros((n, 3))

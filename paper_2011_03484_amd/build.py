@@ -8,8 +8,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpmvs.so")
-SOURCES = ["kernels_core.hip", "ad_kernels.hip", "runtime.hip", "static_run.hip"]
-HEADERS = ["dmath.hpp", "kepler.hpp", "particle.hpp", "ad.hpp", "internal.h", "ad_internal.h"]
+SOURCES = ["kernels_core.hip", "ad_kernels.hip", "diag_kernels.hip", "history.hip",
+           "runtime.hip", "static_run.hip"]
+HEADERS = ["dmath.hpp", "kepler.hpp", "particle.hpp", "universal.hpp", "ad.hpp", "internal.h",
+           "ad_internal.h", "diag_internal.h", "history_internal.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -43,6 +43,7 @@ struct SysConst {
   double rmax2;          // +inf when escape is off
   int kiters;
   double ftol;
+  int universal;         // 1: refused drifts are retried in universal variables
 };
 
 // Ephemeris constants (bodies 0..np, body 0 = central mass).
@@ -78,10 +79,12 @@ hipError_t launch_particle_chunk(const SysConst& S, Work w, const int32_t* d_nac
 
 // Ephemeris chunk: advances the Jacobi state (rj, vj: [np][3]) by nsteps and
 // writes rows[0..nsteps]; flag receives the first step of a planet close
-// approach (or -2 for an unbound planet) if it is still -1.
+// approach (or -2 for an unbound planet) if it is still -1.  vside (may be
+// null) receives the heliocentric planet velocities at rows 0 and nsteps,
+// [2][np][3].
 hipError_t launch_ephemeris_chunk(const EphConst& E, double* rj, double* vj, double* rows,
                                   int nsteps, double dt, int64_t step0, int64_t* flag,
-                                  hipStream_t st);
+                                  hipStream_t st, double* vside = nullptr);
 
 // Stable partition of the working set: active entries of src (in order) go to
 // dst; d_nactive is updated in place.  scratch holds >= 2 * nblocks + 1 ints.
@@ -130,6 +133,7 @@ struct BatchQueueArgs {
   int slot;
   int64_t slot_rows;     // rows per ring slot (chunk + 1)
   int32_t* error;
+  const int32_t* ntiles_dev;   // non-null: the tile count is read here (runs that compact)
 };
 
 hipError_t launch_ephemeris_batch(const EphConst* E, double* rj, double* vj, double* ring,
@@ -141,10 +145,20 @@ hipError_t launch_helio_to_jacobi_batch(const EphConst* E, const double* h, doub
 hipError_t launch_particle_batch(const SysDev* sys, const TileDesc* tiles, Work w, Out out,
                                  const double* ring, const BatchQueueArgs& Q, int workers,
                                  int block, hipStream_t st);
+// Rebuild the tiles after a compaction of a batched working set (grouped by
+// system): psys[slot] is a particle's system, sorder the systems in queue
+// order; start/end are [nsys] scratch; the tile count goes to ntiles_dev.
+hipError_t launch_batch_retile(Work w, const int32_t* d_nactive, int n_upper, const int32_t* psys,
+                               const int32_t* sorder, int nsys, int32_t* start, int32_t* end,
+                               TileDesc* tiles, int32_t* ntiles_dev, hipStream_t st);
+// Zero a work-queue item counter (a kernel, so it can sit in a captured graph).
+hipError_t launch_queue_reset(unsigned long long* ctr, hipStream_t st);
 
 // Unit checks of the device math (test entry points).
 hipError_t launch_sincos_test(const double* x, double* s, double* c, int n, hipStream_t st);
 hipError_t launch_rsqrt_test(const double* x, double* out, int n, hipStream_t st);
+// S.universal: 0 fixed-iteration drift, 1 with the universal fallback, 2
+// universal drift alone.
 hipError_t launch_drift_test(const SysConst& S, const double* rv_in, double* rv_out, int32_t* ok,
                              int n, double dt, hipStream_t st);
 

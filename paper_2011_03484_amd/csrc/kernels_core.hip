@@ -15,6 +15,7 @@
 //  * finalize        - scatter the active particles back to caller order.
 #include "internal.h"
 #include "particle.hpp"
+#include "universal.hpp"
 
 namespace tpm {
 
@@ -35,7 +36,11 @@ struct ChunkArgs {
 // and the wavefront leaves early once none is active.  KIT > 0 fixes the
 // Newton count at compile time; PREFETCH fetches each planet row a step
 // ahead into VGPRs (for launches with about one wavefront per SIMD).
-template <int NP, int KIT, bool PREFETCH>
+//
+// UNIV: a drift the fixed-iteration solve refuses is taken in universal
+// variables instead (drift_universal); the particle is removed as KEPLER only
+// if that gives no finite result either.
+template <int NP, int KIT, bool PREFETCH, bool UNIV = false>
 TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const ChunkArgs<NP>& A,
                      int i, bool valid, int s_begin, int s_end) {
   constexpr int ROW = 3 * NP + 3;
@@ -74,7 +79,14 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
     if (reason == ST_ACTIVE) {
       double nx = x, ny = y, nz = z;
       double nvx = fma_(h, ax, vx), nvy = fma_(h, ay, vy), nvz = fma_(h, az, vz);
-      const bool ok = drift_fixed(A.K, A.dt, kiters, A.ftol, nx, ny, nz, nvx, nvy, nvz);
+      bool ok = drift_fixed(A.K, A.dt, kiters, A.ftol, nx, ny, nz, nvx, nvy, nvz);
+      if (UNIV && !wave_all(ok)) {
+        if (!ok) {
+          nx = x; ny = y; nz = z;
+          nvx = fma_(h, ax, vx); nvy = fma_(h, ay, vy); nvz = fma_(h, az, vz);
+          ok = drift_universal(A.K.mu, A.dt, nx, ny, nz, nvx, nvy, nvz);
+        }
+      }
       double bx, by, bz;
       const int hit1 = accel<NP>(row, A.P, nx, ny, nz, bx, by, bz);
       const double r2 = fma_(nx, nx, fma_(ny, ny, nz * nz));
@@ -152,7 +164,7 @@ TPM_DEV unsigned long long wave_uniform(unsigned long long v) {
 // and the publish are executed by the whole wavefront (lane 0 alone adds 1 to
 // the counter), so the readfirstlane that makes their results wave-uniform
 // always sees the full wavefront and the loop's branches stay scalar.
-template <int NP, int KIT>
+template <int NP, int KIT, bool UNIV>
 __global__ void __launch_bounds__(256)
 particle_queue(Work w, const int32_t* __restrict__ d_nactive, Out out,
                const double* __restrict__ rows, ChunkArgs<NP> A, QueueArgs Q) {
@@ -189,7 +201,7 @@ particle_queue(Work w, const int32_t* __restrict__ d_nactive, Out out,
     const int s_end = min(Q.nsteps, s_begin + Q.sub_steps);
     if (go && s_begin < s_end) {       // the last sub-chunks of a short chunk may be empty
       const int i = t * 64 + lane;
-      advance<NP, KIT, true>(w, out, rows, A, i, i < n, s_begin, s_end);
+      advance<NP, KIT, true, UNIV>(w, out, rows, A, i, i < n, s_begin, s_end);
     }
     // publish completion; the release orders every store of this item
     __hip_atomic_store(Q.progress + t, Q.epoch + (uint32_t)s + 1u, __ATOMIC_RELEASE,
@@ -231,13 +243,15 @@ __global__ void __launch_bounds__(256)
 particle_batch_queue(const SysDev* __restrict__ sys, const TileDesc* __restrict__ tiles, Work w,
                      Out out, const double* __restrict__ ring, BatchQueueArgs Q) {
   const int lane = threadIdx.x & 63;
-  const unsigned long long total = (unsigned long long)Q.ntiles * Q.nsub;
+  // the tile count of a run that compacts lives on the device (batch_tiles)
+  const int ntiles = Q.ntiles_dev ? *Q.ntiles_dev : Q.ntiles;
+  const unsigned long long total = (unsigned long long)ntiles * Q.nsub;
   const unsigned long long one = lane == 0 ? 1ull : 0ull;
   for (;;) {
     const unsigned long long item = wave_uniform(atomicAdd(Q.ctr, one) - Q.base);
     if (item >= total) break;
-    const int s = (int)(item / Q.ntiles);
-    const int t = (int)(item % Q.ntiles);
+    const int s = (int)(item / ntiles);
+    const int t = (int)(item % ntiles);
     bool go = true;
     if (s > 0) {
       const uint32_t target = Q.epoch + (uint32_t)s;
@@ -291,6 +305,83 @@ hipError_t launch_particle_batch(const SysDev* sys, const TileDesc* tiles, Work 
   return hipGetLastError();
 }
 
+// ---- compaction inside a batched run (captured in its graph)
+// After a stable partition of the whole working set (launch_compact), each
+// system's active particles are still contiguous and in order, so the tiles
+// are rebuilt from each system's range [start, end) in the new working set:
+// batch_bounds finds the ranges from the slots' systems, batch_tiles lays the
+// systems' tiles out in the queue's order (most planets first) and stores the
+// new tile count for the next particle launch.
+__global__ void __launch_bounds__(256) batch_bounds_clear(int nsys, int32_t* start, int32_t* end) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nsys) { start[s] = 0; end[s] = 0; }
+}
+
+__global__ void __launch_bounds__(256)
+batch_bounds(const int32_t* __restrict__ slot, const int32_t* __restrict__ d_nactive,
+             const int32_t* __restrict__ psys, int32_t* __restrict__ start,
+             int32_t* __restrict__ end) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = *d_nactive;
+  if (i >= n) return;
+  const int s = psys[slot[i]];
+  if (i == 0 || psys[slot[i - 1]] != s) start[s] = i;
+  if (i == n - 1 || psys[slot[i + 1]] != s) end[s] = i + 1;
+}
+
+__global__ void __launch_bounds__(1024)
+batch_tiles(const int32_t* __restrict__ sorder, int nsys, const int32_t* __restrict__ start,
+            const int32_t* __restrict__ end, TileDesc* __restrict__ tiles,
+            int32_t* __restrict__ ntiles_dev) {
+  __shared__ int buf[1024];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nsys; base += 1024) {
+    const int k = base + threadIdx.x;
+    const int s = k < nsys ? sorder[k] : 0;
+    const int cnt = k < nsys ? end[s] - start[s] : 0;
+    const int nt = (cnt + 63) / 64;
+    buf[threadIdx.x] = nt;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int t = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += t;
+      __syncthreads();
+    }
+    const int first = carry + buf[threadIdx.x] - nt;
+    for (int j = 0; j < nt; ++j)
+      tiles[first + j] = TileDesc{s, start[s] + 64 * j, min(64, cnt - 64 * j), 0};
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += buf[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *ntiles_dev = carry;
+}
+
+__global__ void __launch_bounds__(64) queue_reset(unsigned long long* ctr) {
+  if (threadIdx.x == 0) *ctr = 0ull;
+}
+
+hipError_t launch_batch_retile(Work w, const int32_t* d_nactive, int n_upper, const int32_t* psys,
+                               const int32_t* sorder, int nsys, int32_t* start, int32_t* end,
+                               TileDesc* tiles, int32_t* ntiles_dev, hipStream_t st) {
+  hipLaunchKernelGGL(batch_bounds_clear, dim3((nsys + 255) / 256), dim3(256), 0, st, nsys, start,
+                     end);
+  if (n_upper > 0)
+    hipLaunchKernelGGL(batch_bounds, dim3((n_upper + 255) / 256), dim3(256), 0, st, w.slot,
+                       d_nactive, psys, start, end);
+  hipLaunchKernelGGL(batch_tiles, dim3(1), dim3(1024), 0, st, sorder, nsys, start, end, tiles,
+                     ntiles_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_queue_reset(unsigned long long* ctr, hipStream_t st) {
+  hipLaunchKernelGGL(queue_reset, dim3(1), dim3(64), 0, st, ctr);
+  return hipGetLastError();
+}
+
 template <int NP>
 static hipError_t launch_np(const SysConst& S, Work w, const int32_t* d_nactive, int grid_n,
                             Out out, const double* rows, int nsteps, double dt, int64_t step0,
@@ -318,12 +409,15 @@ static hipError_t launch_np(const SysConst& S, Work w, const int32_t* d_nactive,
   if (Q.ntiles <= 0) return hipSuccess;
   const int waves_per_block = QL.block / 64;
   const int nblocks = (QL.workers + waves_per_block - 1) / waves_per_block;
-  if (S.kiters == 5)
-    hipLaunchKernelGGL((particle_queue<NP, 5>), dim3(nblocks), dim3(QL.block), 0, st, w, d_nactive,
-                       out, rows, A, Q);
+  if (S.universal)
+    hipLaunchKernelGGL((particle_queue<NP, 0, true>), dim3(nblocks), dim3(QL.block), 0, st, w,
+                       d_nactive, out, rows, A, Q);
+  else if (S.kiters == 5)
+    hipLaunchKernelGGL((particle_queue<NP, 5, false>), dim3(nblocks), dim3(QL.block), 0, st, w,
+                       d_nactive, out, rows, A, Q);
   else
-    hipLaunchKernelGGL((particle_queue<NP, 0>), dim3(nblocks), dim3(QL.block), 0, st, w, d_nactive,
-                       out, rows, A, Q);
+    hipLaunchKernelGGL((particle_queue<NP, 0, false>), dim3(nblocks), dim3(QL.block), 0, st, w,
+                       d_nactive, out, rows, A, Q);
   return hipGetLastError();
 }
 
@@ -567,10 +661,28 @@ TPM_DEV bool hill_violation(const EphW<NP>& W, double ox, double oy, double oz,
 #define TPM_PLANET_KERNEL
 #endif
 
+// Heliocentric velocities of the planets (internal order, [NP][3]) from the
+// Jacobi velocities held by lanes 1..NP: the same linear map as the
+// positions'.  Wave-uniform call.
+template <int NP, bool ROWB>
+TPM_DEV void write_helio_velocities(const EphConst& E, const EphW<NP>& W, bool body, int lane,
+                                    double wx, double wy, double wz, double* __restrict__ out) {
+  double hx[NP + 1], hy[NP + 1], hz[NP + 1];
+  double ox, oy, oz;
+  helio_step<NP, ROWB>(E, W, wx, wy, wz, hx, hy, hz, ox, oy, oz);
+  if (body) {
+    out[3 * (lane - 1) + 0] = ox;
+    out[3 * (lane - 1) + 1] = oy;
+    out[3 * (lane - 1) + 2] = oz;
+  }
+}
+
+// vside (may be null): receives the planets' heliocentric velocities at the
+// chunk's first and last rows, [2][NP][3] (for the sampled diagnostics).
 template <int NP, bool ROWB>
 TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* __restrict__ vj,
                             double* __restrict__ rows, int nsteps, double dt, int64_t step0,
-                            int64_t* __restrict__ flag) {
+                            int64_t* __restrict__ flag, double* __restrict__ vside = nullptr) {
   constexpr int ROW = 3 * NP + 3;
   // This wave is a serial chain that shares its SIMD with particle waves:
   // let it issue first.
@@ -623,6 +735,7 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
   // the first event is the smallest key.
   uint32_t first_ev = UINT32_MAX;
   if (NP > 1 && hill_violation<NP>(W, ox, oy, oz, hx, hy, hz)) first_ev = 1u;
+  if (vside) write_helio_velocities<NP, ROWB>(E, W, L.body, L.lane, wx, wy, wz, vside);
   for (int s = 0; s < nsteps; ++s) {
     wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
     bool bound = drift_converged(L.K, dt, L.body, jx, jy, jz, wx, wy, wz);
@@ -642,6 +755,7 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
       first_ev = __builtin_elementwise_min(first_ev, bad ? k1 + 1u : UINT32_MAX);
     }
   }
+  if (vside) write_helio_velocities<NP, ROWB>(E, W, L.body, L.lane, wx, wy, wz, vside + 3 * NP);
   if (L.body) {
     rj[3 * (L.lane - 1) + 0] = jx; rj[3 * (L.lane - 1) + 1] = jy; rj[3 * (L.lane - 1) + 2] = jz;
     vj[3 * (L.lane - 1) + 0] = wx; vj[3 * (L.lane - 1) + 1] = wy; vj[3 * (L.lane - 1) + 2] = wz;
@@ -661,8 +775,8 @@ template <int NP>
 __global__ void __launch_bounds__(64) TPM_PLANET_KERNEL
 ephemeris_chunk(EphConst E, double* __restrict__ rj, double* __restrict__ vj,
                 double* __restrict__ rows, int nsteps, double dt, int64_t step0,
-                int64_t* __restrict__ flag) {
-  ephemeris_body<NP, false>(E, rj, vj, rows, nsteps, dt, step0, flag);
+                int64_t* __restrict__ flag, double* __restrict__ vside) {
+  ephemeris_body<NP, false>(E, rj, vj, rows, nsteps, dt, step0, flag, vside);
 }
 
 // Many systems at once: workgroup b runs system b (its constants, Jacobi
@@ -706,26 +820,26 @@ hipError_t launch_ephemeris_batch(const EphConst* E, double* rj, double* vj, dou
 
 template <int NP>
 static hipError_t eph_np(const EphConst& E, double* rj, double* vj, double* rows, int nsteps,
-                         double dt, int64_t step0, int64_t* flag, hipStream_t st) {
+                         double dt, int64_t step0, int64_t* flag, double* vside, hipStream_t st) {
   hipLaunchKernelGGL(ephemeris_chunk<NP>, dim3(1), dim3(64), 0, st, E, rj, vj, rows, nsteps, dt,
-                     step0, flag);
+                     step0, flag, vside);
   return hipGetLastError();
 }
 
 hipError_t launch_ephemeris_chunk(const EphConst& E, double* rj, double* vj, double* rows,
                                   int nsteps, double dt, int64_t step0, int64_t* flag,
-                                  hipStream_t st) {
+                                  hipStream_t st, double* vside) {
   if (nsteps < 0 || nsteps > MAX_EPH_STEPS) return hipErrorInvalidValue;
   switch (E.np) {
-    case 0: return eph_np<0>(E, rj, vj, rows, nsteps, dt, step0, flag, st);
-    case 1: return eph_np<1>(E, rj, vj, rows, nsteps, dt, step0, flag, st);
-    case 2: return eph_np<2>(E, rj, vj, rows, nsteps, dt, step0, flag, st);
-    case 3: return eph_np<3>(E, rj, vj, rows, nsteps, dt, step0, flag, st);
-    case 4: return eph_np<4>(E, rj, vj, rows, nsteps, dt, step0, flag, st);
-    case 5: return eph_np<5>(E, rj, vj, rows, nsteps, dt, step0, flag, st);
-    case 6: return eph_np<6>(E, rj, vj, rows, nsteps, dt, step0, flag, st);
-    case 7: return eph_np<7>(E, rj, vj, rows, nsteps, dt, step0, flag, st);
-    case 8: return eph_np<8>(E, rj, vj, rows, nsteps, dt, step0, flag, st);
+    case 0: return eph_np<0>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
+    case 1: return eph_np<1>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
+    case 2: return eph_np<2>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
+    case 3: return eph_np<3>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
+    case 4: return eph_np<4>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
+    case 5: return eph_np<5>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
+    case 6: return eph_np<6>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
+    case 7: return eph_np<7>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
+    case 8: return eph_np<8>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1039,13 +1153,21 @@ hipError_t launch_rsqrt_test(const double* x, double* out, int n, hipStream_t st
   return hipGetLastError();
 }
 
+// mode 0: the fixed-iteration drift; 1: as the particle kernel with the
+// universal fallback; 2: the universal-variable drift alone.
 __global__ void drift_test_kernel(KepConst K, int kiters, double ftol, const double* in,
-                                  double* out, int32_t* ok, int n, double dt) {
+                                  double* out, int32_t* ok, int n, double dt, int mode) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double x = in[6 * i + 0], y = in[6 * i + 1], z = in[6 * i + 2];
   double vx = in[6 * i + 3], vy = in[6 * i + 4], vz = in[6 * i + 5];
-  bool g = drift_fixed(K, dt, kiters, ftol, x, y, z, vx, vy, vz);
+  bool g = false;
+  if (mode != 2) g = drift_fixed(K, dt, kiters, ftol, x, y, z, vx, vy, vz);
+  if (mode != 0 && !g) {
+    x = in[6 * i + 0]; y = in[6 * i + 1]; z = in[6 * i + 2];
+    vx = in[6 * i + 3]; vy = in[6 * i + 4]; vz = in[6 * i + 5];
+    g = drift_universal(K.mu, dt, x, y, z, vx, vy, vz);
+  }
   // a refused drift leaves the state as it was
   out[6 * i + 0] = g ? x : in[6 * i + 0]; out[6 * i + 1] = g ? y : in[6 * i + 1];
   out[6 * i + 2] = g ? z : in[6 * i + 2]; out[6 * i + 3] = g ? vx : in[6 * i + 3];
@@ -1058,7 +1180,7 @@ hipError_t launch_drift_test(const SysConst& S, const double* rv_in, double* rv_
   if (n <= 0) return hipSuccess;
   KepConst K{S.mu0, S.inv_mu0, S.sqrt_mu0, S.inv_sqrt_mu0};
   hipLaunchKernelGGL(drift_test_kernel, dim3((n + 255) / 256), dim3(256), 0, st, K, S.kiters,
-                     S.ftol, rv_in, rv_out, ok, n, dt);
+                     S.ftol, rv_in, rv_out, ok, n, dt, S.universal);
   return hipGetLastError();
 }
 

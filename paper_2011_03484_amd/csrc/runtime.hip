@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -25,6 +26,8 @@
 
 #include "../../include/tpmvs.h"
 #include "ad_internal.h"
+#include "diag_internal.h"
+#include "history_internal.h"
 #include "internal.h"
 
 using namespace tpm;
@@ -192,6 +195,12 @@ struct tpm_sim {
   int64_t ring_rows = 0;                 // rows per slot allocated
   double* d_table = nullptr;             // caller-supplied table (optional)
   int64_t table_rows = 0;
+  // planet history (tpm_set_planet_history): t[nrec], r, v [nrec][np][3]
+  // in integration order, one device block
+  double* d_hist = nullptr;
+  int64_t hist_nrec = 0;
+  double hist_t0 = 0.0, hist_tmin = 0.0, hist_tmax = 0.0;
+  double hist_dt = 0.0;                  // dt of the last integrate (the current time)
   int64_t step = 0;
   int ncu = 0;                           // compute units of the device
   unsigned long long* d_qctr = nullptr;  // work-queue item counter
@@ -217,9 +226,29 @@ struct tpm_sim {
     bool valid = false;
   } ad;
   std::vector<hipEvent_t> kev;           // per-launch timing events (time_kernels)
+  // sampled diagnostics and snapshots (tpm_set_diagnostics)
+  struct Diag {
+    bool on = false;
+    int64_t every = 0;
+    int nres = 0, ref = -1;                // ref: internal planet index
+    int p[2]{}, q[2]{};
+    double* emax = nullptr;
+    int64_t* estep = nullptr;
+    int32_t* flags = nullptr;
+    double* lo = nullptr;
+    double* hi = nullptr;
+    tpm_snapshot_fn snap = nullptr;
+    void* user = nullptr;
+    char* d_snap = nullptr;                // device snapshot staging, SNAP_BYTES(n)
+    char* h_snap[2] = {nullptr, nullptr};  // pinned ring
+    hipEvent_t ev_snap[2] = {nullptr, nullptr};
+    int64_t last_step = -1;                // last sampled global step
+  } diag;
+  double* d_vside = nullptr;             // [NSLOT][2][np][3] planet velocities at chunk ends
 
   ~tpm_sim() {
     release_ad();
+    release_diag();
     release_particles();
     release_planets();
     release_ring();
@@ -231,7 +260,20 @@ struct tpm_sim {
     ad = AD{};
   }
 
+  void release_diag() {
+    if (sP) (void)hipStreamSynchronize(sP);
+    dfree(diag.emax); dfree(diag.estep); dfree(diag.flags); dfree(diag.lo); dfree(diag.hi);
+    dfree(diag.d_snap);
+    for (int k = 0; k < 2; ++k) {
+      if (diag.h_snap[k]) (void)hipHostFree(diag.h_snap[k]);
+      if (diag.ev_snap[k]) (void)hipEventDestroy(diag.ev_snap[k]);
+    }
+    dfree(d_vside);
+    diag = Diag{};
+  }
+
   void release_particles() {
+    release_diag();
     for (auto& w : work) {
       dfree(w.x); dfree(w.y); dfree(w.z); dfree(w.vx); dfree(w.vy); dfree(w.vz);
       dfree(w.slot); dfree(w.status);
@@ -247,9 +289,31 @@ struct tpm_sim {
     particles_set = false;
   }
   void release_planets() {
+    release_diag();
     dfree(d_rj); dfree(d_vj); dfree(d_tmp); dfree(d_table);
     d_rj = d_vj = d_tmp = d_table = nullptr;
     table_rows = 0;
+    release_history();
+  }
+  void release_history() {
+    dfree(d_hist);
+    hist_nrec = 0;
+  }
+  HistDev hist() const {
+    HistDev H{};
+    H.np = np;
+    H.nrec = hist_nrec;
+    H.t = d_hist;
+    H.r = d_hist + hist_nrec;
+    H.v = d_hist + hist_nrec * (1 + 3 * np);
+    for (int j = 0; j < np; ++j) H.mu[j] = mu_s[j];
+    H.t0 = hist_t0;
+    return H;
+  }
+  // Rows [step, step + nsteps] of a run of time step dt inside the history?
+  bool hist_covers(int64_t step, int64_t nsteps, double dt) const {
+    const double a = hist_t0 + (double)step * dt, b = hist_t0 + (double)(step + nsteps) * dt;
+    return std::min(a, b) >= hist_tmin && std::max(a, b) <= hist_tmax;
   }
   void release_ring() { dfree(d_ring); d_ring = nullptr; ring_rows = 0; }
   void release_base() {
@@ -281,6 +345,7 @@ struct tpm_sim {
     S.rmax2 = opt.r_escape > 0 ? opt.r_escape * opt.r_escape : INFINITY;
     S.kiters = opt.kepler_iters;
     S.ftol = opt.kepler_ftol;
+    S.universal = opt.universal_drift ? 1 : 0;
     return S;
   }
 
@@ -347,6 +412,28 @@ int load_particles(tpm_sim* s, int64_t n, const double* r, const double* v, cons
   idx.reserve(n);
   for (int64_t i = 0; i < n; ++i)
     if (!reason || reason[i] == TPM_ACTIVE) idx.push_back((int32_t)i);
+  if (s->opt.sort_by_e && s->central_set) {
+    // Expected Newton count grows with eccentricity: bins of 0.1 in the
+    // osculating e about mu0 (unbound orbits in the last bin), most eccentric
+    // first, caller order within a bin.  The compaction is a stable
+    // partition, so the order lasts.
+    auto ebin = [&](int32_t i) {
+      const double* p = r + 3 * (int64_t)i;
+      const double* q = v + 3 * (int64_t)i;
+      const double rr = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+      const double vv = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+      const double rv = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
+      double ev[3];
+      for (int k = 0; k < 3; ++k) ev[k] = ((vv - s->mu0 / rr) * p[k] - rv * q[k]) / s->mu0;
+      const double e = std::sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
+      const double alpha = 2.0 / rr - vv / s->mu0;
+      if (!(alpha > 0.0) || !(e < 1.0)) return 10;
+      return std::min(9, (int)(e * 10.0));
+    };
+    std::vector<int> bin(n, 0);
+    for (int32_t i : idx) bin[i] = ebin(i);
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return bin[a] > bin[b]; });
+  }
   const int64_t na = (int64_t)idx.size();
   std::vector<double> col(na);
   Work& w = s->work[0];
@@ -405,6 +492,8 @@ void tpm_default_options(tpm_options* o) {
   o->kepler_ftol = 0.0;
   o->device = 0;
   o->time_kernels = 0;
+  o->universal_drift = 0;
+  o->sort_by_e = 0;
 }
 
 const char* tpm_last_error(void) { return g_err.c_str(); }
@@ -582,10 +671,12 @@ int tpm_set_planet_table(tpm_sim* s, const double* table, int64_t nrows) {
   TPM_HIP(hipSetDevice(s->opt.device));
   std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   TPM_HIP(hipStreamSynchronize(s->sP));
+  TPM_HIP(hipStreamSynchronize(s->sE));
   dfree(s->d_table);
   s->d_table = nullptr;
   s->table_rows = 0;
   if (nrows <= 0) return TPM_OK;
+  s->release_history();
   if (!table) return fail(TPM_EINVAL, "table is NULL");
   const int rl = 3 * s->np + 3;
   if (!finite_all(table, nrows * rl)) return fail(TPM_EINVAL, "table not finite");
@@ -597,6 +688,49 @@ int tpm_set_planet_table(tpm_sim* s, const double* table, int64_t nrows) {
   return TPM_OK;
 }
 
+int tpm_set_planet_history(tpm_sim* s, int64_t nrec, const double* t, const double* r,
+                           const double* v, double t0) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  if (!s->planets_set) return fail(TPM_ESTATE, "tpm_set_planets must come first");
+  const int np = s->np;
+  if (nrec > 0) {
+    if (!t || (np > 0 && (!r || !v))) return fail(TPM_EINVAL, "NULL history array");
+    if (nrec > (int64_t(1) << 40) / std::max(1, 6 * np + 1))
+      return fail(TPM_EINVAL, "history too long");
+    if (!finite_all(t, nrec) || !finite_all(r, 3 * np * nrec) || !finite_all(v, 3 * np * nrec) ||
+        !std::isfinite(t0))
+      return fail(TPM_EINVAL, "history not finite");
+    for (int64_t k = 1; k < nrec; ++k)
+      if (!(t[k] > t[k - 1])) return fail(TPM_EINVAL, "history times must increase");
+  }
+  TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
+  TPM_HIP(hipStreamSynchronize(s->sP));
+  TPM_HIP(hipStreamSynchronize(s->sE));
+  s->release_history();
+  if (nrec <= 0) return TPM_OK;
+  dfree(s->d_table);
+  s->table_rows = 0;
+  // records in the integration order of the planets
+  std::vector<double> h((size_t)nrec * (1 + 6 * np));
+  std::memcpy(h.data(), t, sizeof(double) * nrec);
+  double* hr = h.data() + nrec;
+  double* hv = hr + (size_t)nrec * 3 * np;
+  for (int64_t k = 0; k < nrec; ++k)
+    for (int j = 0; j < np; ++j)
+      for (int c = 0; c < 3; ++c) {
+        hr[(k * np + j) * 3 + c] = r[(k * np + s->perm[j]) * 3 + c];
+        hv[(k * np + j) * 3 + c] = v[(k * np + s->perm[j]) * 3 + c];
+      }
+  TPM_HIP(hipMalloc(&s->d_hist, sizeof(double) * h.size()));
+  TPM_HIP(hipMemcpy(s->d_hist, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+  s->hist_nrec = nrec;
+  s->hist_t0 = t0;
+  s->hist_tmin = t[0];
+  s->hist_tmax = t[nrec - 1];
+  return TPM_OK;
+}
+
 int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   if (!s) return fail(TPM_EINVAL, "sim is NULL");
   if (!s->planets_set || !s->particles_set)
@@ -605,6 +739,8 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   if (!std::isfinite(dt) || dt == 0.0) return fail(TPM_EINVAL, "dt must be finite and non-zero");
   if (s->d_table && s->step + nsteps > s->table_rows - 1)
     return fail(TPM_EINVAL, "supplied planet table too short");
+  if (s->d_hist && !s->hist_covers(s->step, nsteps, dt))
+    return fail(TPM_EINVAL, "the run's row times leave the planet history");
   TPM_HIP(hipSetDevice(s->opt.device));
   std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   auto w0 = std::chrono::steady_clock::now();
@@ -614,10 +750,24 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   // The particles wait for the whole first chunk of the planet map before
   // they start, so when the map runs on the fly the first chunk is short;
   // chunk c covers steps [begin(c), begin(c + 1)) of this call.
-  const int K0 = s->d_table ? K : std::min(K, FIRST_CHUNK_STEPS);
-  auto begin = [K, K0](int64_t c) -> int64_t { return c == 0 ? 0 : K0 + (c - 1) * (int64_t)K; };
-  auto length = [&](int64_t c) -> int { return (int)(std::min(begin(c + 1), nsteps) - begin(c)); };
-  const int64_t nchunks = nsteps == 0 ? 0 : nsteps <= K0 ? 1 : 1 + (nsteps - K0 + K - 1) / K;
+  const int K0 = (s->d_table || s->d_hist) ? K : std::min(K, FIRST_CHUNK_STEPS);
+  auto& D = s->diag;
+  if (D.on && D.nres > 0 && s->d_table)
+    return fail(TPM_ESTATE, "resonant angles need planet velocities, which a supplied planet "
+                            "table does not carry");
+  // Chunk c covers steps [cb[c], cb[c + 1]) of this call: the first K0 steps
+  // long, the others K, each also ending at every sample boundary (global
+  // steps that are multiples of the diagnostics interval).
+  std::vector<int64_t> cb{0};
+  while (cb.back() < nsteps) {
+    const int64_t b = cb.back();
+    int64_t e = std::min(nsteps, b + (cb.size() == 1 ? K0 : K));
+    if (D.on) e = std::min(e, ((s->step + b) / D.every + 1) * D.every - s->step);
+    cb.push_back(e);
+  }
+  auto begin = [&](int64_t c) -> int64_t { return cb[c]; };
+  auto length = [&](int64_t c) -> int { return (int)(cb[c + 1] - cb[c]); };
+  const int64_t nchunks = (int64_t)cb.size() - 1;
   if (!s->d_table) {
     int rc = ensure_ring(s, (int64_t)K + 1);
     if (rc) return rc;
@@ -647,8 +797,12 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
       const int slot = (int)(c % NSLOT);
       double* srow = s->d_ring + (size_t)slot * s->ring_rows * rl;
       TPM_HIP(hipStreamWaitEvent(s->sE, s->ev_done[slot], 0));
-      TPM_HIP(launch_ephemeris_chunk(E, s->d_rj, s->d_vj, srow, ks, dt, s->step + begin(c),
-                                     s->d_flag, s->sE));
+      double* vs = s->d_vside ? s->d_vside + (size_t)slot * 6 * s->np : nullptr;
+      if (s->d_hist)
+        TPM_HIP(launch_history_rows(s->hist(), srow, ks + 1, s->step + begin(c), dt, vs, s->sE));
+      else
+        TPM_HIP(launch_ephemeris_chunk(E, s->d_rj, s->d_vj, srow, ks, dt, s->step + begin(c),
+                                       s->d_flag, s->sE, vs));
       TPM_HIP(hipEventRecord(s->ev_eph[slot], s->sE));
     }
     return TPM_OK;
@@ -665,6 +819,64 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
       s->n_active = std::min(s->n_active, (int)s->h_pin[s->cnt_seen % NCNT]);
       s->cnt_seen++;
     }
+    return TPM_OK;
+  };
+  // Snapshots copied to the pinned ring, in order, waiting for their callbacks.
+  std::deque<std::pair<int, int64_t>> pend;     // (ring buffer, step)
+  int64_t snaps = 0;
+  auto fire = [&](bool block, size_t upto) -> int {   // hand out at most `upto`, in order
+    for (; !pend.empty() && upto > 0; --upto) {
+      const int k = pend.front().first;
+      if (block) {
+        TPM_HIP(hipEventSynchronize(D.ev_snap[k]));
+      } else {
+        hipError_t q = hipEventQuery(D.ev_snap[k]);
+        if (q == hipErrorNotReady) break;
+        TPM_HIP(q);
+      }
+      const int64_t n = s->n;
+      const char* h = D.h_snap[k];
+      D.snap(D.user, pend.front().second, n, (const double*)h, (const double*)(h + 24 * n),
+             (const int64_t*)(h + 96 * n), (const int32_t*)(h + 104 * n),
+             (const double*)(h + 48 * n));
+      pend.pop_front();
+    }
+    return TPM_OK;
+  };
+  // Sample (and snapshot) the state at global step `gstep`, whose table row is
+  // `row` and planet velocities (internal order) `vel`.
+  auto sample = [&](int64_t gstep, const double* row, const double* vel, int n_upper) -> int {
+    DiagArgs A{};
+    A.emax = D.emax; A.estep = D.estep; A.flags = D.flags; A.lo = D.lo; A.hi = D.hi;
+    A.nres = D.nres;
+    for (int k = 0; k < 2; ++k) { A.p[k] = D.p[k]; A.q[k] = D.q[k]; }
+    A.ref = D.ref;
+    A.mu0 = s->mu0;
+    A.mu_ref = D.ref >= 0 ? s->mu0 + s->mu_s[D.ref] : s->mu0;
+    A.vref = (vel && D.ref >= 0) ? vel + 3 * D.ref : nullptr;
+    const int64_t n = s->n;
+    if (D.snap) {
+      A.snap_r = (double*)D.d_snap;
+      A.snap_v = (double*)(D.d_snap + 24 * n);
+      A.snap_el = (double*)(D.d_snap + 48 * n);
+      A.snap_step = (int64_t*)(D.d_snap + 96 * n);
+      A.snap_reason = (int32_t*)(D.d_snap + 104 * n);
+      TPM_HIP(launch_snapshot_base(s->out, (int)n, s->mu0, A, s->sP));
+    }
+    TPM_HIP(launch_sample(S, s->work[s->cur], s->d_nactive, n_upper, row, gstep, A, s->sP));
+    if (D.snap) {
+      const int k = (int)(snaps % 2);
+      if (pend.size() == 2) {                  // ring full: hand out the oldest first
+        int rc = fire(true, 1);
+        if (rc) return rc;
+      }
+      TPM_HIP(hipMemcpyAsync(D.h_snap[k], D.d_snap, (size_t)108 * n, hipMemcpyDeviceToHost,
+                             s->sP));
+      TPM_HIP(hipEventRecord(D.ev_snap[k], s->sP));
+      pend.emplace_back(k, gstep);
+      snaps++;
+    }
+    D.last_step = gstep;
     return TPM_OK;
   };
   int n_grid = s->n_active;
@@ -685,6 +897,11 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
       int rc = poll_counts();
       if (rc) return rc;
       n_grid = std::min(n_grid, s->n_active);
+    }
+    const double* vel = s->d_vside ? s->d_vside + (size_t)slot * 6 * s->np : nullptr;
+    if (c == 0 && D.on && step0 % D.every == 0 && step0 != D.last_step) {
+      int rc = sample(step0, rows, vel, n_grid);
+      if (rc) return rc;
     }
     if (n_grid > 0) {
       Work& w = s->work[s->cur];
@@ -713,6 +930,12 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
       if (timed) TPM_HIP(hipEventRecord(s->kev[2 * s->stats.chunks + 1], s->sP));
       s->stats.chunks++;
     }
+    if (D.on && (step0 + ks) % D.every == 0) {
+      int rc = sample(step0 + ks, rows + (size_t)ks * rl, vel ? vel + 3 * s->np : nullptr, n_grid);
+      if (rc) return rc;
+      rc = fire(false, SIZE_MAX);
+      if (rc) return rc;
+    }
     TPM_HIP(hipEventRecord(s->ev_done[slot], s->sP));
     const bool last = (c == nchunks - 1);
     if (n_grid > 0 && (((c + 1) % R == 0) || last)) {
@@ -739,6 +962,8 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   {
     int rc = poll_counts();
     if (rc) return rc;
+    rc = fire(true, SIZE_MAX);
+    if (rc) return rc;
   }
   {
     int32_t qerr = 0;
@@ -746,6 +971,7 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
     if (qerr) return fail(TPM_EDEVICE, "particle work queue: a wait exceeded its limit");
   }
   s->step += nsteps;
+  s->hist_dt = dt;
   float msP = 0.f, msE = 0.f;
   TPM_HIP(hipEventElapsedTime(&msP, s->t0P, s->t1P));
   TPM_HIP(hipEventElapsedTime(&msE, s->t0E, s->t1E));
@@ -794,6 +1020,79 @@ int tpm_get_particles(tpm_sim* s, double* r, double* v, int64_t* deact_step, int
   return TPM_OK;
 }
 
+int tpm_set_diagnostics(tpm_sim* s, const tpm_diag_options* o) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  if (!s->particles_set || !s->planets_set)
+    return fail(TPM_ESTATE, "set planets and particles before the diagnostics");
+  if (o && o->every < 0) return fail(TPM_EINVAL, "every < 0");
+  int ref = -1;
+  if (o && o->every > 0) {
+    if (o->nres < 0 || o->nres > 2) return fail(TPM_EINVAL, "nres must be 0, 1 or 2");
+    for (int k = 0; k < o->nres; ++k)
+      if (o->p[k] <= 0 || o->q[k] <= 0 || o->p[k] > 1000 || o->q[k] > 1000)
+        return fail(TPM_EINVAL, "resonance p:q needs 0 < p, q <= 1000");
+    if (o->nres > 0) {
+      if (o->ref_planet < 0 || o->ref_planet >= s->np)
+        return fail(TPM_EINVAL, "reference planet out of range");
+      for (int j = 0; j < s->np; ++j)
+        if (s->perm[j] == o->ref_planet) ref = j;
+    }
+  }
+  TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
+  s->release_diag();
+  if (!o || o->every == 0) return TPM_OK;
+  auto& D = s->diag;
+  const int64_t n = std::max<int64_t>(s->n, 1);
+  const int nr = std::max(o->nres, 1);
+  TPM_HIP(hipMalloc(&D.emax, n * 8));
+  TPM_HIP(hipMalloc(&D.estep, n * 8));
+  TPM_HIP(hipMalloc(&D.flags, n * nr * 4));
+  TPM_HIP(hipMalloc(&D.lo, n * nr * 8));
+  TPM_HIP(hipMalloc(&D.hi, n * nr * 8));
+  if (o->nres > 0) TPM_HIP(hipMalloc(&s->d_vside, sizeof(double) * NSLOT * 6 * s->np));
+  if (o->snapshot) {
+    TPM_HIP(hipMalloc(&D.d_snap, 108 * n));
+    for (int k = 0; k < 2; ++k) {
+      TPM_HIP(hipHostMalloc(&D.h_snap[k], 108 * n, hipHostMallocDefault));
+      TPM_HIP(hipEventCreateWithFlags(&D.ev_snap[k], hipEventDisableTiming));
+    }
+  }
+  D.every = o->every;
+  D.nres = o->nres;
+  D.ref = ref;
+  for (int k = 0; k < 2; ++k) {
+    D.p[k] = k < o->nres ? o->p[k] : 0;
+    D.q[k] = k < o->nres ? o->q[k] : 0;
+  }
+  D.snap = o->snapshot;
+  D.user = o->user;
+  DiagArgs A{};
+  A.emax = D.emax; A.estep = D.estep; A.flags = D.flags; A.lo = D.lo; A.hi = D.hi;
+  A.nres = D.nres;
+  TPM_HIP(launch_diag_reset((int)s->n, A, s->sP));
+  TPM_HIP(hipStreamSynchronize(s->sP));
+  D.on = true;
+  return TPM_OK;
+}
+
+int tpm_get_diagnostics(tpm_sim* s, double* emax, int64_t* emax_step, int32_t* flags,
+                        double* phi_lo, double* phi_hi) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  if (!s->diag.on) return fail(TPM_ESTATE, "diagnostics are off");
+  TPM_HIP(hipSetDevice(s->opt.device));
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
+  TPM_HIP(hipStreamSynchronize(s->sP));
+  const int64_t n = s->n, m = n * s->diag.nres;
+  if (n == 0) return TPM_OK;
+  if (emax) TPM_HIP(hipMemcpy(emax, s->diag.emax, n * 8, hipMemcpyDeviceToHost));
+  if (emax_step) TPM_HIP(hipMemcpy(emax_step, s->diag.estep, n * 8, hipMemcpyDeviceToHost));
+  if (m && flags) TPM_HIP(hipMemcpy(flags, s->diag.flags, m * 4, hipMemcpyDeviceToHost));
+  if (m && phi_lo) TPM_HIP(hipMemcpy(phi_lo, s->diag.lo, m * 8, hipMemcpyDeviceToHost));
+  if (m && phi_hi) TPM_HIP(hipMemcpy(phi_hi, s->diag.hi, m * 8, hipMemcpyDeviceToHost));
+  return TPM_OK;
+}
+
 int tpm_get_planets(tpm_sim* s, double* r, double* v) {
   if (!s) return fail(TPM_EINVAL, "sim is NULL");
   if (!s->planets_set) return fail(TPM_ESTATE, "no planets");
@@ -802,9 +1101,23 @@ int tpm_get_planets(tpm_sim* s, double* r, double* v) {
   TPM_HIP(hipSetDevice(s->opt.device));
   std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   TPM_HIP(hipStreamSynchronize(s->sE));
-  TPM_HIP(launch_jacobi_to_helio(s->eph(), s->d_rj, s->d_vj, s->d_tmp, s->d_tmp + 3 * np, s->sE));
   std::vector<double> h(6 * np);
-  TPM_HIP(hipMemcpyAsync(h.data(), s->d_tmp, sizeof(double) * 6 * np, hipMemcpyDeviceToHost, s->sE));
+  if (s->d_hist) {
+    // the history's state at the current step (time t0 + step dt of the last
+    // integrate's dt)
+    if (!s->hist_covers(s->step, 0, s->hist_dt))
+      return fail(TPM_EINVAL, "the current step's time lies outside the planet history");
+    double* row = s->d_tmp;                     // 3 np + 3
+    double* vel = s->d_tmp + 3 * np + 3;        // [2][np][3]
+    TPM_HIP(launch_history_rows(s->hist(), row, 1, s->step, s->hist_dt, vel, s->sE));
+    TPM_HIP(hipMemcpyAsync(h.data(), row, sizeof(double) * 3 * np, hipMemcpyDeviceToHost, s->sE));
+    TPM_HIP(hipMemcpyAsync(h.data() + 3 * np, vel, sizeof(double) * 3 * np, hipMemcpyDeviceToHost,
+                           s->sE));
+  } else {
+    TPM_HIP(launch_jacobi_to_helio(s->eph(), s->d_rj, s->d_vj, s->d_tmp, s->d_tmp + 3 * np, s->sE));
+    TPM_HIP(hipMemcpyAsync(h.data(), s->d_tmp, sizeof(double) * 6 * np, hipMemcpyDeviceToHost,
+                           s->sE));
+  }
   TPM_HIP(hipStreamSynchronize(s->sE));
   for (int j = 0; j < np; ++j) {
     int c = s->perm[j];
@@ -968,6 +1281,9 @@ int tpm_get_stats(tpm_sim* s, tpm_stats* o) {
   tpm_stats st = s->stats;
   st.sub_chunks = s->opt.sub_chunks;
   st.waves_per_simd = s->opt.waves_per_simd;
+  st.block_threads = s->opt.block_threads;
+  st.chunk_steps = s->opt.chunk_steps;
+  st.resync_chunks = s->opt.resync_chunks;
   st.step = s->step;
   st.n_particles = s->n;
   st.n_active = 0;
@@ -1001,6 +1317,17 @@ int tpm_planet_table(tpm_sim* s, int64_t nsteps, double dt, double* table) {
   size_t b = sizeof(double) * 3 * std::max(np, 1);
   TPM_HIP(hipStreamSynchronize(s->sE));
   DevScope mem;
+  if (s->d_hist) {
+    if (!s->hist_covers(s->step, nsteps, dt))
+      return fail(TPM_EINVAL, "the rows' times leave the planet history");
+    TPM_HIP(mem.alloc(rows, sizeof(double) * (nsteps + 1) * rl));
+    TPM_HIP(launch_history_rows(s->hist(), rows, (int)(nsteps + 1), s->step, dt, nullptr, s->sE));
+    std::vector<double> t((nsteps + 1) * rl);
+    TPM_HIP(hipStreamSynchronize(s->sE));
+    TPM_HIP(hipMemcpy(t.data(), rows, sizeof(double) * t.size(), hipMemcpyDeviceToHost));
+    permute_table(s, t.data(), table, nsteps + 1, true);
+    return TPM_OK;
+  }
   TPM_HIP(mem.alloc(rj, b));
   TPM_HIP(mem.alloc(vj, b));
   TPM_HIP(mem.alloc(flag, sizeof(int64_t)));
@@ -1062,8 +1389,9 @@ int tpm_debug_rsqrt(int64_t n, const double* x, double* out) {
   return TPM_OK;
 }
 
-int tpm_debug_drift(double mu, int64_t n, const double* rv_in, double* rv_out, int32_t* ok,
-                    double dt, int32_t kepler_iters, double kepler_ftol) {
+namespace {
+int debug_drift(double mu, int64_t n, const double* rv_in, double* rv_out, int32_t* ok,
+                double dt, int32_t kepler_iters, double kepler_ftol, int mode) {
   if (n < 0 || n >= (int64_t(1) << 31) || (n && (!rv_in || !rv_out || !ok)))
     return fail(TPM_EINVAL, "bad arguments");
   if (!(mu > 0.0) || !std::isfinite(dt) || kepler_iters < 0 || kepler_iters > 64)
@@ -1076,6 +1404,7 @@ int tpm_debug_drift(double mu, int64_t n, const double* rv_in, double* rv_out, i
   S.inv_sqrt_mu0 = 1.0 / std::sqrt(mu);
   S.kiters = kepler_iters;
   S.ftol = kepler_ftol > 0 ? kepler_ftol : 1e-13;
+  S.universal = mode;
   double *di, *dout;
   int32_t* dok;
   DevScope mem;
@@ -1088,6 +1417,18 @@ int tpm_debug_drift(double mu, int64_t n, const double* rv_in, double* rv_out, i
   TPM_HIP(hipMemcpy(rv_out, dout, n * 48, hipMemcpyDeviceToHost));
   TPM_HIP(hipMemcpy(ok, dok, n * 4, hipMemcpyDeviceToHost));
   return TPM_OK;
+}
+}  // namespace
+
+int tpm_debug_drift(double mu, int64_t n, const double* rv_in, double* rv_out, int32_t* ok,
+                    double dt, int32_t kepler_iters, double kepler_ftol) {
+  return debug_drift(mu, n, rv_in, rv_out, ok, dt, kepler_iters, kepler_ftol, 0);
+}
+
+int tpm_debug_drift_universal(double mu, int64_t n, const double* rv_in, double* rv_out,
+                              int32_t* ok, double dt, int32_t mode) {
+  if (mode != 1 && mode != 2) return fail(TPM_EINVAL, "mode must be 1 or 2");
+  return debug_drift(mu, n, rv_in, rv_out, ok, dt, 5, 0.0, mode);
 }
 
 }  // extern "C"
@@ -1245,8 +1586,13 @@ int tpm_ad_tangent(tpm_sim* s, const double* d_dR0, const double* d_dV0, double*
 // wavefront each); the particles of all systems form one work queue whose
 // tiles (64 particles of one system) are ordered by planet count, largest
 // first.  The whole chunk loop is captured once into a HIP graph and launched
-// once.  Work-queue shapes come from a small autotuner whose choices are
-// cached per (systems, particles, planet-count histogram, chunk, device).
+// once.  Every R chunks the graph compacts the working set (a stable
+// partition keeps each system's survivors contiguous) and rebuilds the tiles
+// on the device, so removed particles stop occupying lanes.  Workgroup size,
+// chunk length and work-queue shape come from an autotuner that times one
+// chunk of each candidate from the initial state; R from the measured cost of
+// one compaction against a chunk's.  Choices are cached per (device, systems,
+// particles, planet-count histogram, fixed options).
 namespace {
 
 struct BatchBuffers {
@@ -1260,8 +1606,15 @@ struct BatchBuffers {
   int64_t* flag = nullptr;
   double* ring = nullptr;
   Work w{};
+  Work w2{};                  // second working set (compaction target)
   Out out{};
   int32_t* nall = nullptr;
+  int32_t* psys = nullptr;    // [n] system of each particle (by slot)
+  int32_t* sorder = nullptr;  // [nsys] systems in queue order
+  int32_t* sbeg = nullptr;    // [nsys] scratch of the retiling
+  int32_t* send = nullptr;
+  int32_t* ntiles_dev = nullptr;
+  int32_t* cscratch = nullptr;  // compaction scratch
   unsigned long long* ctr = nullptr;
   uint32_t* progress = nullptr;
   int32_t* qerr = nullptr;
@@ -1273,8 +1626,11 @@ struct BatchBuffers {
   ~BatchBuffers() {
     dfree(E); dfree(sys); dfree(tiles); dfree(rj); dfree(vj); dfree(dt); dfree(ring_off);
     dfree(flag); dfree(ring);
-    dfree(w.x); dfree(w.y); dfree(w.z); dfree(w.vx); dfree(w.vy); dfree(w.vz);
-    dfree(w.slot); dfree(w.status);
+    for (Work* p : {&w, &w2}) {
+      dfree(p->x); dfree(p->y); dfree(p->z); dfree(p->vx); dfree(p->vy); dfree(p->vz);
+      dfree(p->slot); dfree(p->status);
+    }
+    dfree(psys); dfree(sorder); dfree(sbeg); dfree(send); dfree(ntiles_dev); dfree(cscratch);
     dfree(out.r); dfree(out.v); dfree(out.step); dfree(out.reason); dfree(out.planet);
     dfree(nall); dfree(ctr); dfree(progress); dfree(qerr); dfree(acc);
     dfree(rj0); dfree(vj0); dfree(st0);
@@ -1282,7 +1638,7 @@ struct BatchBuffers {
 };
 
 struct TuneChoice {
-  int sub_chunks, waves_per_simd;
+  int block, chunk, sub_chunks, waves_per_simd, resync;
 };
 
 std::map<std::string, TuneChoice>& tune_cache() {
@@ -1324,15 +1680,23 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
   tpm_default_options(&o);
   if (opt_in) o = *opt_in;
   if (o.kepler_iters <= 0) o.kepler_iters = 5;
-  if (o.chunk_steps <= 0) o.chunk_steps = 1024;
-  if (o.chunk_steps > (1 << 30)) return fail(TPM_EINVAL, "chunk_steps > 2^30");
-  if (o.block_threads <= 0) o.block_threads = 64;
-  if (o.block_threads % 64 || o.block_threads > 256) return fail(TPM_EINVAL, "bad block_threads");
+  if (o.chunk_steps < 0 || o.chunk_steps > (1 << 30)) return fail(TPM_EINVAL, "chunk_steps out of range");
+  if (o.block_threads < 0 || o.block_threads % 64 || o.block_threads > 256)
+    return fail(TPM_EINVAL, "bad block_threads");
+  if (o.resync_chunks < 0) return fail(TPM_EINVAL, "resync_chunks < 0");
   if (!(o.kepler_ftol > 0.0)) o.kepler_ftol = 1e-13;
-  const bool autotune = o.sub_chunks <= 0 || o.waves_per_simd <= 0;
+  // zero / negative members are the tuner's to choose
+  const bool autotune = o.sub_chunks <= 0 || o.waves_per_simd <= 0 || o.chunk_steps == 0 ||
+                        o.block_threads == 0 || o.resync_chunks == 0;
+  static const int kChunks[] = {512, 1024, 2048};
+  static const int kBlocks[] = {64, 256};
+  const int Kmax = o.chunk_steps > 0 ? o.chunk_steps : 2048;
 
   // a device context via the single-system object (streams, events, device)
   tpm_options so = o;
+  so.chunk_steps = Kmax;
+  so.block_threads = 64;
+  so.resync_chunks = 1;
   tpm_sim* ctx = nullptr;
   {
     int rc = tpm_create(&so, &ctx);
@@ -1341,8 +1705,7 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
   std::unique_ptr<tpm_sim, void (*)(tpm_sim*)> guard(ctx, tpm_destroy);
   std::lock_guard<std::mutex> dev_lock(device_streams(o.device).lock);
   BatchBuffers B;
-  const int K = o.chunk_steps;
-  const int64_t slot_rows = K + 1;
+  const int64_t slot_rows = Kmax + 1;   // ring rows per slot (the longest candidate chunk)
 
   // ---- per-system set-up (host: ordering and constants; device: Jacobi)
   std::vector<EphConst> E(nsys);
@@ -1393,6 +1756,11 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
   std::stable_sort(tiles.begin(), tiles.end(),
                    [&](const TileDesc& x, const TileDesc& y) { return S[x.sys].np > S[y.sys].np; });
   const int ntiles = (int)tiles.size();
+  std::vector<int32_t> sorder(nsys), psys(std::max<int64_t>(n, 1), 0);
+  std::iota(sorder.begin(), sorder.end(), 0);
+  std::stable_sort(sorder.begin(), sorder.end(), [&](int x, int y) { return S[x].np > S[y].np; });
+  for (int s = 0; s < nsys; ++s)
+    for (int64_t i = part_off[s]; i < part_off[s + 1]; ++i) psys[i] = s;
 
   // ---- device buffers
   const size_t nn = (size_t)std::max<int64_t>(n, 1);
@@ -1408,9 +1776,19 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
   TPM_HIP(hipMalloc(&B.ring_off, sizeof(int64_t) * nsys));
   TPM_HIP(hipMalloc(&B.flag, sizeof(int64_t) * nsys));
   TPM_HIP(hipMalloc(&B.ring, sizeof(double) * std::max<int64_t>(ring_total, 1)));
-  for (double** p : {&B.w.x, &B.w.y, &B.w.z, &B.w.vx, &B.w.vy, &B.w.vz}) TPM_HIP(hipMalloc(p, nn * 8));
-  TPM_HIP(hipMalloc(&B.w.slot, nn * 4));
-  TPM_HIP(hipMalloc(&B.w.status, nn * 4));
+  for (Work* W : {&B.w, &B.w2}) {
+    for (double** p : {&W->x, &W->y, &W->z, &W->vx, &W->vy, &W->vz}) TPM_HIP(hipMalloc(p, nn * 8));
+    TPM_HIP(hipMalloc(&W->slot, nn * 4));
+    TPM_HIP(hipMalloc(&W->status, nn * 4));
+  }
+  TPM_HIP(hipMalloc(&B.psys, nn * 4));
+  TPM_HIP(hipMalloc(&B.sorder, sizeof(int32_t) * nsys));
+  TPM_HIP(hipMalloc(&B.sbeg, sizeof(int32_t) * nsys));
+  TPM_HIP(hipMalloc(&B.send, sizeof(int32_t) * nsys));
+  TPM_HIP(hipMalloc(&B.ntiles_dev, sizeof(int32_t)));
+  TPM_HIP(hipMalloc(&B.cscratch, sizeof(int32_t) * compact_scratch_ints((int)nn)));
+  TPM_HIP(hipMemcpy(B.psys, psys.data(), nn * 4, hipMemcpyHostToDevice));
+  TPM_HIP(hipMemcpy(B.sorder, sorder.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice));
   TPM_HIP(hipMalloc(&B.out.r, nn * 24));
   TPM_HIP(hipMalloc(&B.out.v, nn * 24));
   TPM_HIP(hipMalloc(&B.out.step, nn * 8));
@@ -1463,12 +1841,18 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
   }
   const int32_t n32 = (int32_t)n;
   TPM_HIP(hipMemcpy(B.nall, &n32, 4, hipMemcpyHostToDevice));
+  std::vector<int32_t> slot0(std::max<int64_t>(n, 1));
+  std::iota(slot0.begin(), slot0.end(), 0);
   auto reset_run = [&]() -> int {
     // initial particle, planet and queue state (outside any captured graph)
     double* dst[6] = {B.w.x, B.w.y, B.w.z, B.w.vx, B.w.vy, B.w.vz};
     for (int c = 0; c < 6; ++c)
       if (n) TPM_HIP(hipMemcpy(dst[c], B.st0 + (size_t)c * n, n * 8, hipMemcpyDeviceToDevice));
     if (n) TPM_HIP(hipMemset(B.w.status, 0, n * 4));
+    if (n) TPM_HIP(hipMemcpy(B.w.slot, slot0.data(), n * 4, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(B.nall, &n32, 4, hipMemcpyHostToDevice));
+    if (ntiles) TPM_HIP(hipMemcpy(B.tiles, tiles.data(), sizeof(TileDesc) * ntiles, hipMemcpyHostToDevice));
+    TPM_HIP(hipMemcpy(B.ntiles_dev, &ntiles, 4, hipMemcpyHostToDevice));
     TPM_HIP(hipMemcpy(B.rj, B.rj0, sizeof(double) * ps, hipMemcpyDeviceToDevice));
     TPM_HIP(hipMemcpy(B.vj, B.vj0, sizeof(double) * ps, hipMemcpyDeviceToDevice));
     TPM_HIP(hipMemset(B.ctr, 0, sizeof(unsigned long long)));
@@ -1484,14 +1868,21 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
     return TPM_OK;
   };
 
-  // ---- the chunk loop, enqueued on (sE: planet maps, sP: particles)
-  const int64_t nchunks = (nsteps + K - 1) / K;
-  auto enqueue_run = [&](int64_t chunks, int sub, int wps) -> int {
+  // ---- the chunk loop, enqueued on (sE: planet maps, sP: particles).  With
+  // cfg.resync > 0 the working set is compacted after every resync-th chunk
+  // (and the tiles rebuilt on the device); each particle launch then reads
+  // its tile count from the device and starts from a zeroed item counter.
+  // `cur` receives the working set holding the results.
+  auto enqueue_run = [&](int64_t chunks, const TuneChoice& cfg, int& cur) -> int {
+    const int K = cfg.chunk;
     unsigned long long base = 0;
     uint32_t epoch = 0;
-    const int workers = std::max(1, std::min(ntiles, 4 * ctx->ncu * wps));
-    const int wpb = o.block_threads / 64;
+    const int workers = std::max(1, std::min(ntiles, 4 * ctx->ncu * cfg.waves_per_simd));
+    const int wpb = cfg.block / 64;
     const unsigned long long waves = (unsigned long long)((workers + wpb - 1) / wpb) * wpb;
+    const bool compacting = cfg.resync > 0;
+    Work ws[2] = {B.w, B.w2};
+    cur = 0;
     TPM_HIP(hipEventRecord(ctx->ev_cnt[0], ctx->sP));
     TPM_HIP(hipStreamWaitEvent(ctx->sE, ctx->ev_cnt[0], 0));
     for (int64_t c = 0; c < chunks; ++c) {
@@ -1504,59 +1895,117 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
       TPM_HIP(hipStreamWaitEvent(ctx->sP, ctx->ev_eph[slot], 0));
       BatchQueueArgs Q;
       Q.ctr = B.ctr;
-      Q.base = base;
+      Q.base = compacting ? 0 : base;
       Q.progress = B.progress;
       Q.epoch = epoch;
       Q.ntiles = ntiles;
-      Q.nsub = std::max(1, std::min(sub, ks));
+      Q.nsub = std::max(1, std::min(cfg.sub_chunks, ks));
       Q.sub_steps = (ks + Q.nsub - 1) / Q.nsub;
       Q.nsteps = ks;
-      Q.step0 = c * K;
+      Q.step0 = c * (int64_t)K;
       Q.slot = slot;
       Q.slot_rows = slot_rows;
       Q.error = B.qerr;
-      TPM_HIP(launch_particle_batch(B.sys, B.tiles, B.w, B.out, B.ring, Q, workers, o.block_threads,
+      Q.ntiles_dev = compacting ? B.ntiles_dev : nullptr;
+      if (compacting) TPM_HIP(launch_queue_reset(B.ctr, ctx->sP));
+      TPM_HIP(launch_particle_batch(B.sys, B.tiles, ws[cur], B.out, B.ring, Q, workers, cfg.block,
                                     ctx->sP));
       if (ntiles > 0) {
         base += (unsigned long long)ntiles * Q.nsub + waves;
         epoch += (uint32_t)Q.nsub;
       }
       TPM_HIP(hipEventRecord(ctx->ev_done[slot], ctx->sP));
+      if (compacting && (c + 1) % cfg.resync == 0 && c + 1 < chunks) {
+        TPM_HIP(launch_compact(ws[cur], ws[1 - cur], B.nall, (int)n, B.cscratch, ctx->sP));
+        cur = 1 - cur;
+        TPM_HIP(launch_batch_retile(ws[cur], B.nall, (int)n, B.psys, B.sorder, nsys, B.sbeg, B.send,
+                                    B.tiles, B.ntiles_dev, ctx->sP));
+      }
     }
     TPM_HIP(hipEventRecord(ctx->ev_cnt[1], ctx->sE));
     TPM_HIP(hipStreamWaitEvent(ctx->sP, ctx->ev_cnt[1], 0));
     return TPM_OK;
   };
 
-  // ---- autotuner: time one chunk of each candidate from the initial state
-  TuneChoice choice{o.sub_chunks > 0 ? o.sub_chunks : 16, o.waves_per_simd > 0 ? o.waves_per_simd : 2};
-  if (autotune && nchunks > 0 && ntiles > 0) {
+  // ---- autotuner: time one chunk of each (workgroup size, chunk length,
+  // work-queue shape) candidate from the initial state, per step; then one
+  // compaction, whose cost against the chosen chunk's sets the interval R
+  // (compaction under 1% of the particle time)
+  TuneChoice choice{o.block_threads > 0 ? o.block_threads : 64,
+                    o.chunk_steps > 0 ? o.chunk_steps : 1024,
+                    o.sub_chunks > 0 ? o.sub_chunks : 16, o.waves_per_simd > 0 ? o.waves_per_simd : 2,
+                    o.resync_chunks > 0 ? o.resync_chunks : 1};
+  int cur = 0;
+  if (autotune && nsteps > 0 && ntiles > 0) {
     hipDeviceProp_t prop;
     TPM_HIP(hipGetDeviceProperties(&prop, o.device));
     std::string key = std::string(prop.gcnArchName) + "/" + std::to_string(nsys) + "/" +
-                      std::to_string(n) + "/" + std::to_string(K);
+                      std::to_string(n) + "/" + std::to_string(nsteps) + "/" +
+                      std::to_string(o.block_threads) + "/" + std::to_string(o.chunk_steps) + "/" +
+                      std::to_string(o.sub_chunks) + "/" + std::to_string(o.waves_per_simd) + "/" +
+                      std::to_string(o.resync_chunks);
     for (int k = 0; k <= MAX_NP; ++k) key += "," + std::to_string(hist[k]);
     auto it = tune_cache().find(key);
     if (it != tune_cache().end()) {
       choice = it->second;
     } else {
-      const TuneChoice cands[] = {{4, 2}, {8, 2}, {16, 2}, {4, 4}, {16, 4}};
-      float best = 1e30f;
+      const int shapes[][2] = {{4, 2}, {8, 2}, {16, 2}, {4, 4}, {16, 4}};
+      std::vector<TuneChoice> cands;
+      for (int b : kBlocks) {
+        if (o.block_threads > 0 && b != o.block_threads) continue;
+        for (int k : kChunks) {
+          if (o.chunk_steps > 0 && k != o.chunk_steps) continue;
+          if (o.chunk_steps == 0 && k > std::max<int64_t>(512, nsteps)) continue;
+          for (auto& sh : shapes) {
+            if (o.sub_chunks > 0 && sh[0] != o.sub_chunks) continue;
+            if (o.waves_per_simd > 0 && sh[1] != o.waves_per_simd) continue;
+            cands.push_back(TuneChoice{b, k, sh[0], sh[1], 0});
+          }
+        }
+      }
+      if (o.block_threads > 0 && std::find(std::begin(kBlocks), std::end(kBlocks), o.block_threads) == std::end(kBlocks))
+        for (auto& c : cands) c.block = o.block_threads;
+      if (cands.empty()) cands.push_back(TuneChoice{choice.block, choice.chunk, choice.sub_chunks,
+                                                    choice.waves_per_simd, 0});
+      double best = 1e300, best_chunk_ms = 0.0;
       for (const auto& cand : cands) {
         int rc = reset_run();
         if (rc) return rc;
         TPM_HIP(hipEventRecord(ctx->t0P, ctx->sP));
-        rc = enqueue_run(1, cand.sub_chunks, cand.waves_per_simd);
+        rc = enqueue_run(1, cand, cur);
         if (rc) return rc;
         TPM_HIP(hipEventRecord(ctx->t1P, ctx->sP));
         TPM_HIP(hipEventSynchronize(ctx->t1P));
         float ms = 0.f;
         TPM_HIP(hipEventElapsedTime(&ms, ctx->t0P, ctx->t1P));
-        if (ms < best) { best = ms; choice = cand; }
+        const double per_step = ms / (double)std::min<int64_t>(cand.chunk, nsteps);
+        if (per_step < best) {
+          best = per_step;
+          best_chunk_ms = ms;
+          const int keep_r = choice.resync;
+          choice = cand;
+          choice.resync = keep_r;
+        }
+      }
+      if (o.resync_chunks == 0) {
+        int rc = reset_run();
+        if (rc) return rc;
+        TPM_HIP(hipEventRecord(ctx->t0P, ctx->sP));
+        TPM_HIP(launch_compact(B.w, B.w2, B.nall, (int)n, B.cscratch, ctx->sP));
+        TPM_HIP(launch_batch_retile(B.w2, B.nall, (int)n, B.psys, B.sorder, nsys, B.sbeg, B.send,
+                                    B.tiles, B.ntiles_dev, ctx->sP));
+        TPM_HIP(hipEventRecord(ctx->t1P, ctx->sP));
+        TPM_HIP(hipEventSynchronize(ctx->t1P));
+        float cms = 0.f;
+        TPM_HIP(hipEventElapsedTime(&cms, ctx->t0P, ctx->t1P));
+        choice.resync = std::max(1, (int)std::ceil(cms / (0.01 * std::max(best_chunk_ms, 1e-3))));
+        choice.resync = std::min(choice.resync, 64);
       }
       tune_cache()[key] = choice;
     }
   }
+  const int K = choice.chunk;
+  const int64_t nchunks = (nsteps + K - 1) / K;
 
   // ---- capture the whole run into one graph and launch it once
   {
@@ -1567,7 +2016,7 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
   hipGraphExec_t exec = nullptr;
   TPM_HIP(hipStreamBeginCapture(ctx->sP, hipStreamCaptureModeThreadLocal));
   {
-    int rc = enqueue_run(nchunks, choice.sub_chunks, choice.waves_per_simd);
+    int rc = enqueue_run(nchunks, choice, cur);
     if (rc) {
       (void)hipStreamEndCapture(ctx->sP, &graph);
       if (graph) (void)hipGraphDestroy(graph);
@@ -1594,7 +2043,7 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
     if (qerr) return fail(TPM_EDEVICE, "particle work queue: a wait exceeded its limit");
   }
   // ---- results
-  TPM_HIP(launch_finalize(B.w, B.nall, (int)n, B.out, ctx->sP));
+  TPM_HIP(launch_finalize(cur ? B.w2 : B.w, B.nall, (int)n, B.out, ctx->sP));
   TPM_HIP(hipMemsetAsync(B.acc, 0, sizeof(unsigned long long), ctx->sP));
   TPM_HIP(launch_active_steps(B.out.step, (int)n, 0, nsteps, B.acc, ctx->sP));
   TPM_HIP(hipStreamSynchronize(ctx->sP));
@@ -1625,6 +2074,10 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
     st.chunks = nchunks;
     st.sub_chunks = choice.sub_chunks;
     st.waves_per_simd = choice.waves_per_simd;
+    st.block_threads = choice.block;
+    st.chunk_steps = choice.chunk;
+    st.resync_chunks = choice.resync;
+    st.compactions = choice.resync > 0 ? (nchunks - 1) / choice.resync : 0;
     if (n) {
       std::vector<int32_t> rs(n);
       TPM_HIP(hipMemcpy(rs.data(), B.out.reason, n * 4, hipMemcpyDeviceToHost));

@@ -24,6 +24,11 @@ secs. 3-4, synthetic stand-ins for their real planet initial conditions):
   * ``adjoint_16k``    - same planets, 16,384 particles of the single-planet
     distribution; dt = 120 d, 1e5 steps; 3 R_H, r > 100 au.
   * ``batched_512``    - 512 independent systems (see :func:`make_batched`).
+  * ``high_e``         - same planets, particles over the applications' a range
+    (a ~ U[20, 70]) at high eccentricity: 85% e ~ U[0.5, 0.99], 10% near-parabolic
+    e ~ U[0.99, 0.9999], 5% made unbound (velocity scaled to v^2 = 2.4 mu0/r);
+    dt = 120 d; 1 R_H, r > 1000 au.  The case the Kepler-solver paragraph of
+    sec. 2.2 sets aside (e >= 0.8 and unbound orbits).
 """
 from __future__ import annotations
 
@@ -224,9 +229,30 @@ def make_batched(nsys: int = 512, seed: int | None = None, nmin: int = 64, nmax:
     return systems
 
 
+def high_e(n: int = 4096, seed: int | None = None) -> Workload:
+    rng = _rng(5, seed)
+    mu, rp, vp, a = _giant_planets(rng)
+    n_np = n // 10
+    n_hyp = n // 20
+    n_ell = n - n_np - n_hyp
+    r1, v1 = _particles(rng, n_ell, 20.0, 70.0, 0.5, 0.99, 20.0)
+    r2, v2 = _particles(rng, n_np + n_hyp, 20.0, 70.0, 0.99, 0.9999, 20.0)
+    r, v = np.concatenate([r1, r2]), np.concatenate([v1, v2])
+    # the last n_hyp: speed raised to v^2 = 2.4 mu0 / r (unbound)
+    h = slice(n - n_hyp, n)
+    rn = np.linalg.norm(r[h], axis=1)
+    v2n = np.sum(v[h] * v[h], axis=1)
+    v[h] *= np.sqrt(2.4 * MU_SUN / (rn * v2n))[:, None]
+    perm = rng.permutation(n)
+    rcrit = 1.0 * hill_radius(MU_SUN, mu, a)
+    return Workload("high_e", MU_SUN, mu, rp, vp, rcrit, 1000.0, r[perm], v[perm], 120.0 * DAY,
+                    10_000)
+
+
 WORKLOADS = {
     "single_planet": single_planet,
     "giants_100k": giants_100k,
     "resonant_200k": resonant_200k,
     "adjoint_16k": adjoint_16k,
+    "high_e": high_e,
 }

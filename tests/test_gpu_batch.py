@@ -66,12 +66,40 @@ def test_batched_shape_invariance(P):
     base, _ = P.batch_integrate(systems, nsteps=T, sub_chunks=1, waves_per_simd=1)
     for kw in ({"sub_chunks": 8, "waves_per_simd": 4}, {"sub_chunks": 3, "waves_per_simd": 2,
                                                        "chunk_steps": 128},
-               {"block_threads": 256, "sub_chunks": 2, "waves_per_simd": 2}, {}):
+               {"block_threads": 256, "sub_chunks": 2, "waves_per_simd": 2},
+               {"chunk_steps": 64, "resync_chunks": 1}, {"chunk_steps": 100, "resync_chunks": 3,
+                                                         "block_threads": 128},
+               {"chunk_steps": 512}, {}):
         other, st = P.batch_integrate(systems, nsteps=T, **kw)
         for a, b in zip(base, other):
             for k in ("r", "v", "deact_step", "reason", "planet"):
                 assert np.array_equal(a[k], b[k]), (kw, k)
+        print(f"{kw}: block {st['block_threads']} chunk {st['chunk_steps']} sub {st['sub_chunks']} "
+              f"waves {st['waves_per_simd']} resync {st['resync_chunks']} "
+              f"compactions {st['compactions']}", flush=True)
     assert st["sub_chunks"] > 0 and st["waves_per_simd"] > 0
+    assert st["block_threads"] in (64, 256) and st["chunk_steps"] in (512, 1024, 2048)
+    assert st["resync_chunks"] >= 1
+
+
+def test_batched_compaction_with_heavy_removals(P):
+    """Encounter radii ten times larger remove most particles within the first
+    chunks; compacting after every 64-step chunk (the tiles rebuilt on the
+    device inside the graph) gives every system bit for bit its own
+    single-system result."""
+    base = _systems(nsys=9, nmax=500, seed=21)
+    T = 1000
+    systems = [W.Workload(w.name, w.mu0, w.mu.copy(), w.rp.copy(), w.vp.copy(), 10 * w.rcrit,
+                          w.rmax, w.r.copy(), w.v.copy(), w.dt, T) for w in base]
+    res, st = P.batch_integrate(systems, nsteps=T, chunk_steps=64, resync_chunks=1, strict=False)
+    removed = sum(int(np.sum(g["reason"] != 0)) for g in res)
+    n = sum(w.n for w in systems)
+    print(f"{removed} of {n} removed, {st['compactions']} compactions", flush=True)
+    assert removed > n // 3 and st["compactions"] == (T + 63) // 64 - 1
+    for w, g in zip(systems, res):
+        ref = _single(P, w, T)
+        for k in ("r", "v", "deact_step", "reason", "planet"):
+            assert np.array_equal(g[k], ref[k]), (w.name, k)
 
 
 def test_full_batched_workload_sampled(P, orc):

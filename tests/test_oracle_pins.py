@@ -760,6 +760,9 @@ def test_diagnostics_match_segmented_runs(orc):
         dist = np.minimum(np.abs(np.abs(w0) - math.radians(10)), np.abs(np.abs(w180) - math.radians(10)))
         clear = np.all(~sampled | (dist > 1e-9), axis=0)
         assert clear.mean() > 0.99
+        # the oracle's own margin from the 10-degree thresholds
+        mref = np.where(sampled, dist, np.inf).min(axis=0)
+        assert np.max(np.abs(d.margin[:, k] - mref)) < 1e-9
         assert np.array_equal(d.flags[clear, k], (near0 * 1 + near180 * 2)[clear])
         lo = np.where(sampled, w180, np.inf).min(axis=0)
         hi = np.where(sampled, w180, -np.inf).max(axis=0)
