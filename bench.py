@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 # The kernel executes fewer (its Newton loop stops once converged, its kick
 # uses one reciprocal square root per planet); what it executes comes from the
 # counter runs below and is reported as `executed_fp64`.
-ALGORITHMIC_FLOPS_PER_PARTICLE_STEP = {4: 721}
+ALGORITHMIC_FLOPS_PER_PARTICLE_STEP = {4: 718}
 # The paper's own CPU-vs-GPU figure, quoted with the hardware it names (sec. 1
 # and sec. 5): GLISSE on a Tesla K20m ran about 100 times faster than the same
 # integration on a CPU core it does not name.

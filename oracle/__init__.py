@@ -42,62 +42,103 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The same source built with every a*b+c contracted into one fused operation:
+# a different rounding at almost every step of the same arithmetic.  Not an
+# oracle of its own; a probe of how far rounding alone moves a trajectory.
+_LIB_FMA = os.path.join(_HERE, "liboracle_fma.so")
 
 ACTIVE, ENCOUNTER, ESCAPE, KEPLER = 0, 1, 2, 3
 KEPLER_FTOL = 1e-13
 
+_FLAGS = {_LIB: ["-ffp-contract=off", "-fno-fast-math"],
+          _LIB_FMA: ["-ffp-contract=fast", "-mfma", "-fno-fast-math"]}
+
+
+def _compile(lib: str, force: bool):
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", *_FLAGS[lib], "-fopenmp", "-fPIC", "-shared", _SRC,
+               "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, lib)
+
 
 def build(force: bool = True) -> str:
-    """Compile ``liboracle.so`` with g++ (strict IEEE doubles, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-               "-fPIC", "-shared", _SRC, "-o", tmp]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+    """Compile ``liboracle.so`` with g++ (strict IEEE doubles, OpenMP), and the
+    contracted build ``liboracle_fma.so`` (see rounding_probe)."""
+    _compile(_LIB, force)
+    _compile(_LIB_FMA, force)
     return _LIB
 
 
 _lib = None
+_lib_fma = None
 
 
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        lib = C.CDLL(_LIB)
-        d, i, i64 = C.c_double, C.c_int, C.c_int64
-        P = C.c_void_p
-        lib.orc_kepler_solve.argtypes = [d, d, d, C.POINTER(i)]
-        lib.orc_kepler_solve.restype = d
-        lib.orc_kepler_fixedk.argtypes = [d, d, d, i, C.POINTER(d)]
-        lib.orc_kepler_fixedk.restype = d
-        lib.orc_drift.argtypes = [d, P, P, d, i, d, P]
-        lib.orc_drift.restype = i
-        lib.orc_ephemeris.argtypes = [d, i, P, P, P, i64, d, P, P, P, P]
-        lib.orc_ephemeris.restype = i64
-        lib.orc_particles.argtypes = [d, i, P, P, d, P, i64, d, i64, i, d, i64, P, P, P, P, P, i, i]
-        lib.orc_drift_universal.argtypes = [d, P, P, d]
-        lib.orc_drift_universal.restype = i
-        lib.orc_particles.restype = d
-        lib.orc_max_threads.argtypes = [i]
-        lib.orc_max_threads.restype = i
-        lib.orc_tangent.argtypes = [d, i, P, P, d, P, i64, d, i, d, i64, P, P, P, P, P, P, i]
-        lib.orc_tangent.restype = None
-        lib.orc_count_ops.argtypes = [d, i, P, P, d, P, d, i, d, i64, P, P, P]
-        lib.orc_count_ops.restype = i64
-        lib.orc_particles_diag.argtypes = [d, i, P, P, d, P, i64, d, i64, i, d, i64, P, P, P, P, P,
-                                           i, i64, P, i, P, P, P, P, P, P, P, P]
-        lib.orc_particles_diag.restype = d
-        lib.orc_history_table.argtypes = [i, P, i64, P, P, P, d, d, i64, P, P]
-        lib.orc_history_table.restype = i64
-        lib.orc_elements.argtypes = [d, i64, P, P, P]
-        lib.orc_elements.restype = None
-        lib.orc_mean_longitudes.argtypes = [d, i64, P, P, P]
-        lib.orc_mean_longitudes.restype = None
-        _lib = lib
+            _compile(_LIB, True)
+        _lib = _declare(C.CDLL(_LIB))
     return _lib
+
+
+class rounding_probe:
+    """Context manager: inside it, every entry point runs the contracted build
+    of the same source (a different rounding sequence of the same method).  How
+    far a result moves under it measures how strongly that particle's
+    trajectory amplifies per-step rounding, which a one-ulp change of the
+    initial state alone can underestimate (near-parabolic passages)."""
+
+    def __enter__(self):
+        global _lib, _lib_fma
+        if _lib_fma is None:
+            if not os.path.exists(_LIB_FMA) or os.path.getmtime(_LIB_FMA) < os.path.getmtime(_SRC):
+                _compile(_LIB_FMA, True)
+            _lib_fma = _declare(C.CDLL(_LIB_FMA))
+        self._saved = _load()
+        _lib = _lib_fma
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self._saved
+        return False
+
+
+def _declare(lib):
+    """Argument and result types of the library's entry points."""
+    d, i, i64 = C.c_double, C.c_int, C.c_int64
+    P = C.c_void_p
+    lib.orc_kepler_solve.argtypes = [d, d, d, C.POINTER(i)]
+    lib.orc_kepler_solve.restype = d
+    lib.orc_kepler_fixedk.argtypes = [d, d, d, i, C.POINTER(d)]
+    lib.orc_kepler_fixedk.restype = d
+    lib.orc_drift.argtypes = [d, P, P, d, i, d, P]
+    lib.orc_drift.restype = i
+    lib.orc_ephemeris.argtypes = [d, i, P, P, P, i64, d, P, P, P, P]
+    lib.orc_ephemeris.restype = i64
+    lib.orc_particles.argtypes = [d, i, P, P, d, P, i64, d, i64, i, d, i64, P, P, P, P, P, i, i]
+    lib.orc_drift_universal.argtypes = [d, P, P, d]
+    lib.orc_drift_universal.restype = i
+    lib.orc_particles.restype = d
+    lib.orc_max_threads.argtypes = [i]
+    lib.orc_max_threads.restype = i
+    lib.orc_tangent.argtypes = [d, i, P, P, d, P, i64, d, i, d, i64, P, P, P, P, P, P, i]
+    lib.orc_tangent.restype = None
+    lib.orc_count_ops.argtypes = [d, i, P, P, d, P, d, i, d, i64, P, P, P]
+    lib.orc_count_ops.restype = i64
+    lib.orc_particles_diag.argtypes = [d, i, P, P, d, P, i64, d, i64, i, d, i64, P, P, P, P, P,
+                                       i, i64, P, i, P, P, P, P, P, P, P, P]
+    lib.orc_particles_diag.restype = d
+    lib.orc_history_table.argtypes = [i, P, i64, P, P, P, d, d, i64, P, P]
+    lib.orc_history_table.restype = i64
+    lib.orc_elements.argtypes = [d, i64, P, P, P]
+    lib.orc_elements.restype = None
+    lib.orc_mean_longitudes.argtypes = [d, i64, P, P, P]
+    lib.orc_mean_longitudes.restype = None
+    return lib
 
 
 def _ptr(a: np.ndarray):

@@ -156,9 +156,20 @@ enum { ACTIVE = 0, ENCOUNTER = 1, ESCAPE = 2, KEPLER = 3 };
 // Since ec sin x - es (1 - cos x) = e [sin(E0 + x) - sin E0], the root obeys
 // |x - dM| <= 2e, and F' >= 1 - e > 0 makes it unique for e < 1.
 // ---------------------------------------------------------------------------
+// cos x - 1 as -2 sin^2(x/2), the same quantity without the cancellation of
+// subtracting cos x from 1 when x is small (there c - 1 would carry the
+// rounding of cos x, half an ulp of 1, into a value far below 1).  The tally
+// follows the method's plain subtraction.
+template <class T>
+inline T cosm1(const T& x) {
+  T h = tsin(0.5 * x);
+  return -2.0 * h * h;
+}
+inline Counted cosm1(const Counted& x) { return tcos(x) - 1.0; }
+
 template <class T>
 inline T kep_F(const T& x, const T& ec, const T& es, const T& dM) {
-  return x - ec * tsin(x) + es * (1.0 - tcos(x)) - dM;
+  return x - ec * tsin(x) - es * cosm1(x) - dM;
 }
 template <class T>
 inline T kep_dF(const T& x, const T& ec, const T& es) {
@@ -166,13 +177,18 @@ inline T kep_dF(const T& x, const T& ec, const T& es) {
 }
 
 // Fixed-k reference iteration (sec. 2.2: a fixed number of Newton iterations,
-// five by default, from a starting guess).  Starter: the second-order series
-// solution of F = 0 for small dM, clamped to the bracket dM +- 2(|ec| + |es|)
-// (a valid bracket since |ec| + |es| >= e).  Returns x_k.
+// five by default, from a starting guess the paper leaves to judgement).
+// Starter: the series solution of F = 0 for small dM through third order.
+// With p = 1 - ec and t = dM/p, F = p x + (es/2) x^2 + (ec/6) x^3 - dM + O(x^4)
+// vanishes for x = t - (es/(2p)) t^2 + (es^2/(2p^2) - ec/(6p)) t^3 + O(t^4).
+// It is clamped to the bracket dM +- 2(|ec| + |es|) (a valid bracket since
+// |ec| + |es| >= e).  Returns x_k.
 template <class T>
 T kep_fixedk(const T& ec, const T& es, const T& dM, int k) {
   T om = 1.0 - ec;
-  T x = dM / om - es * dM * dM / (2.0 * om * om * om);
+  T t = dM / om;
+  T q = es / om;
+  T x = t - 0.5 * q * t * t + (0.5 * q * q - (1.0 / 6.0) * ec / om) * t * t * t;
   double w = 2.0 * (std::fabs(re(ec)) + std::fabs(re(es)));
   if (re(x) > re(dM) + w) x = dM + w;
   if (re(x) < re(dM) - w) x = dM - w;
@@ -248,10 +264,11 @@ int drift(double mu, T r[3], T v[3], double dt, int kfix, double ftol, KepOut* d
   T x = MethodOnly<T>::value ? xk : kep_solve(ec, es, dM, nullptr);
   T s = tsin(x), c = tcos(x);
   T r1 = a * (1.0 - ec * c + es * s);
-  T f = 1.0 + (a / r0) * (c - 1.0);
+  T cm1 = cosm1(x);
+  T f = 1.0 + (a / r0) * cm1;
   T g = dte + (s - x) / n;
   T fd = -(a * a * n * s) / (r1 * r0);
-  T gd = 1.0 + (a / r1) * (c - 1.0);
+  T gd = 1.0 + (a / r1) * cm1;
   T rn[3], vn[3];
   for (int k = 0; k < 3; ++k) {
     rn[k] = f * r[k] + g * v[k];

@@ -627,7 +627,7 @@ def test_operation_count_per_planet_and_newton_step(orc):
     flops = orc.flops_per_step(base)
     print(f"giants_100k, 4 planets, 5 Newton steps: {base[ok][0].tolist()} -> {flops:.0f} flops",
           flush=True)
-    assert flops == 721.0
+    assert flops == 718.0
 
 
 # ---------------------------------------------------------------- diagnostics
@@ -713,10 +713,13 @@ def test_diagnostics_match_segmented_runs(orc):
     """Brute force: the in-loop samples equal samples taken from separate runs
     of `every` steps each (resumed bit for bit), with the elements of their
     states computed by the numpy textbook relations and the planet's from the
-    planet map's own end states: e_max to 1e-14 and its step (where no two
+    planet map's own end states: e_max to 1e-13 and its step (where no two
     samples tie within 1e-12), the flags (away from the 10-degree
     thresholds) and the range of phi - 180 degrees.  Removed particles stop
-    being sampled at their removal step."""
+    being sampled at their removal step.  (The segments restart the planets
+    from heliocentric states, so their rows differ from the continuous run's
+    by rounding; e_max itself moves by up to 2e-14 under a one-ulp change of
+    the particles' initial positions over these 6,000 steps.)"""
     w = W.resonant_200k(n=400, seed=61)
     every, nseg = 150, 40
     T = every * nseg
@@ -746,7 +749,7 @@ def test_diagnostics_match_segmented_runs(orc):
     assert np.array_equal(alive, d.result.reason == 0)
     assert (~alive).sum() > 0
     emax = es.max(axis=0)
-    assert np.max(np.abs(d.emax - emax)) < 1e-14
+    assert np.max(np.abs(d.emax - emax)) < 1e-13
     srt = np.sort(es, axis=0)
     untied = (srt[-1] - srt[-2]) > 1e-12
     assert np.array_equal(d.emax_step[untied], (np.argmax(es, axis=0) * every)[untied])

@@ -10,10 +10,6 @@ the oracle itself: the same source built a second time with FMA contraction
 difference the GPU's explicit FMAs make) against the strict-IEEE build, on the
 workloads the parity tests use.  No GPU result enters.
 """
-import ctypes as C
-import os
-import subprocess
-
 import numpy as np
 import pytest
 
@@ -32,28 +28,10 @@ def _has_fma():
 
 
 @pytest.fixture(scope="module")
-def contracted(orc, tmp_path_factory):
+def contracted(orc):
     if not _has_fma():
         pytest.skip("host CPU has no FMA instructions")
-    src = os.path.join(os.path.dirname(orc.__file__), "oracle.cpp")
-    lib = str(tmp_path_factory.mktemp("orc_fma") / "liboracle_fma.so")
-    subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=fast", "-mfma", "-fopenmp", "-fPIC",
-                    "-shared", src, "-o", lib], check=True)
-    alt = C.CDLL(lib)
-    plain = orc._load()
-    for f in ("orc_ephemeris", "orc_particles"):
-        getattr(alt, f).argtypes = getattr(plain, f).argtypes
-        getattr(alt, f).restype = getattr(plain, f).restype
-    return alt
-
-
-def _with_lib(orc, lib, fn):
-    saved = orc._lib
-    orc._lib = lib
-    try:
-        return fn()
-    finally:
-        orc._lib = saved
+    return orc.rounding_probe
 
 
 @pytest.mark.parametrize("name,make,T,limit,max_moved", [
@@ -73,14 +51,15 @@ def test_chaos_multiplier(orc, contracted, name, make, T, limit, max_moved):
     from test_gpu_parity import _oracle_reference
     w = make()
     eph = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, T, w.dt)
-    res, near, spread = _oracle_reference(orc, w, T, eph.table)
+    res, near, spread = _oracle_reference(orc, w, T, eph.table, rounding=False)
 
     def run():
         tab = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, T, w.dt).table
         return orc.particles(w.mu0, w.mu, w.rcrit, w.rmax, tab, w.dt, w.r, w.v, T,
                              kepler_iters=w.kepler_iters)
 
-    alt = _with_lib(orc, contracted, run)
+    with contracted():
+        alt = run()
     stable = ~near & np.isfinite(spread)
     moved = stable & ((alt.deact_step != res.deact_step) | (alt.planet != res.planet))
     cmp_ = stable & ~moved
