@@ -23,7 +23,7 @@ namespace tpm {
 
 // Values of one drift that its derivatives need.
 struct DriftVals {
-  double u, r0, rinv, alpha, sa, a, n, ec, es, dMr, q, x, s, c, Fp, r1, f, g, fd, gd;
+  double u, r0, rinv, alpha, sa, a, n, ec, es, dMr, q, x, s, c, m, Fp, r1, f, g, fd, gd;
   bool ok;
 };
 
@@ -53,25 +53,21 @@ TPM_DEV void drift_vals(const KepConst& K, double dt, int kiters, double ftol, d
   D.dMr = fma_(-D.q, TWO_PI_LO, dMr);
   double dte = (D.q == 0.0) ? dt : D.dMr * ninv;
   dM = D.dMr;
-  double om = 1.0 - D.ec;
-  double oinv = rcp_newton(om);
-  double t = dM * oinv;
-  double xk = t * fma_(-0.5 * D.es * t, oinv, 1.0);
-  double w = 2.0 * (__builtin_fabs(D.ec) + __builtin_fabs(D.es));
-  xk = __builtin_fmin(__builtin_fmax(xk, dM - w), dM + w);
-  double s, c;
-  xk = kepler_solve(D.ec, D.es, dM, kiters, xk, s, c);
-  double F = fma_(-D.ec, s, fma_(D.es, 1.0 - c, xk - dM));
-  D.Fp = fma_(-D.ec, c, fma_(D.es, s, 1.0));
-  D.ok = bound && (__builtin_fabs(F) <= ftol);
-  D.x = xk; D.s = s; D.c = c;
-  double cm1 = c - 1.0;
+  const double w = 2.0 * (__builtin_fabs(D.ec) + __builtin_fabs(D.es));
+  const double om = 1.0 - D.ec;
+  double xk = kepler_starter(D.ec, D.es, om, dM, w);
+  double s, m, Fk;
+  xk = kepler_solve(D.ec, D.es, om, dM, kiters, w, xk, s, m, Fk);
+  double F = fma_(-D.ec, s, fma_(-D.es, m, xk - dM));
+  D.Fp = fma_(-D.ec, m, fma_(D.es, s, om));
+  D.ok = bound && (__builtin_fmax(__builtin_fabs(F), __builtin_fabs(Fk)) <= ftol);
+  D.x = xk; D.s = s; D.m = m; D.c = 1.0 + m;
   D.r1 = D.a * D.Fp;
   double r1inv = rcp(D.r1);
-  D.f = fma_(D.a * D.rinv, cm1, 1.0);
+  D.f = fma_(D.a * D.rinv, m, 1.0);
   D.g = fma_(s - xk, ninv, dte);
   D.fd = -(D.a * D.a) * D.n * s * D.rinv * r1inv;
-  D.gd = fma_(D.a * r1inv, cm1, 1.0);
+  D.gd = fma_(D.a * r1inv, m, 1.0);
   nx = fma_(D.f, x, D.g * vx); ny = fma_(D.f, y, D.g * vy); nz = fma_(D.f, z, D.g * vz);
   nvx = fma_(D.fd, x, D.gd * vx); nvy = fma_(D.fd, y, D.gd * vy); nvz = fma_(D.fd, z, D.gd * vz);
 }
@@ -93,10 +89,10 @@ TPM_DEV void drift_jvp(const KepConst& K, double dt, const DriftVals& D, const d
   double des = (du * D.sa + D.u * dsa) * K.inv_sqrt_mu;
   double ddM = dn * dt;
   double ddte = (D.q == 0.0) ? 0.0 : (ddM * D.n - D.dMr * dn) / (D.n * D.n);
-  double dx = (D.s * dec - (1.0 - D.c) * des + ddM) / D.Fp;
+  double dx = (D.s * dec + D.m * des + ddM) / D.Fp;
   double ds = D.c * dx, dc = -D.s * dx;
   double dFp = -(dec * D.c + D.ec * dc) + des * D.s + D.es * ds;
-  double df = (da * D.rinv + D.a * drinv) * (D.c - 1.0) + D.a * D.rinv * dc;
+  double df = (da * D.rinv + D.a * drinv) * D.m + D.a * D.rinv * dc;
   double dg = ddte + (ds - dx) / D.n - (D.s - D.x) * dn / (D.n * D.n);
   double dr1 = da * D.Fp + D.a * dFp;
   // fd = -s Q with Q = a^2 n rinv / r1
@@ -104,7 +100,7 @@ TPM_DEV void drift_jvp(const KepConst& K, double dt, const DriftVals& D, const d
   double dQ = Q * (2.0 * da / D.a + dn / D.n + drinv / D.rinv - dr1 / D.r1);
   double dP = D.s * dQ + Q * ds;
   double dfd = -dP;
-  double dgd = (da / D.r1 - D.a * dr1 / (D.r1 * D.r1)) * (D.c - 1.0) + D.a / D.r1 * dc;
+  double dgd = (da / D.r1 - D.a * dr1 / (D.r1 * D.r1)) * D.m + D.a / D.r1 * dc;
   for (int k = 0; k < 3; ++k) {
     odr[k] = df * r[k] + D.f * dr[k] + dg * v[k] + D.g * dv[k];
     odv[k] = dfd * r[k] + D.fd * dr[k] + dgd * v[k] + D.gd * dv[k];
@@ -129,9 +125,9 @@ TPM_DEV void drift_vjp(const KepConst& K, double dt, const DriftVals& D, const d
   double ba = 0, bc = 0, bs = 0, bx = 0, bn = 0, brinv = 0, br1 = 0, bFp = 0, bec = 0, bes = 0;
   double bdte = 0, bdM = 0, bsa = 0, balpha = 0, bu = 0, br0 = 0, bv2 = 0, br2 = 0;
   // gd = 1 + (a/r1)(c - 1)
-  ba += bgd * (D.c - 1.0) / D.r1;
+  ba += bgd * D.m / D.r1;
   bc += bgd * D.a / D.r1;
-  br1 -= bgd * D.a * (D.c - 1.0) / (D.r1 * D.r1);
+  br1 -= bgd * D.a * D.m / (D.r1 * D.r1);
   // fd = -s Q, Q = a^2 n rinv / r1
   {
     double Q = D.a * D.a * D.n * D.rinv / D.r1;
@@ -151,8 +147,8 @@ TPM_DEV void drift_vjp(const KepConst& K, double dt, const DriftVals& D, const d
   bx -= bg / D.n;
   bn -= bg * (D.s - D.x) / (D.n * D.n);
   // f = 1 + a rinv (c - 1)
-  ba += bf * D.rinv * (D.c - 1.0);
-  brinv += bf * D.a * (D.c - 1.0);
+  ba += bf * D.rinv * D.m;
+  brinv += bf * D.a * D.m;
   bc += bf * D.a * D.rinv;
   // Fp = 1 - ec c + es s
   bec -= bFp * D.c;
@@ -163,7 +159,7 @@ TPM_DEV void drift_vjp(const KepConst& K, double dt, const DriftVals& D, const d
   bx += bs * D.c - bc * D.s;
   // x(ec, es, dM): implicit function of x - ec sin x + es (1 - cos x) = dM
   bec += bx * D.s / D.Fp;
-  bes -= bx * (1.0 - D.c) / D.Fp;
+  bes += bx * D.m / D.Fp;
   bdM += bx / D.Fp;
   // dte = dMr / n when a whole period was removed (else dt itself)
   if (D.q != 0.0) {

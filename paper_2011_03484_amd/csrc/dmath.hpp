@@ -12,10 +12,10 @@
 //   series truncated after e, good to about 2^-46.
 // * sincos reduces the argument by pi/2 with the two-constant Cody-Waite scheme
 //   done in fused multiply-adds (exact first product for the quadrant counts
-//   used here, |q| <= 2^20), then evaluates the Taylor series of sin and cos on
-//   [-pi/4, pi/4] (truncation below 1e-19) in Estrin's form and picks the
-//   quadrant with selects; a wavefront whose arguments are all inside
-//   [-0.78, 0.78] skips the reduction (same values).
+//   used here, |q| <= 2^20), then evaluates the Taylor series of sin and of
+//   cos - 1 on [-pi/4, pi/4] (truncation below 1e-19) in Estrin's form and
+//   picks the quadrant with selects; a wavefront whose arguments are all
+//   inside [-0.78, 0.78] skips the reduction (same values).
 //   The constants are pi/2 split into its nearest double and the nearest double
 //   to the remainder (from 50-digit pi; gen_constants.py reproduces them) and
 //   the reciprocals 1/n! of the Taylor series.
@@ -116,10 +116,14 @@ constexpr double C14 = -1.0 / 87178291200.0;
 constexpr double C16 = 1.0 / 20922789888000.0;
 constexpr double C18 = -1.0 / 6402373705728000.0;
 
-// sin and cos of r for |r| <= pi/4 (plus a little slack).  With z = r^2 the
-// two series in z are evaluated in Estrin's pairing (shared z^2, z^4), which
-// halves the dependent-FMA depth of Horner's rule at the same count.
-TPM_DEV void sincos_poly(double r, double& s, double& c) {
+// sin r and cos r - 1 for |r| <= pi/4 (plus a little slack).  With z = r^2
+// the two series in z are evaluated in Estrin's pairing (shared z^2, z^4),
+// which halves the dependent-FMA depth of Horner's rule at the same count.
+// cos r - 1 = -z/2 + z^2 (C4 + C6 z + ...) is summed as such, never as cos r
+// minus 1: the f and g functions and Kepler's equation need it for small r,
+// where the difference would carry the rounding of cos r (half an ulp of 1)
+// into a value far below 1.
+TPM_DEV void sincos_poly(double r, double& s, double& m) {
   const double z = r * r;
   const double z2 = z * z;
   const double z4 = z2 * z2;
@@ -128,22 +132,18 @@ TPM_DEV void sincos_poly(double r, double& s, double& c) {
   double s45 = fma_(S13, z, S11), s67 = fma_(S17, z, S15);
   double ps = fma_(z4, fma_(z2, s67, s45), fma_(z2, s23, s01));
   s = fma_(r * z, ps, r);
-  // cos r = 1 - z/2 + z^2 (C4 + C6 z + ... + C18 z^7), the rounding of
-  // 1 - z/2 carried along
+  // cos r - 1 = -z/2 + z^2 (C4 + C6 z + ... + C18 z^7)
   double c01 = fma_(C6, z, C4), c23 = fma_(C10, z, C8);
   double c45 = fma_(C14, z, C12), c67 = fma_(C18, z, C16);
   double pc = fma_(z4, fma_(z2, c67, c45), fma_(z2, c23, c01));
-  double hz = 0.5 * z;
-  double w = 1.0 - hz;
-  double tail = (1.0 - w) - hz;
-  c = w + fma_(z2, pc, tail);
+  m = fma_(z2, pc, -0.5 * z);
 }
 
 // sincos_poly by Horner's rule: fewer instructions, longer dependency chains.
 // The planet map's lone wavefront runs it faster (its time is its instruction
 // count); the particle kernels, with many wavefronts per SIMD, prefer Estrin's
 // shorter chains.  The values agree to rounding.
-TPM_DEV void sincos_poly_horner(double r, double& s, double& c) {
+TPM_DEV void sincos_poly_horner(double r, double& s, double& m) {
   const double z = r * r;
   double ps = fma_(S17, z, S15);
   ps = fma_(ps, z, S13);
@@ -160,33 +160,47 @@ TPM_DEV void sincos_poly_horner(double r, double& s, double& c) {
   pc = fma_(pc, z, C8);
   pc = fma_(pc, z, C6);
   pc = fma_(pc, z, C4);
-  const double hz = 0.5 * z;
-  const double w = 1.0 - hz;
-  const double tail = (1.0 - w) - hz;
-  c = w + fma_(z * z, pc, tail);
+  m = fma_(z * z, pc, -0.5 * z);
 }
 
-// sin(x), cos(x) for |x| up to about 2^20.  When every active lane of the
-// wavefront has |x| <= 0.78 (< pi/4, so the quadrant count is 0 and the
-// reduction leaves x unchanged) the reduction is skipped; the values are the
-// same (the full path would only turn a -0 input into +0).  The only branch is
-// that wave-uniform one.
-TPM_DEV void sincos(double x, double& s, double& c) {
+// sin(x), cos(x) and cos(x) - 1 for |x| up to about 2^20.  When every active
+// lane of the wavefront has |x| <= 0.78 (< pi/4, so the quadrant count is 0
+// and the reduction leaves x unchanged) the reduction is skipped; the values
+// are the same (the full path would only turn a -0 input into +0).  The only
+// branch is that wave-uniform one.  cos(x) - 1 comes from the series in the
+// first quadrant; beyond it |cos(x) - 1| >= 1 - cos(pi/4) and the difference
+// loses at most two bits.
+TPM_DEV void sincos3(double x, double& s, double& c, double& m) {
   if (wave_all(__builtin_fabs(x) <= 0.78)) {
-    sincos_poly(x, s, c);
+    sincos_poly(x, s, m);
+    c = 1.0 + m;
     return;
   }
   double q = __builtin_rint(x * TWO_OVER_PI);
   double r = fma_(-q, PIO2_HI, x);
   r = fma_(-q, PIO2_LO, r);
-  double ps, pc;
-  sincos_poly(r, ps, pc);
+  double ps, pm;
+  sincos_poly(r, ps, pm);
+  const double pc = 1.0 + pm;
   int iq = (int)q;
   bool swap = iq & 1;
   double ss = swap ? pc : ps;
   double cc = swap ? ps : pc;
   s = (iq & 2) ? -ss : ss;
   c = ((iq + 1) & 2) ? -cc : cc;
+  m = (iq & 3) == 0 ? pm : c - 1.0;
+}
+
+// sin(x) and cos(x) - 1 (see sincos3).
+TPM_DEV void sincosm1(double x, double& s, double& m) {
+  double c;
+  sincos3(x, s, c, m);
+}
+
+// sin(x) and cos(x) (see sincos3).
+TPM_DEV void sincos(double x, double& s, double& c) {
+  double m;
+  sincos3(x, s, c, m);
 }
 
 }  // namespace tpm

@@ -677,6 +677,44 @@ TPM_DEV void write_helio_velocities(const EphConst& E, const EphW<NP>& W, bool b
   }
 }
 
+// One step of the planet map (sec. 2.2, planet integration: kick, Jacobi
+// drift, kick), from the Jacobi state (j, w) and the interaction acceleration
+// a at it; writes table row `row` (this lane's entry).  key1 = 2t for step
+// t of the launch: the general form (FAST false) keeps the first event as a
+// key ordered in time (see ephemeris_body); the fast form returns instead
+// whether the lane would have taken another path than its own (the general
+// drift's branches), or, with events on, met an event at all.
+template <int NP, bool ROWB, bool FAST>
+TPM_DEV bool eph_step(const EphConst& E, const EphLane& L, const EphW<NP>& W, double h, double dt,
+                      double& jx, double& jy, double& jz, double& wx, double& wy, double& wz,
+                      double& ax, double& ay, double& az, bool writer, double rsign,
+                      double* __restrict__ row, uint32_t key1, bool events, uint32_t& first_ev) {
+  double hx[NP + 1], hy[NP + 1], hz[NP + 1];
+  double ox, oy, oz;
+  wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
+  bool bad;
+  const bool bound = drift_converged_t<FAST>(L.K, dt, L.body, jx, jy, jz, wx, wy, wz, bad);
+  if (FAST) bad = bad | (events & L.body & !bound);
+  else first_ev = __builtin_elementwise_min(first_ev, (L.body && !bound) ? key1 : UINT32_MAX);
+  helio_step<NP, ROWB>(E, W, jx, jy, jz, hx, hy, hz, ox, oy, oz);
+  eph_accel<NP, ROWB>(E, L, W, jx, jy, jz, hx, hy, hz, ox, oy, oz, ax, ay, az);
+  wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
+  if (writer) {
+    row[0] = fma_(rsign, ax, ox);
+    row[1] = fma_(rsign, ay, oy);
+    row[2] = fma_(rsign, az, oz);
+  }
+  if (NP > 1) {
+    const bool close = hill_violation<NP>(W, ox, oy, oz, hx, hy, hz);
+    if (FAST) bad = bad | (events & close);
+    else first_ev = __builtin_elementwise_min(first_ev, close ? key1 + 1u : UINT32_MAX);
+  }
+  return bad;
+}
+
+// Steps of one fast block (see ephemeris_body).
+constexpr int EPH_BLOCK = 64;
+
 // vside (may be null): receives the planets' heliocentric velocities at the
 // chunk's first and last rows, [2][NP][3] (for the sampled diagnostics).
 template <int NP, bool ROWB>
@@ -736,23 +774,41 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
   uint32_t first_ev = UINT32_MAX;
   if (NP > 1 && hill_violation<NP>(W, ox, oy, oz, hx, hy, hz)) first_ev = 1u;
   if (vside) write_helio_velocities<NP, ROWB>(E, W, L.body, L.lane, wx, wy, wz, vside);
-  for (int s = 0; s < nsteps; ++s) {
-    wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
-    bool bound = drift_converged(L.K, dt, L.body, jx, jy, jz, wx, wy, wz);
-    const uint32_t k1 = 2u * (uint32_t)(s + 1);
-    first_ev = __builtin_elementwise_min(first_ev, (L.body && !bound) ? k1 : UINT32_MAX);
-    helio_step<NP, ROWB>(E, W, jx, jy, jz, hx, hy, hz, ox, oy, oz);
-    eph_accel<NP, ROWB>(E, L, W, jx, jy, jz, hx, hy, hz, ox, oy, oz, ax, ay, az);
-    wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
-    if (writer) {
-      double* row = rows + (size_t)(s + 1) * ROW + roff;
-      row[0] = fma_(rsign, ax, ox);
-      row[1] = fma_(rsign, ay, oy);
-      row[2] = fma_(rsign, az, oz);
+  // Blocks of EPH_BLOCK steps.  Giant planets on near-circular orbits take
+  // the general drift's short sin/cos path and leave its Newton loop after
+  // two steps every time, and meet no event; the fast form runs exactly that,
+  // with none of the general form's wave-uniform branches, and only notes on
+  // each lane whether the general form would have done otherwise.  A block in
+  // which any lane did is restored from its start and run again in the
+  // general form, as is the rest of the launch.  Either way the rows and the
+  // state are the general form's bit for bit.  Once the run's first event is
+  // on record (*flag != -1) later events cannot change it and no longer stop
+  // the fast form.  (The many-system map keeps the general form: its
+  // wavefronts share SIMDs with the particles, which hide its branches.)
+  const bool events = *flag == -1;
+  bool fast = !ROWB;
+  for (int s0 = 0; s0 < nsteps; s0 += EPH_BLOCK) {
+    const int nb = nsteps - s0 < EPH_BLOCK ? nsteps - s0 : EPH_BLOCK;
+    if (!ROWB && fast) {
+      const double sjx = jx, sjy = jy, sjz = jz, swx = wx, swy = wy, swz = wz;
+      const double sax = ax, say = ay, saz = az;
+      bool bad = false;
+      for (int t = 0; t < nb; ++t) {
+        const int s = s0 + t;
+        bad = bad | eph_step<NP, ROWB, true>(E, L, W, h, dt, jx, jy, jz, wx, wy, wz, ax, ay, az,
+                                             writer, rsign, rows + (size_t)(s + 1) * ROW + roff,
+                                             2u * (uint32_t)(s + 1), events, first_ev);
+      }
+      if (wave_all(!bad)) continue;
+      jx = sjx; jy = sjy; jz = sjz; wx = swx; wy = swy; wz = swz;
+      ax = sax; ay = say; az = saz;
+      fast = false;
     }
-    if (NP > 1) {
-      bool bad = hill_violation<NP>(W, ox, oy, oz, hx, hy, hz);
-      first_ev = __builtin_elementwise_min(first_ev, bad ? k1 + 1u : UINT32_MAX);
+    for (int t = 0; t < nb; ++t) {
+      const int s = s0 + t;
+      eph_step<NP, ROWB, false>(E, L, W, h, dt, jx, jy, jz, wx, wy, wz, ax, ay, az, writer, rsign,
+                                rows + (size_t)(s + 1) * ROW + roff, 2u * (uint32_t)(s + 1), events,
+                                first_ev);
     }
   }
   if (vside) write_helio_velocities<NP, ROWB>(E, W, L.body, L.lane, wx, wy, wz, vside + 3 * NP);

@@ -54,8 +54,9 @@ TPM_DEV int accel(const RowT& row, const PlanetConst<NP>& P,
     double dz = z - row[3 * j + 2];
     double d2 = fma_(dx, dx, fma_(dy, dy, dz * dz));
     d2s[j] = d2;
-    // the kick is a perturbation (|a| << mu0/r^2): 2^-45 relative is ample
-    double k = mul_rsqrt3_1(P.mu[j], d2);
+    // to rounding (the first-order form, good to 2^-45, is always a little
+    // low: a bias of the same sign in every kick)
+    double k = mul_rsqrt3(P.mu[j], d2);
     ax = fma_(-k, dx, ax);
     ay = fma_(-k, dy, ay);
     az = fma_(-k, dz, az);

@@ -102,14 +102,17 @@ def test_dot_product_identity(env):
     rhs = ((dr * r0.grad).sum(1) + (dv * v0.grad).sum(1)).cpu().numpy()
     # <J d, g> = <d, J^T g> per particle.  Rounding in either side is bounded
     # relative to |J d||g| and |d||J^T g| (Cauchy-Schwarz), not to the dot
-    # products themselves, which may cancel.
+    # products themselves, which may cancel.  Each of the T steps of a sweep
+    # rounds about 300 FP64 operations once each, relative to those norms, and
+    # the errors add up at most linearly: 300 T u, u = 2^-53 (5e-11 at
+    # T = 1,500).
     nrm = lambda a, b: torch.sqrt((a * a).sum(1) + (b * b).sum(1)).cpu().numpy()
     scale = nrm(tr, tv) * nrm(gr, gv) + nrm(dr, dv) * nrm(r0.grad, v0.grad) + 1e-300
     rel = np.abs(lhs - rhs) / scale
     rel_dot = np.abs(lhs - rhs) / (np.abs(lhs) + np.abs(rhs) + 1e-300)
     print(f"dot-product identity: max rel (norm-scaled) {rel.max():.2e}, "
           f"(dot-scaled) {rel_dot.max():.2e}", flush=True)
-    assert rel.max() < 1e-11
+    assert rel.max() < 300 * w.nsteps * (np.finfo(float).eps / 2)
 
 
 def test_gradcheck_small(env):
