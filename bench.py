@@ -50,7 +50,7 @@ PMC_PASSES = {
     "p4": "WRITE_SIZE",
 }
 PMC_BENCH_ARGS = ("--nsteps 20000 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched "
-                  "--copy-calibration-mb 256")
+                  "--no-resonant --copy-calibration-mb 256")
 
 
 def kernel_source_hash() -> str:
@@ -303,9 +303,25 @@ def cpu_baseline(w, steps_sample: int, n_single: int):
 
 def adjoint_ratio(P, W, torch, nsteps: int, n: int, ckpt: int):
     """Forward (with checkpoints) and backward of loss = sum |r_T|^2 on the
-    16,384-particle four-planet workload; returns times and their ratio."""
+    16,384-particle four-planet workload; returns times and their ratio, also
+    against the production forward (tpm_integrate, no checkpoints) of the same
+    run."""
     from paper_2011_03484_amd import autograd as AG
     w = W.adjoint_16k(n=n)
+    # the production forward: the same particles and steps through tpm_integrate
+    p = P.Simulation(r_escape=w.rmax, kepler_iters=w.kepler_iters)
+    p.set_central(w.mu0)
+    p.set_planets(w.mu, w.rp, w.vp, w.rcrit)
+    p.set_particles(w.r, w.v)
+    p.integrate(2 * ckpt, w.dt)
+    p.set_planets(w.mu, w.rp, w.vp, w.rcrit)
+    p.set_particles(w.r, w.v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.integrate(nsteps, w.dt)
+    torch.cuda.synchronize()
+    prod_s = time.perf_counter() - t0
+    p.close()
     s = P.Simulation(r_escape=w.rmax, kepler_iters=w.kepler_iters)
     s.set_central(w.mu0)
     s.set_planets(w.mu, w.rp, w.vp, w.rcrit)
@@ -329,6 +345,8 @@ def adjoint_ratio(P, W, torch, nsteps: int, n: int, ckpt: int):
     return {"workload": f"adjoint_16k: {n} particles, 4 planets, {nsteps} steps, checkpoint every "
                         f"{ckpt}, loss = sum |r_T|^2",
             "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
+            "production_forward_s": prod_s,
+            "backward_over_production_forward": (t2 - t1) / prod_s,
             "survivors": survivors}
 
 
@@ -346,7 +364,35 @@ def batched_run(P, W, nsteps: int):
             "call_s_incl_setup_and_tuning": t1 - t0,
             "active_particle_steps": st["active_particle_steps"],
             "systems_with_planet_close_approach": int((st["planet_flag"] != -1).sum()),
-            "queue_shape": {"sub_chunks": st["sub_chunks"], "waves_per_simd": st["waves_per_simd"]}}
+            "tuned": {"block_threads": st["block_threads"], "chunk_steps": st["chunk_steps"],
+                      "sub_chunks": st["sub_chunks"], "waves_per_simd": st["waves_per_simd"],
+                      "resync_chunks": st["resync_chunks"]}}
+
+
+def resonant_run(P, W, torch, nsteps: int):
+    """The 200,000-particle resonant workload (a 54-64 au, e 0.1-0.5, i up to
+    20 degrees; removal within one Hill radius or beyond 1000 au) for nsteps
+    steps: a decaying population with compaction, end to end."""
+    w = W.resonant_200k()
+    s = P.Simulation(r_escape=w.rmax, kepler_iters=w.kepler_iters, time_kernels=True)
+    s.set_central(w.mu0)
+    s.set_planets(w.mu, w.rp, w.vp, w.rcrit)
+    s.set_particles(w.r, w.v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.integrate(nsteps, w.dt)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    st = s.stats()
+    s.close()
+    return {"workload": f"resonant_200k: 200,000 particles, 4 planets, dt = 120 d, {nsteps} steps "
+                        f"(the first {nsteps / 1e7:.0%} of its 1e7-step length)",
+            "value": st["active_particle_steps"] / secs, "unit": "particle-steps/s",
+            "run_ms": secs * 1e3,
+            "particle_steps_per_s_kernels_only": st["active_particle_steps"] / (st["particle_kernel_ms"] / 1e3),
+            "active_particle_steps": st["active_particle_steps"],
+            "removed_by_reason": st["count_by_reason"][1:], "survivors": st["count_by_reason"][0],
+            "compactions": st["compactions"]}
 
 
 def main():
@@ -370,6 +416,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=100_000)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=100_000)
+    ap.add_argument("--no-resonant", action="store_true")
+    ap.add_argument("--resonant-steps", type=int, default=1_000_000)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device with a plain copy "
                          "kernel (the reference for scaling HBM byte counters)")
@@ -500,6 +548,9 @@ def main():
     if not args.no_batched:
         line["batched"] = batched_run(P, W, args.batched_steps)
         print("batched done", file=sys.stderr, flush=True)
+    if not args.no_resonant:
+        line["resonant"] = resonant_run(P, W, torch, args.resonant_steps)
+        print("resonant done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.cpu_single)
     print(json.dumps(line))
