@@ -242,6 +242,13 @@ soa_to_aos(const double* __restrict__ o, double* __restrict__ r, double* __restr
 
 static int grid_of(int64_t n) { return (int)((n + 255) / 256); }
 
+// The derivative kernels run one particle per lane for a whole segment, and
+// the derivative workloads are small (16,384 particles: 256 wavefronts for
+// 1,024 SIMDs): one wavefront per workgroup spreads them over every compute
+// unit instead of packing four onto each of 64.
+constexpr int AD_BLOCK = 64;
+static int ad_grid(int64_t n) { return (int)((n + AD_BLOCK - 1) / AD_BLOCK); }
+
 hipError_t launch_aos_to_soa(const double* r, const double* v, double* o, int64_t n,
                              hipStream_t st) {
   if (n <= 0) return hipSuccess;
@@ -275,7 +282,7 @@ hipError_t launch_ad_segment(const SysConst& S, double dt, int64_t n, int s0, in
                              hipStream_t st) {
   if (n <= 0) return hipSuccess;
 #define TPM_SEG(N)                                                                          \
-  hipLaunchKernelGGL(ad_segment<N>, dim3(grid_of(n)), dim3(256), 0, st,                     \
+  hipLaunchKernelGGL(ad_segment<N>, dim3(ad_grid(n)), dim3(AD_BLOCK), 0, st,                     \
                      make_args<N>(S, dt, n, s0, s1), table, in, out, tape, dstep, reason,   \
                      planet, mode)
   TPM_NP_SWITCH(S.np, TPM_SEG)
@@ -288,7 +295,7 @@ hipError_t launch_ad_reverse(const SysConst& S, double dt, int64_t n, int s0, in
                              const int64_t* dstep, hipStream_t st) {
   if (n <= 0) return hipSuccess;
 #define TPM_REV(N)                                                                     \
-  hipLaunchKernelGGL(ad_reverse<N>, dim3(grid_of(n)), dim3(256), 0, st,                \
+  hipLaunchKernelGGL(ad_reverse<N>, dim3(ad_grid(n)), dim3(AD_BLOCK), 0, st,                \
                      make_args<N>(S, dt, n, s0, s1), table, tape, lam, dstep)
   TPM_NP_SWITCH(S.np, TPM_REV)
 #undef TPM_REV
@@ -300,7 +307,7 @@ hipError_t launch_ad_tangent(const SysConst& S, double dt, int64_t n, int s0, in
                              bool first, hipStream_t st) {
   if (n <= 0) return hipSuccess;
 #define TPM_TAN(N)                                                                     \
-  hipLaunchKernelGGL(ad_tangent<N>, dim3(grid_of(n)), dim3(256), 0, st,                \
+  hipLaunchKernelGGL(ad_tangent<N>, dim3(ad_grid(n)), dim3(AD_BLOCK), 0, st,                \
                      make_args<N>(S, dt, n, s0, s1), table, st_, tg, reason, first ? 1 : 0)
   TPM_NP_SWITCH(S.np, TPM_TAN)
 #undef TPM_TAN

@@ -216,7 +216,7 @@ struct tpm_sim {
     double dt = 0.0;
     double* table = nullptr;      // [nsteps+1][3np+3]
     double* ckpts = nullptr;      // [nseg+1][6][n]
-    double* tape = nullptr;       // [ckpt][6][n]
+    double* tape = nullptr;       // [2][ckpt][6][n]: two segments' tapes (see tpm_ad_backward)
     double* work = nullptr;       // [2][6][n]
     int64_t* dstep = nullptr;
     int32_t* reason = nullptr;
@@ -224,6 +224,8 @@ struct tpm_sim {
     int32_t* treason = nullptr;   // tangent's own removal flags
     size_t cap_table = 0, cap_ckpts = 0, cap_tape = 0, cap_n = 0;
     bool valid = false;
+    // ordering events between the caller's stream and the library's streams
+    hipEvent_t ev_tab[2]{}, ev_rec[2]{}, ev_rev[2]{}, ev_in = nullptr;
   } ad;
   std::vector<hipEvent_t> kev;           // per-launch timing events (time_kernels)
   // sampled diagnostics and snapshots (tpm_set_diagnostics)
@@ -257,6 +259,12 @@ struct tpm_sim {
   void release_ad() {
     dfree(ad.table); dfree(ad.ckpts); dfree(ad.tape); dfree(ad.work);
     dfree(ad.dstep); dfree(ad.reason); dfree(ad.planet); dfree(ad.treason);
+    for (int k = 0; k < 2; ++k) {
+      if (ad.ev_tab[k]) (void)hipEventDestroy(ad.ev_tab[k]);
+      if (ad.ev_rec[k]) (void)hipEventDestroy(ad.ev_rec[k]);
+      if (ad.ev_rev[k]) (void)hipEventDestroy(ad.ev_rev[k]);
+    }
+    if (ad.ev_in) (void)hipEventDestroy(ad.ev_in);
     ad = AD{};
   }
 
@@ -1487,31 +1495,49 @@ int tpm_ad_forward(tpm_sim* s, int64_t n, const double* d_r0, const double* d_v0
   A.ckpt = ckpt_every;
   A.nseg = nseg;
   A.dt = dt;
-  // planet table of the whole run from the current planet state (not advanced)
-  {
-    const size_t b = sizeof(double) * 3 * std::max(s->np, 1);
-    double* rj = s->d_tmp + 6 * std::max(s->np, 1);
-    double* vj = rj + 3 * std::max(s->np, 1);
-    TPM_HIP(hipStreamSynchronize(s->sE));
-    TPM_HIP(hipMemcpyAsync(rj, s->d_rj, b, hipMemcpyDeviceToDevice, st));
-    TPM_HIP(hipMemcpyAsync(vj, s->d_vj, b, hipMemcpyDeviceToDevice, st));
-    const EphConst E = s->eph();
-    const int K = s->opt.chunk_steps;
-    for (int64_t c = 0; c == 0 || c * K < nsteps; ++c) {
-      const int ks = (int)std::min<int64_t>(K, nsteps - c * K);
-      TPM_HIP(launch_ephemeris_chunk(E, rj, vj, A.table + (size_t)c * K * rl, ks, dt, c * K,
-                                     s->d_flag, st));
-      if (nsteps == 0) break;
+  if (!A.ev_in) {
+    for (int k = 0; k < 2; ++k) {
+      TPM_HIP(hipEventCreateWithFlags(&A.ev_tab[k], hipEventDisableTiming));
+      TPM_HIP(hipEventCreateWithFlags(&A.ev_rec[k], hipEventDisableTiming));
+      TPM_HIP(hipEventCreateWithFlags(&A.ev_rev[k], hipEventDisableTiming));
     }
+    TPM_HIP(hipEventCreateWithFlags(&A.ev_in, hipEventDisableTiming));
   }
+  // The planet table of the whole run, from the current planet state (not
+  // advanced), is computed on the library's planet-map stream in pieces of
+  // whole segments (at least 1,024 steps), after whatever that stream already
+  // holds (an earlier integrate); the caller's stream runs each segment once
+  // the piece holding its last row is written, so the planet map and the
+  // particle segments overlap.  A later tpm_integrate is ordered after these
+  // pieces by the same stream.
   const SysConst S = s->sys();
+  const EphConst E = s->eph();
+  const size_t pb = sizeof(double) * 3 * std::max(s->np, 1);
+  double* rj = s->d_tmp + 6 * std::max(s->np, 1);
+  double* vj = rj + 3 * std::max(s->np, 1);
+  TPM_HIP(hipMemcpyAsync(rj, s->d_rj, pb, hipMemcpyDeviceToDevice, s->sE));
+  TPM_HIP(hipMemcpyAsync(vj, s->d_vj, pb, hipMemcpyDeviceToDevice, s->sE));
   TPM_HIP(launch_aos_to_soa(d_r0, d_v0, A.ckpts, n, st));
-  for (int k = 0; k < nseg; ++k) {
-    const int s0 = k * ckpt_every;
-    const int s1 = (int)std::min<int64_t>(nsteps, (int64_t)s0 + ckpt_every);
-    TPM_HIP(launch_ad_segment(S, dt, n, s0, s1, A.table, A.ckpts + (size_t)k * 6 * n,
-                              A.ckpts + (size_t)(k + 1) * 6 * n, nullptr, A.dstep, A.reason,
-                              A.planet, k == 0 ? 0 : 1, st));
+  const int64_t piece = (int64_t)ckpt_every * std::max<int64_t>(1, (1024 + ckpt_every - 1) / ckpt_every);
+  int k = 0;   // next segment
+  for (int64_t p0 = 0, j = 0;; p0 += piece, ++j) {
+    const int64_t p1 = std::min<int64_t>(nsteps, p0 + piece);
+    for (int64_t q0 = p0;;) {   // launches of at most 2^20 steps
+      const int64_t q1 = std::min<int64_t>(p1, q0 + (int64_t(1) << 20));
+      TPM_HIP(launch_ephemeris_chunk(E, rj, vj, A.table + (size_t)q0 * rl, (int)(q1 - q0), dt, q0,
+                                     s->d_flag, s->sE));
+      if ((q0 = q1) >= p1) break;
+    }
+    TPM_HIP(hipEventRecord(A.ev_tab[j % 2], s->sE));
+    TPM_HIP(hipStreamWaitEvent(st, A.ev_tab[j % 2], 0));
+    for (; k < nseg && std::min<int64_t>(nsteps, (int64_t)(k + 1) * ckpt_every) <= p1; ++k) {
+      const int s0 = k * ckpt_every;
+      const int s1 = (int)std::min<int64_t>(nsteps, (int64_t)s0 + ckpt_every);
+      TPM_HIP(launch_ad_segment(S, dt, n, s0, s1, A.table, A.ckpts + (size_t)k * 6 * n,
+                                A.ckpts + (size_t)(k + 1) * 6 * n, nullptr, A.dstep, A.reason,
+                                A.planet, k == 0 ? 0 : 1, st));
+    }
+    if (p1 >= nsteps) break;
   }
   if (nseg == 0) {
     // no step: only the checks at step 0
@@ -1535,21 +1561,51 @@ int tpm_ad_backward(tpm_sim* s, const double* d_gRT, const double* d_gVT, double
   TPM_HIP(hipSetDevice(s->opt.device));
   hipStream_t st = (hipStream_t)stream;
   {
-    int rc = grow(A.tape, A.cap_tape, (size_t)A.ckpt * 6 * n);
+    int rc = grow(A.tape, A.cap_tape, (size_t)2 * A.ckpt * 6 * n);
     if (rc) return rc;
   }
+  std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   const SysConst S = s->sys();
   double* lam = A.work;
+  double* tape[2] = {A.tape, A.tape + (size_t)A.ckpt * 6 * n};
+  // Segment k's states are recomputed from its checkpoint into tape k % 2 on
+  // the library's particle stream while the caller's stream sweeps segment
+  // k + 1 backwards through the other tape: the recomputation does not depend
+  // on the adjoint, so the two overlap (each fills only part of the device at
+  // these particle counts).  A recomputation waits until the sweep that last
+  // read its tape is done; a sweep waits for its tape.
+  const hipStream_t sR = s->sP;
+  TPM_HIP(hipEventRecord(A.ev_in, st));
+  TPM_HIP(hipStreamWaitEvent(sR, A.ev_in, 0));
+  auto recompute = [&](int k) -> int {
+    const int s0 = k * A.ckpt;
+    const int s1 = (int)std::min<int64_t>(A.nsteps, (int64_t)s0 + A.ckpt);
+    TPM_HIP(launch_ad_segment(S, A.dt, n, s0, s1, A.table, A.ckpts + (size_t)k * 6 * n, nullptr,
+                              tape[k % 2], A.dstep, nullptr, nullptr, 2, sR));
+    TPM_HIP(hipEventRecord(A.ev_rec[k % 2], sR));
+    return TPM_OK;
+  };
   TPM_HIP(launch_aos_to_soa(d_gRT, d_gVT, lam, n, st));
+  for (int k = A.nseg - 1; k >= 0 && k >= A.nseg - 2; --k) {
+    int rc = recompute(k);
+    if (rc) return rc;
+  }
   for (int k = A.nseg - 1; k >= 0; --k) {
     const int s0 = k * A.ckpt;
     const int s1 = (int)std::min<int64_t>(A.nsteps, (int64_t)s0 + A.ckpt);
-    // recompute the segment from its checkpoint, recording the state at the
-    // start of every step
-    TPM_HIP(launch_ad_segment(S, A.dt, n, s0, s1, A.table, A.ckpts + (size_t)k * 6 * n, nullptr,
-                              A.tape, A.dstep, nullptr, nullptr, 2, st));
-    TPM_HIP(launch_ad_reverse(S, A.dt, n, s0, s1, A.table, A.tape, lam, A.dstep, st));
+    TPM_HIP(hipStreamWaitEvent(st, A.ev_rec[k % 2], 0));
+    TPM_HIP(launch_ad_reverse(S, A.dt, n, s0, s1, A.table, tape[k % 2], lam, A.dstep, st));
+    if (k >= 2) {
+      TPM_HIP(hipEventRecord(A.ev_rev[k % 2], st));
+      TPM_HIP(hipStreamWaitEvent(sR, A.ev_rev[k % 2], 0));
+      int rc = recompute(k - 2);
+      if (rc) return rc;
+    }
   }
+  // the library's stream is done with this call's tapes before anything else
+  // runs on it
+  TPM_HIP(hipEventRecord(A.ev_in, st));
+  TPM_HIP(hipStreamWaitEvent(sR, A.ev_in, 0));
   TPM_HIP(launch_soa_to_aos(lam, d_gR0, d_gV0, n, st));
   return TPM_OK;
 }
