@@ -258,6 +258,152 @@ def summarize_ephemeris(pmc_dir: str, tot, cnt, steps: int, src: str) -> None:
     print("\n".join(out[-4:]))
 
 
+# rocprofv3 kernel-trace runs summarized by --summarize-traces DIR: subdirectory
+# of DIR -> (summary under profiles/, title, bench.py arguments of the run)
+TRACE_RUNS = {
+    "tl": ("pipeline_giants_100k_1e6_timeline.md",
+           "Pipeline timeline -- giants_100k, 100,000 particles x 1,000,000 steps (one benchmark run)",
+           "--steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched --no-resonant"),
+    "k100k": ("particle_queue_giants_100k_kernel_trace.md",
+              "particle_queue / ephemeris_chunk -- giants_100k, 100,000 particles x 100,000 steps",
+              "--nsteps 100000 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched --no-resonant"),
+    "ad": ("ad_kernels_adjoint_16k_kernel_trace.md",
+           "ad_segment / ad_reverse -- adjoint_16k, 16,384 particles x 100,000 steps, checkpoint 1,000",
+           "--nsteps 1000 --n 1024 --steps 1 --warmup 0 --no-cpu --no-batched --no-resonant"),
+    "batched": ("particle_batch_queue_batched_512_kernel_trace.md",
+                "particle_batch_queue / ephemeris_batch -- 512 systems, 811,726 particles x 100,000 "
+                "steps (one graph launch)",
+                "--nsteps 1000 --n 1024 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-resonant"),
+    "res": ("particle_queue_resonant_200k_kernel_trace.md",
+            "particle_queue / ephemeris_chunk -- resonant_200k, 200,000 particles x 1,000,000 steps",
+            "--nsteps 1000 --n 1024 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched"),
+}
+
+
+def _trace_rows(path: str):
+    import csv
+    rows = []
+    for r in csv.DictReader(open(path)):
+        rows.append((r["Kernel_Name"], int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    rows.sort(key=lambda x: x[1])
+    return rows
+
+
+def _short(name: str) -> str:
+    """Kernel name without its argument list."""
+    name = name.strip()
+    if name.startswith("void "):
+        name = name[5:]
+    i = name.find("(")
+    return name[:i] if i > 0 else name
+
+
+def summarize_traces(tdir: str) -> None:
+    """Write the kernel-trace summaries of TRACE_RUNS from rocprofv3 runs made
+    by `rocprofv3 --kernel-trace -f csv -d <tdir>/<key> -o run -- python3
+    bench.py <args>` with stdout in <tdir>/<key>.log (no GPU use)."""
+    import collections
+    for key, (fname, title, args) in TRACE_RUNS.items():
+        path = os.path.join(tdir, key, "run_kernel_trace.csv")
+        if not os.path.exists(path):
+            print(f"skipping {key}: no {path}")
+            continue
+        rows = _trace_rows(path)
+        log = [x for x in open(os.path.join(tdir, key + ".log")) if x.startswith("{")]
+        line = json.loads(log[-1]) if log else {}
+        stats = collections.OrderedDict()
+        for k, t0, t1 in rows:
+            st = stats.setdefault(_short(k), [0, 0.0, 1e30, 0.0])
+            d = (t1 - t0) * 1e-3
+            st[0] += 1
+            st[1] += d
+            st[2] = min(st[2], d)
+            st[3] = max(st[3], d)
+        total = sum(v[1] for v in stats.values())
+        out = [f"# {title}", "",
+               "Command (from the repository root on the GPU box, `cd /tmp && export TMPDIR=/tmp` "
+               "first), then `python3 bench.py --summarize-traces <out>` for this summary:", "",
+               f"    rocprofv3 --kernel-trace -f csv -d <out>/{key} -o run -- python3 <repo>/bench.py "
+               f"{args} > <out>/{key}.log", "",
+               f"Kernel sources: `bench.kernel_source_hash()` = `{line.get('kernel_sources', '?')}`.", "",
+               "All dispatches of the process, from `run_kernel_trace.csv`:", "",
+               "| kernel | calls | total ms | average us | min us | max us | % of kernel time |",
+               "|---|---|---|---|---|---|---|"]
+        for k, (c, tot, mn, mx) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
+            out.append(f"| {k} | {c} | {tot / 1e3:.2f} | {tot / c:.1f} | {mn:.1f} | {mx:.1f} | "
+                       f"{100 * tot / total:.2f} |")
+        out += [""] + _trace_details(key, rows, line)
+        open(os.path.join(ROOT, "profiles", fname), "w").write("\n".join(out) + "\n")
+        print(f"wrote profiles/{fname}")
+
+
+def _trace_details(key, rows, line):
+    """Figures of one trace beyond the per-kernel table."""
+    pq = [(t0, t1) for k, t0, t1 in rows if "particle_queue" in k]
+    eph = [(t0, t1) for k, t0, t1 in rows if "ephemeris_chunk" in k]
+    out = []
+    if key in ("tl", "k100k", "res") and pq:
+        kern = line.get("kernel", {})
+        if key == "res":
+            r = line.get("resonant", {})
+            out += [f"Resonant line of the same run: {r.get('value', 0):.4g} active particle-steps/s end "
+                    f"to end, {r.get('particle_steps_per_s_kernels_only', 0):.4g} kernels only, "
+                    f"{r.get('run_ms', 0):.1f} ms, survivors {r.get('survivors')}.", ""]
+            return out
+        avg = sum(t1 - t0 for t0, t1 in pq) / len(pq) * 1e-6
+        out += [f"Bench line of the same run: {line.get('value', 0):.4g} active particle-steps/s, "
+                f"{line.get('ms_per_step', 0):.1f} ms per run; particle kernel "
+                f"{kern.get('launches')} launches, HIP-event average {kern.get('avg_launch_ms', 0):.3f} ms "
+                f"per launch against rocprofv3's {avg:.3f} ms.", ""]
+        if key == "tl":
+            span = (max(t1 for _, t1 in pq + eph) - min(t0 for t0, _ in pq + eph)) * 1e-6
+            bp = sum(t1 - t0 for t0, t1 in pq) * 1e-6
+            be = sum(t1 - t0 for t0, t1 in eph) * 1e-6
+            gaps = sum(max(0, pq[i + 1][0] - pq[i][1]) for i in range(len(pq) - 1)) * 1e-6
+            out += [f"Span of the run {span:.1f} ms; particle kernels busy {bp:.1f} ms "
+                    f"({100 * bp / span:.0f}%), planet map busy {be:.1f} ms ({100 * be / span:.0f}%); "
+                    f"gaps between particle launches {gaps:.1f} ms in total.", "",
+                    "Average duration per tenth of the run (launch 0 covers 1,024 steps, the others "
+                    "8,192 but the last):", "",
+                    "| launches | particle_queue us | ephemeris_chunk us |", "|---|---|---|"]
+            m = min(len(pq), len(eph))
+            step = max(1, m // 10)
+            for a in range(0, m, step):
+                b = min(m, a + step)
+                out.append(f"| {a}-{b - 1} | {sum(t1 - t0 for t0, t1 in pq[a:b]) / (b - a) / 1e3:.0f} | "
+                           f"{sum(t1 - t0 for t0, t1 in eph[a:b]) / (b - a) / 1e3:.0f} |")
+            out.append("")
+    if key == "ad":
+        a = line.get("adjoint", {})
+        seg = [(t0, t1) for k, t0, t1 in rows if "ad_segment" in k]
+        rev = [(t0, t1) for k, t0, t1 in rows if "ad_reverse" in k]
+        out += [f"Adjoint line of the same run: forward {a.get('forward_s', 0) * 1e3:.1f} ms, backward "
+                f"{a.get('backward_s', 0) * 1e3:.1f} ms (x{a.get('backward_over_forward', 0):.2f}); "
+                f"production forward {a.get('production_forward_s', 0) * 1e3:.1f} ms "
+                f"(backward over it x{a.get('backward_over_production_forward', 0):.2f}).", ""]
+        if rev:
+            # the timed backward pass: its sweeps and recomputations are the
+            # last nseg of each (a warm-up pass and the forward's segments
+            # come before them)
+            import re
+            m = re.search(r"(\d+) steps, checkpoint every (\d+)", a.get("workload", ""))
+            nseg = -(-int(m.group(1)) // int(m.group(2))) if m else len(rev)
+            rev, rec = rev[-nseg:], seg[-nseg:]
+            ov = sum(max(0, min(t1, u1) - max(t0, u0)) for t0, t1 in rec for u0, u1 in rev)
+            span = (max(t1 for _, t1 in rev + rec) - min(t0 for t0, _ in rev + rec)) * 1e-6
+            out += [f"Timed backward pass ({nseg} segments): sweeps (ad_reverse, caller's stream) "
+                    f"{sum(t1 - t0 for t0, t1 in rev) * 1e-6:.1f} ms busy, {sum(t1 - t0 for t0, t1 in rev) * 1e-3 / nseg:.0f} us "
+                    f"each; recomputations (ad_segment, library stream) "
+                    f"{sum(t1 - t0 for t0, t1 in rec) * 1e-6:.1f} ms busy, {ov * 1e-6:.1f} ms of it beside a "
+                    f"sweep; span {span:.1f} ms.", ""]
+    if key == "batched":
+        b = line.get("batched", {})
+        out += [f"Many-system line of the same run: {b.get('value', 0):.4g} active particle-steps/s, "
+                f"graph {b.get('graph_ms', 0):.1f} ms by HIP events, tuned {b.get('tuned')}, "
+                f"call {b.get('call_s_incl_setup_and_tuning', 0):.2f} s including set-up and tuning.", ""]
+    return out
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -424,12 +570,18 @@ def main():
     ap.add_argument("--ephemeris-only", action="store_true",
                     help="run only the planet map of the workload for --nsteps steps (its time "
                          "alone) and print one JSON line")
+    ap.add_argument("--summarize-traces", metavar="DIR",
+                    help="write the kernel-trace summaries under profiles/ from rocprofv3 "
+                         "--kernel-trace runs in DIR (see TRACE_RUNS), then exit (no GPU use)")
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="write the counter summary under profiles/ from rocprofv3 --pmc passes "
                          "p1..p4 in DIR, then exit (no GPU use)")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(args.summarize_counters)
+        return
+    if args.summarize_traces:
+        summarize_traces(args.summarize_traces)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs on a single MI355X "
