@@ -15,6 +15,9 @@ Entry points (each cites the passage of Zhang & Gladman 2021 it follows):
   the difference form of Kepler's equation with f and g functions, half kick,
   and the encounter / escape / Kepler-failure deactivation (sec. 2.2).
 * :func:`run`        - both of the above.
+* :func:`particles_handoff` - the particle map with the close-encounter
+  hand-off (sec. 5): encounter steps taken in substeps with the planets
+  interpolated between table rows.
 * :func:`history_table` - the planet table interpolated from a history of
   planet states instead of the planet map (sec. 2.2, planet positions from
   any source).
@@ -138,6 +141,9 @@ def _declare(lib):
     lib.orc_elements.restype = None
     lib.orc_mean_longitudes.argtypes = [d, i64, P, P, P]
     lib.orc_mean_longitudes.restype = None
+    lib.orc_particles_handoff.argtypes = [d, i, P, P, P, d, P, P, i64, d, i64, i, d, i, i, i64, P,
+                                          P, P, P, P, P, i]
+    lib.orc_particles_handoff.restype = d
     return lib
 
 
@@ -266,6 +272,43 @@ def particles(mu0: float, mu, rcrit, rmax: float, table, dt: float, r, v, nsteps
                                  n, _ptr(r), _ptr(v), _ptr(ds), _ptr(rs), _ptr(pl), int(nthreads),
                                  int(bool(universal)))
     return Result(r, v, ds, rs, pl, secs)
+
+
+@dataclass
+class HandoffResult(Result):
+    encounter_steps: np.ndarray = None   # encounter steps taken per particle
+
+
+def particles_handoff(mu0: float, mu, r_enc, r_rem, rmax: float, table, vtable, dt: float, r, v,
+                      nsteps: int | None = None, substeps: int = 32, step0: int = 0,
+                      kepler_iters: int = 5, ftol: float = KEPLER_FTOL, universal: bool = False,
+                      nthreads: int = 0) -> HandoffResult:
+    """Particles with the close-encounter hand-off (sec. 5; the reading is in
+    oracle.cpp above run_particle_handoff): a particle within r_enc of a
+    planet at a step boundary takes its next step as `substeps` substeps with
+    the planets interpolated between the rows (vtable: the planets'
+    heliocentric velocities per row, as ephemeris(keep_velocities=True) gives
+    them); removal within r_rem, beyond rmax, or on a refused drift."""
+    mu = _f64(mu).reshape(-1)
+    npl = mu.shape[0]
+    r_enc, r_rem = _f64(r_enc).reshape(-1), _f64(r_rem).reshape(-1)
+    table, vtable = _f64(table), _f64(vtable)
+    if nsteps is None:
+        nsteps = table.shape[0] - 1
+    assert table.shape[0] >= nsteps + 1 and vtable.shape[0] >= nsteps + 1
+    r = _f64(r).reshape(-1, 3).copy()
+    v = _f64(v).reshape(-1, 3).copy()
+    n = r.shape[0]
+    ds = np.zeros(n, dtype=np.int64)
+    rs = np.zeros(n, dtype=np.int32)
+    pl = np.zeros(n, dtype=np.int32)
+    es = np.zeros(n, dtype=np.int64)
+    secs = _load().orc_particles_handoff(float(mu0), npl, _ptr(mu), _ptr(r_enc), _ptr(r_rem),
+                                         float(rmax), _ptr(table), _ptr(vtable), int(nsteps),
+                                         float(dt), int(step0), int(kepler_iters), float(ftol),
+                                         int(bool(universal)), int(substeps), n, _ptr(r), _ptr(v),
+                                         _ptr(ds), _ptr(rs), _ptr(pl), _ptr(es), int(nthreads))
+    return HandoffResult(r, v, ds, rs, pl, secs, es)
 
 
 def run(w, nsteps: int | None = None, nthreads: int = 0):

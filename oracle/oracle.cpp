@@ -452,6 +452,131 @@ Deact run_particle(double mu0, int np, const double* mu, const double* rcrit, do
 }
 
 // ---------------------------------------------------------------------------
+// Close-encounter hand-off (sec. 5: particles in close encounters move off the
+// main integration to a separate treatment; the paper leaves the method open).
+// Reading: at every step boundary n, a particle within r_enc,j of any planet
+// takes its next step as an encounter step, any other particle the plain map
+// step above.  An encounter step divides dt into M equal substeps of
+// h = dt / M, each a kick - drift - kick of the same map:
+//   v += (h/2) a(t_i);  Kepler drift about mu0 for h;  v += (h/2) a(t_i + h),
+// with the planets between rows n and n+1 on the cubic Hermite interpolant of
+// their heliocentric positions and velocities at the two rows (the row values
+// themselves at the step's two ends), and h0 = -sum_j mu_j r_j / |r_j|^3 of
+// the interpolated positions.  Removal: within r_rem,j of a planet at any step
+// or substep boundary (lowest j; deact_step n at a step boundary n, n + 1 at a
+// substep inside step n), beyond rmax at a step boundary, a refused drift (the
+// state at the start of the failing substep, deact_step n).  At a boundary
+// the order is: within r_rem, beyond rmax, then the mode of the next step.
+// ---------------------------------------------------------------------------
+// Planet j's heliocentric position at fraction tau of the step between rows a
+// and b (positions ra, rb, velocities va, vb), by the cubic Hermite basis.
+inline void hermite_at(double tau, double dt, const double* ra, const double* va,
+                       const double* rb, const double* vb, double* out) {
+  const double t2 = tau * tau, t3 = t2 * tau;
+  const double h00 = 2.0 * t3 - 3.0 * t2 + 1.0;
+  const double h10 = t3 - 2.0 * t2 + tau;
+  const double h01 = -2.0 * t3 + 3.0 * t2;
+  const double h11 = t3 - t2;
+  for (int c = 0; c < 3; ++c)
+    out[c] = h00 * ra[c] + h10 * dt * va[c] + h01 * rb[c] + h11 * dt * vb[c];
+}
+
+// Acceleration of the particle at fraction tau of the step from row a (with
+// its velocities va) to row b: a = h0 - sum_j mu_j (r - r_j)/|r - r_j|^3 with
+// interpolated planets; returns the lowest j with |r - r_j| < rrem_j, or -1.
+int interp_accel(double tau, double dt, int np, const double* mu, const double* rrem,
+                 const double* rowa, const double* va, const double* rowb, const double* vb,
+                 const double r[3], double acc[3]) {
+  double pj[8][3];
+  double h0[3] = {0.0, 0.0, 0.0};
+  for (int j = 0; j < np; ++j) {
+    hermite_at(tau, dt, rowa + 3 * j, va + 3 * j, rowb + 3 * j, vb + 3 * j, pj[j]);
+    const double p2 = pj[j][0] * pj[j][0] + pj[j][1] * pj[j][1] + pj[j][2] * pj[j][2];
+    const double p3 = p2 * std::sqrt(p2);
+    for (int c = 0; c < 3; ++c) h0[c] -= mu[j] * pj[j][c] / p3;
+  }
+  for (int c = 0; c < 3; ++c) acc[c] = h0[c];
+  int hit = -1;
+  for (int j = 0; j < np; ++j) {
+    double d[3];
+    for (int c = 0; c < 3; ++c) d[c] = r[c] - pj[j][c];
+    const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const double dist = std::sqrt(d2);
+    if (hit < 0 && dist < rrem[j]) hit = j;
+    const double d3 = d2 * dist;
+    for (int c = 0; c < 3; ++c) acc[c] -= mu[j] * d[c] / d3;
+  }
+  return hit;
+}
+
+// Lowest planet index with |r - r_j| < rad_j in a table row, or -1.
+int within(const double* row, int np, const double* rad, const double r[3]) {
+  for (int j = 0; j < np; ++j) {
+    double d[3];
+    for (int c = 0; c < 3; ++c) d[c] = r[c] - row[3 * j + c];
+    if (std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) < rad[j]) return j;
+  }
+  return -1;
+}
+
+// One particle through rows 0..nsteps (table, and planet velocities vtable
+// [nsteps+1][np][3]) with the hand-off reading above; encounter_steps
+// receives the number of encounter steps taken.
+Deact run_particle_handoff(double mu0, int np, const double* mu, const double* renc,
+                           const double* rrem, double rmax, const double* table,
+                           const double* vtable, int64_t nsteps, double dt, int64_t step0,
+                           int kfix, double ftol, bool universal, int M, double r[3], double v[3],
+                           int64_t* encounter_steps) {
+  const int rowlen = 3 * np + 3;
+  const double h = dt / M;
+  auto escaped = [&](const double* rr) {
+    return rmax > 0.0 && std::sqrt(rr[0] * rr[0] + rr[1] * rr[1] + rr[2] * rr[2]) > rmax;
+  };
+  auto drift_or_fallback = [&](double* rr, double* vv, double tau_dt) {
+    return drift(mu0, rr, vv, tau_dt, kfix, ftol) != 0 ||
+           (universal && universal_fallback(mu0, rr, vv, tau_dt) != 0);
+  };
+  double acc[3];
+  kick_accel(table, np, mu, rrem, r, acc);
+  int hit = within(table, np, rrem, r);
+  if (hit >= 0) return {step0, ENCOUNTER, hit};
+  if (escaped(r)) return {step0, ESCAPE, -1};
+  *encounter_steps = 0;
+  for (int64_t i = 0; i < nsteps; ++i) {
+    const double* rowa = table + i * rowlen;
+    const double* rowb = table + (i + 1) * rowlen;
+    if (within(rowa, np, renc, r) < 0) {
+      // the plain map step
+      double rn[3], vn[3];
+      for (int k = 0; k < 3; ++k) { rn[k] = r[k]; vn[k] = v[k] + 0.5 * dt * acc[k]; }
+      if (!drift_or_fallback(rn, vn, dt)) return {step0 + i, KEPLER, -1};
+      hit = kick_accel(rowb, np, mu, rrem, rn, acc);
+      for (int k = 0; k < 3; ++k) { r[k] = rn[k]; v[k] = vn[k] + 0.5 * dt * acc[k]; }
+      if (hit >= 0) return {step0 + i + 1, ENCOUNTER, hit};
+    } else {
+      // an encounter step of M substeps
+      ++*encounter_steps;
+      const double* va = vtable + i * 3 * np;
+      const double* vb = vtable + (i + 1) * 3 * np;
+      for (int m = 0; m < M; ++m) {
+        double rn[3], vn[3];
+        for (int k = 0; k < 3; ++k) { rn[k] = r[k]; vn[k] = v[k] + 0.5 * h * acc[k]; }
+        if (!drift_or_fallback(rn, vn, h)) return {step0 + i, KEPLER, -1};
+        if (m + 1 == M) {
+          hit = kick_accel(rowb, np, mu, rrem, rn, acc);
+        } else {
+          hit = interp_accel((double)(m + 1) / M, dt, np, mu, rrem, rowa, va, rowb, vb, rn, acc);
+        }
+        for (int k = 0; k < 3; ++k) { r[k] = rn[k]; v[k] = vn[k] + 0.5 * h * acc[k]; }
+        if (hit >= 0) return {step0 + i + 1, ENCOUNTER, hit};
+      }
+    }
+    if (escaped(r)) return {step0 + i + 1, ESCAPE, -1};
+  }
+  return {-1, ACTIVE, -1};
+}
+
+// ---------------------------------------------------------------------------
 // Osculating heliocentric elements of (r, v) about mu by the textbook
 // two-body relations: a = 1/(2/r - v^2/mu); e from the eccentricity vector
 // ((v^2 - mu/r) r - (r.v) v)/mu; h = r x v gives the inclination and the
@@ -755,6 +880,32 @@ double orc_particles(double mu0, int np, const double* mu, const double* rcrit, 
     deact_step[i] = d.step;
     reason[i] = d.reason;
     planet[i] = d.planet;
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  return std::chrono::duration<double>(t1 - t0).count();
+}
+
+// Particles with the close-encounter hand-off (run_particle_handoff); the
+// state arrays are updated in place; encounter_steps[n] (may be null).
+double orc_particles_handoff(double mu0, int np, const double* mu, const double* renc,
+                             const double* rrem, double rmax, const double* table,
+                             const double* vtable, int64_t nsteps, double dt, int64_t step0,
+                             int kfix, double ftol, int universal, int M, int64_t n, double* r,
+                             double* v, int64_t* deact_step, int32_t* reason, int32_t* planet,
+                             int64_t* encounter_steps, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  auto t0 = std::chrono::steady_clock::now();
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t es = 0;
+    Deact d = run_particle_handoff(mu0, np, mu, renc, rrem, rmax, table, vtable, nsteps, dt, step0,
+                                   kfix, ftol, universal != 0, M, r + 3 * i, v + 3 * i, &es);
+    deact_step[i] = d.step;
+    reason[i] = d.reason;
+    planet[i] = d.planet;
+    if (encounter_steps) encounter_steps[i] = es;
   }
   auto t1 = std::chrono::steady_clock::now();
   return std::chrono::duration<double>(t1 - t0).count();

@@ -989,3 +989,130 @@ def test_universal_fallback_keeps_unbound_and_near_parabolic_particles(orc):
         err = np.linalg.norm(on.r[0] - ref) / np.linalg.norm(ref)
         print(f"two-body after {T} universal drifts: relative error {err:.2e}", flush=True)
         assert err < 1e-11
+
+
+# ------------------------------------------------------ close-encounter hand-off
+def _hermite(tau, dt, ra, va, rb, vb):
+    """Cubic Hermite interpolant between two planet states (written out here,
+    independently of the oracle's C++)."""
+    h00 = 2 * tau ** 3 - 3 * tau ** 2 + 1
+    h10 = tau ** 3 - 2 * tau ** 2 + tau
+    h01 = -2 * tau ** 3 + 3 * tau ** 2
+    h11 = tau ** 3 - tau ** 2
+    return h00 * ra + h10 * dt * va + h01 * rb + h11 * dt * vb
+
+
+def test_handoff_reduces_to_the_plain_map(orc):
+    """sec. 5 hand-off (reading in oracle.cpp): with one substep an encounter
+    step is the plain map step, so the whole run equals the plain map with
+    the removal radius as its encounter radius, bit for bit; and a particle
+    that never comes within the hand-off radius never leaves the plain map."""
+    w = W.giants_100k(n=1500, seed=71)
+    T = 2500
+    eph = orc.ephemeris(w.mu0, w.mu, w.rp, w.vp, T, w.dt, keep_velocities=True)
+    rrem = np.full(w.np_, 0.01)
+    plain = orc.particles(w.mu0, w.mu, rrem, w.rmax, eph.table, w.dt, w.r, w.v, T)
+    one = orc.particles_handoff(w.mu0, w.mu, w.rcrit, rrem, w.rmax, eph.table, eph.vtable, w.dt,
+                                w.r, w.v, T, substeps=1)
+    assert one.encounter_steps.sum() > 100
+    for k in ("r", "v", "deact_step", "reason", "planet"):
+        assert np.array_equal(getattr(one, k), getattr(plain, k)), k
+    tiny = np.full(w.np_, 1e-6)
+    many = orc.particles_handoff(w.mu0, w.mu, tiny, tiny, w.rmax, eph.table, eph.vtable, w.dt,
+                                 w.r, w.v, T, substeps=32)
+    ref = orc.particles(w.mu0, w.mu, tiny, w.rmax, eph.table, w.dt, w.r, w.v, T)
+    assert many.encounter_steps.sum() == 0
+    for k in ("r", "v", "deact_step", "reason", "planet"):
+        assert np.array_equal(getattr(many, k), getattr(ref, k)), k
+
+
+def test_encounter_substeps_converge_to_direct_integration(orc):
+    """An encounter step is a second-order map in its substep h: a close flyby
+    of a Jupiter-mass planet (closest approach about 0.04 au, a twentieth of
+    its Hill radius) over sixteen steps in encounter mode converges, as the
+    substep count doubles, to a DOP853 integration (rtol 1e-13) of the
+    particle's heliocentric equation of motion
+        r'' = -mu0 r/|r|^3 - mu_p (r - r_p)/|r - r_p|^3 - mu_p r_p/|r_p|^3
+    with the planet on the cubic Hermite interpolant of the table rows (the
+    same trajectory the map sees), the error falling about fourfold per
+    doubling."""
+    from scipy.integrate import solve_ivp
+    mu0 = W.MU_SUN
+    mup = 9.55e-4 * mu0
+    a = 5.2
+    rp = np.array([[a, 0.0, 0.0]])
+    vp = np.array([[0.0, math.sqrt((mu0 + mup) / a), 0.0]])
+    dt, T = 0.02, 16
+    eph = orc.ephemeris(mu0, np.array([mup]), rp, vp, T, dt, keep_velocities=True)
+    tab, vt = eph.table, eph.vtable
+    # a particle 0.26 au behind the planet on its orbit, 1.4 times faster:
+    # it overtakes the planet at about 0.04 au
+    phi = -0.05
+    r0 = np.array([[a * math.cos(phi), a * math.sin(phi), 0.05]])
+    v0 = np.array([[-math.sin(phi), math.cos(phi), 0.0]]) * math.sqrt(mu0 / a) * 1.4
+    renc, rrem = np.array([2.0]), np.array([1e-4])
+
+    def rhs(t, y, k):
+        tau = (t - k * dt) / dt
+        p = _hermite(tau, dt, tab[k, :3], vt[k], tab[k + 1, :3], vt[k + 1])
+        r = y[:3]
+        d = r - p
+        acc = (-mu0 * r / np.linalg.norm(r) ** 3 - mup * d / np.linalg.norm(d) ** 3
+               - mup * p / np.linalg.norm(p) ** 3)
+        return np.concatenate([y[3:], acc])
+
+    y = np.concatenate([r0[0], v0[0]])
+    dmin = np.inf
+    for k in range(T):
+        sol = solve_ivp(rhs, (k * dt, (k + 1) * dt), y, args=(k,), method="DOP853", rtol=1e-13,
+                        atol=1e-16, dense_output=True)
+        for t in np.linspace(k * dt, (k + 1) * dt, 50):
+            tau = (t - k * dt) / dt
+            p = _hermite(tau, dt, tab[k, :3], vt[k], tab[k + 1, :3], vt[k + 1])
+            dmin = min(dmin, np.linalg.norm(sol.sol(t)[:3] - p))
+        y = sol.y[:, -1]
+    assert dmin < 0.06, dmin
+    errs = []
+    for M in (8, 16, 32, 64, 128):
+        res = orc.particles_handoff(mu0, np.array([mup]), renc, rrem, 0.0, tab, vt, dt, r0, v0, T,
+                                    substeps=M, universal=True)
+        assert res.reason[0] == orc.ACTIVE and res.encounter_steps[0] == T
+        errs.append(np.linalg.norm(res.r[0] - y[:3]) / np.linalg.norm(y[:3]))
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    print(f"closest approach {dmin:.3f} au; errors {np.array(errs)}; ratios {np.round(ratios, 2)}",
+          flush=True)
+    assert all(3.5 < q < 4.5 for q in ratios), ratios
+    assert errs[-1] < 1e-7
+
+
+def test_handoff_removal_within_the_removal_radius(orc):
+    """Removal by proximity in an encounter step: a particle already within
+    the removal radius is removed at once (step 0, its initial state); one
+    falling onto the planet is removed at the step that contains the substep
+    boundary where it first comes within the radius (deact_step n + 1 for a
+    substep of step n), keeping that substep's state, which lies within the
+    radius of the planet's interpolated position at one of the step's
+    substep boundaries."""
+    mu0 = W.MU_SUN
+    mup = 9.55e-4 * mu0
+    a = 5.2
+    rp = np.array([[a, 0.0, 0.0]])
+    vp = np.array([[0.0, math.sqrt((mu0 + mup) / a), 0.0]])
+    dt, T, M = 0.05, 40, 16
+    eph = orc.ephemeris(mu0, np.array([mup]), rp, vp, T, dt, keep_velocities=True)
+    tab, vt = eph.table, eph.vtable
+    renc, rrem = np.array([1.0]), np.array([0.02])
+    inside = orc.particles_handoff(mu0, np.array([mup]), renc, rrem, 0.0, tab, vt, dt,
+                                   rp + [[0.01, 0.0, 0.0]], vp, T, substeps=M)
+    assert inside.deact_step[0] == 0 and inside.reason[0] == orc.ENCOUNTER
+    assert np.array_equal(inside.r, rp + [[0.01, 0.0, 0.0]])
+    # 0.3 au outside the planet, moving with it, falling in
+    r0 = rp + [[0.3, 0.0, 0.0]]
+    res = orc.particles_handoff(mu0, np.array([mup]), renc, rrem, 0.0, tab, vt, dt, r0, vp, T,
+                                substeps=M)
+    assert res.reason[0] == orc.ENCOUNTER and res.planet[0] == 0
+    n = int(res.deact_step[0]) - 1
+    assert 0 <= n < T
+    d = [np.linalg.norm(res.r[0] - _hermite(m / M, dt, tab[n, :3], vt[n], tab[n + 1, :3],
+                                             vt[n + 1])) for m in range(1, M + 1)]
+    assert min(d) < rrem[0]
