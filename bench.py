@@ -50,7 +50,7 @@ PMC_PASSES = {
     "p4": "WRITE_SIZE",
 }
 PMC_BENCH_ARGS = ("--nsteps 20000 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched "
-                  "--no-resonant --copy-calibration-mb 256")
+                  "--no-resonant --no-handoff --copy-calibration-mb 256")
 
 
 def kernel_source_hash() -> str:
@@ -263,20 +263,29 @@ def summarize_ephemeris(pmc_dir: str, tot, cnt, steps: int, src: str) -> None:
 TRACE_RUNS = {
     "tl": ("pipeline_giants_100k_1e6_timeline.md",
            "Pipeline timeline -- giants_100k, 100,000 particles x 1,000,000 steps (one benchmark run)",
-           "--steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched --no-resonant"),
+           "--steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched --no-resonant --no-handoff"),
     "k100k": ("particle_queue_giants_100k_kernel_trace.md",
               "particle_queue / ephemeris_chunk -- giants_100k, 100,000 particles x 100,000 steps",
-              "--nsteps 100000 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched --no-resonant"),
+              "--nsteps 100000 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched --no-resonant "
+              "--no-handoff"),
     "ad": ("ad_kernels_adjoint_16k_kernel_trace.md",
            "ad_segment / ad_reverse -- adjoint_16k, 16,384 particles x 100,000 steps, checkpoint 1,000",
-           "--nsteps 1000 --n 1024 --steps 1 --warmup 0 --no-cpu --no-batched --no-resonant"),
+           "--nsteps 1000 --n 1024 --steps 1 --warmup 0 --no-cpu --no-batched --no-resonant "
+           "--no-handoff"),
     "batched": ("particle_batch_queue_batched_512_kernel_trace.md",
                 "particle_batch_queue / ephemeris_batch -- 512 systems, 811,726 particles x 100,000 "
                 "steps (one graph launch)",
-                "--nsteps 1000 --n 1024 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-resonant"),
+                "--nsteps 1000 --n 1024 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-resonant "
+                "--no-handoff"),
     "res": ("particle_queue_resonant_200k_kernel_trace.md",
             "particle_queue / ephemeris_chunk -- resonant_200k, 200,000 particles x 1,000,000 steps",
-            "--nsteps 1000 --n 1024 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched"),
+            "--nsteps 1000 --n 1024 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched "
+            "--no-handoff"),
+    "ho": ("encounter_chunk_giants_100k_handoff_kernel_trace.md",
+           "particle_queue / encounter_chunk -- giants_100k with the close-encounter hand-off, "
+           "100,000 particles x 1,000,000 steps, 16 substeps",
+           "--nsteps 1000 --n 1024 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched "
+           "--no-resonant"),
 }
 
 
@@ -396,6 +405,21 @@ def _trace_details(key, rows, line):
                     f"each; recomputations (ad_segment, library stream) "
                     f"{sum(t1 - t0 for t0, t1 in rec) * 1e-6:.1f} ms busy, {ov * 1e-6:.1f} ms of it beside a "
                     f"sweep; span {span:.1f} ms.", ""]
+    if key == "ho":
+        h = line.get("handoff", {})
+        enc = [(t0, t1) for k, t0, t1 in rows if "encounter_chunk" in k]
+        ov = 0
+        for t0, t1 in enc:          # overlap of each encounter launch with the particle launches
+            ov += sum(max(0, min(t1, u1) - max(t0, u0)) for u0, u1 in pq)
+        out += [f"Hand-off line of the same run: {h.get('value', 0):.4g} active particle-steps/s, "
+                f"{h.get('run_ms', 0):.1f} ms, {h.get('handoffs')} hand-offs, removed by reason "
+                f"{h.get('removed_by_reason')}, survivors {h.get('survivors')}.", ""]
+        if enc:
+            out += [f"encounter_chunk: {len(enc)} launches, {sum(t1 - t0 for t0, t1 in enc) * 1e-6:.1f} ms "
+                    f"busy, {ov * 1e-6:.1f} ms of it beside a particle_queue launch; particle_queue "
+                    f"{sum(t1 - t0 for t0, t1 in pq) * 1e-6:.1f} ms busy.", "",
+                    "encounter_chunk durations in launch order, ms:", "",
+                    "    " + " ".join(f"{(t1 - t0) * 1e-6:.0f}" for t0, t1 in enc), ""]
     if key == "batched":
         b = line.get("batched", {})
         out += [f"Many-system line of the same run: {b.get('value', 0):.4g} active particle-steps/s, "
@@ -541,6 +565,35 @@ def resonant_run(P, W, torch, nsteps: int):
             "compactions": st["compactions"]}
 
 
+def handoff_run(P, W, torch, nsteps: int, substeps: int = 16, r_rem: float = 0.05):
+    """The headline workload with the close-encounter hand-off: a particle
+    within 0.5 au of a planet moves to the encounter integrator (substeps
+    substeps per step, planets on their Hermite interpolants) and is removed
+    within r_rem; the encounter stream runs one chunk behind the main one."""
+    w = W.giants_100k()
+    s = P.Simulation(r_escape=w.rmax, kepler_iters=w.kepler_iters, time_kernels=True,
+                     handoff_substeps=substeps, universal_drift=True)
+    s.set_central(w.mu0)
+    s.set_planets(w.mu, w.rp, w.vp, w.rcrit)
+    s.set_removal_radii([r_rem] * w.np_)
+    s.set_particles(w.r, w.v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.integrate(nsteps, w.dt)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    st = s.stats()
+    s.close()
+    return {"workload": f"giants_100k with the close-encounter hand-off: 100,000 particles, "
+                        f"4 planets, dt = 120 d, {nsteps} steps, hand-off within 0.5 au, "
+                        f"{substeps} substeps per encounter step, removal within {r_rem} au",
+            "value": st["active_particle_steps"] / secs, "unit": "particle-steps/s",
+            "run_ms": secs * 1e3, "handoffs": st["handoffs"],
+            "particle_kernel_ms": st["particle_kernel_ms"],
+            "active_particle_steps": st["active_particle_steps"],
+            "removed_by_reason": st["count_by_reason"][1:], "survivors": st["count_by_reason"][0]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -564,6 +617,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=100_000)
     ap.add_argument("--no-resonant", action="store_true")
     ap.add_argument("--resonant-steps", type=int, default=1_000_000)
+    ap.add_argument("--no-handoff", action="store_true")
+    ap.add_argument("--handoff-steps", type=int, default=1_000_000)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device with a plain copy "
                          "kernel (the reference for scaling HBM byte counters)")
@@ -703,6 +758,9 @@ def main():
     if not args.no_resonant:
         line["resonant"] = resonant_run(P, W, torch, args.resonant_steps)
         print("resonant done", file=sys.stderr, flush=True)
+    if not args.no_handoff:
+        line["handoff"] = handoff_run(P, W, torch, args.handoff_steps)
+        print("handoff done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.cpu_single)
     print(json.dumps(line))

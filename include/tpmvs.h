@@ -88,6 +88,28 @@ typedef struct {
                              wavefronts hold particles of similar Newton counts and the
                              most eccentric tiles are taken first; never changes
                              results; 0 = caller order                                */
+  /* Close-encounter hand-off (sec. 5: particles in close encounters move off
+   * the main integration; the paper leaves the method open, this library's
+   * reading follows).  With handoff_substeps = M > 0, a particle that comes
+   * within a planet's r_crit (tpm_set_planets; the hand-off radius) is not
+   * removed but handed off to a secondary kernel that integrates the list of
+   * such particles one chunk behind the main kernel, on a stream of its own:
+   * at every step boundary a particle within the hand-off radius of any
+   * planet takes its next step as M equal substeps of the same kick - drift -
+   * kick, with the planets between the two table rows on the cubic Hermite
+   * interpolant of their heliocentric positions and velocities (the row
+   * values at the step's two ends) and h0 from the interpolated positions;
+   * any other step is the plain map step.  A particle is removed within its
+   * removal radius (tpm_set_removal_radii) at any step or substep boundary
+   * (reason TPM_ENCOUNTER; step n at a step boundary, n + 1 at a substep
+   * inside step n, keeping that substep's state), beyond r_escape at a step
+   * boundary, or on a refused drift (TPM_KEPLER, the state at the start of
+   * the failing substep).  The list's particles rejoin the main working set
+   * at the end of each tpm_integrate.  Needs the on-device planet map (no
+   * supplied table or history) and removal radii; tpm_integrate returns
+   * TPM_ESTATE otherwise, and with diagnostics on.  The derivative, many-system
+   * and no-allocation calls refuse it.  0 = off (removal at r_crit).          */
+  int32_t handoff_substeps;
 } tpm_options;
 
 typedef struct {
@@ -108,6 +130,7 @@ typedef struct {
   int32_t block_threads;          /* workgroup size, chunk length and compaction  */
   int32_t chunk_steps;            /* interval used (after autotuning)             */
   int32_t resync_chunks;
+  int64_t handoffs;               /* close-encounter hand-offs in the last integrate */
 } tpm_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -133,6 +156,13 @@ int tpm_set_planets(tpm_sim* sim, int32_t np, const double* mu, const double* r,
 
 /* n particles, heliocentric r[n][3], v[n][3]; all active.  0 <= n < 2^31. */
 int tpm_set_particles(tpm_sim* sim, int64_t n, const double* r, const double* v);
+
+/* Removal radii r_rem[np] (> 0, caller planet order) of the close-encounter
+ * hand-off (see tpm_options.handoff_substeps): a handed-off particle within
+ * r_rem of a planet is removed.  After tpm_set_planets (which, like
+ * tpm_set_state, clears them); TPM_ESTATE before it, TPM_EINVAL for a radius
+ * that is not positive and finite. */
+int tpm_set_removal_radii(tpm_sim* sim, const double* r_rem);
 
 /* Advance planets and particles by nsteps steps of dt (dt < 0 integrates
  * backwards).  Checks run at every step boundary, including the first and last.

@@ -36,7 +36,7 @@ class Options(C.Structure):
                 ("sub_chunks", C.c_int32), ("waves_per_simd", C.c_int32),
                 ("r_escape", C.c_double), ("kepler_ftol", C.c_double), ("device", C.c_int32),
                 ("time_kernels", C.c_int32), ("universal_drift", C.c_int32),
-                ("sort_by_e", C.c_int32)]
+                ("sort_by_e", C.c_int32), ("handoff_substeps", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -46,7 +46,8 @@ class Stats(C.Structure):
                 ("particle_kernel_ms", C.c_double), ("compactions", C.c_int64),
                 ("count_by_reason", C.c_int64 * 4), ("sub_chunks", C.c_int32),
                 ("waves_per_simd", C.c_int32), ("block_threads", C.c_int32),
-                ("chunk_steps", C.c_int32), ("resync_chunks", C.c_int32)]
+                ("chunk_steps", C.c_int32), ("resync_chunks", C.c_int32),
+                ("handoffs", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "count_by_reason"}
@@ -74,6 +75,7 @@ SIGNATURES = {
     "tpm_set_central": (C.c_int, [_P, C.c_double]),
     "tpm_set_planets": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P]),
     "tpm_set_particles": (C.c_int, [_P, C.c_int64, _P, _P]),
+    "tpm_set_removal_radii": (C.c_int, [_P, _P]),
     "tpm_integrate": (C.c_int, [_P, C.c_int64, C.c_double]),
     "tpm_get_particles": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "tpm_get_planets": (C.c_int, [_P, _P, _P]),
@@ -161,7 +163,7 @@ class Simulation:
                  block_threads: int = 0, r_escape: float = 0.0, kepler_ftol: float = 0.0,
                  device: int = 0, time_kernels: bool = False, sub_chunks: int = 0,
                  waves_per_simd: int = 0, universal_drift: bool = False,
-                 sort_by_e: bool = False):
+                 sort_by_e: bool = False, handoff_substeps: int = 0):
         lib = load()
         o = default_options()
         o.kepler_iters, o.chunk_steps, o.resync_chunks = kepler_iters, chunk_steps, resync_chunks
@@ -170,6 +172,7 @@ class Simulation:
         o.time_kernels = int(bool(time_kernels))
         o.sub_chunks, o.waves_per_simd = sub_chunks, waves_per_simd
         o.universal_drift, o.sort_by_e = int(bool(universal_drift)), int(bool(sort_by_e))
+        o.handoff_substeps = int(handoff_substeps)
         h = C.c_void_p()
         _check(lib.tpm_create(C.byref(o), C.byref(h)))
         self._h = h
@@ -203,6 +206,12 @@ class Simulation:
         rc = _f64(r_crit, (npl,))
         _check(load().tpm_set_planets(self._h, npl, _p(mu), _p(r), _p(v), _p(rc)))
         self.np = npl
+
+    def set_removal_radii(self, r_rem):
+        """Per-planet removal radii of the close-encounter hand-off
+        (tpm_set_removal_radii; after set_planets)."""
+        rr = _f64(r_rem, (self.np,))
+        _check(load().tpm_set_removal_radii(self._h, _p(rr)))
 
     def set_particles(self, r, v):
         r = _f64(r, (-1, 3))

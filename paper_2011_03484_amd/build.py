@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpmvs.so")
 SOURCES = ["kernels_core.hip", "ad_kernels.hip", "diag_kernels.hip", "history.hip",
-           "runtime.hip", "static_run.hip"]
+           "handoff.hip", "runtime.hip", "static_run.hip"]
 HEADERS = ["dmath.hpp", "kepler.hpp", "particle.hpp", "universal.hpp", "ad.hpp", "internal.h",
            "ad_internal.h", "diag_internal.h", "history_internal.h"]
 

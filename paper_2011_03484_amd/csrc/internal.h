@@ -44,6 +44,23 @@ struct SysConst {
   int kiters;
   double ftol;
   int universal;         // 1: refused drifts are retried in universal variables
+  int handoff;           // 1: within rcrit a particle is handed off, not removed
+};
+
+// Particles handed off to the encounter integrator (close-encounter hand-off):
+// structure of arrays of capacity n, filled in hand-off order; `step` is the
+// global step of each entry's state, `status` ST_ACTIVE or its removal reason.
+struct EncList {
+  double* x;
+  double* y;
+  double* z;
+  double* vx;
+  double* vy;
+  double* vz;
+  int32_t* slot;
+  int32_t* status;
+  int64_t* step;
+  int32_t* count;        // entries in use
 };
 
 // Ephemeris constants (bodies 0..np, body 0 = central mass).
@@ -82,9 +99,32 @@ hipError_t launch_particle_chunk(const SysConst& S, Work w, const int32_t* d_nac
 // approach (or -2 for an unbound planet) if it is still -1.  vside (may be
 // null) receives the heliocentric planet velocities at rows 0 and nsteps,
 // [2][np][3].
+// vrows (may be null) receives the heliocentric planet velocities of every
+// row, [nsteps+1][np][3] (for the encounter integrator's interpolation).
 hipError_t launch_ephemeris_chunk(const EphConst& E, double* rj, double* vj, double* rows,
                                   int nsteps, double dt, int64_t step0, int64_t* flag,
-                                  hipStream_t st, double* vside = nullptr);
+                                  hipStream_t st, double* vside = nullptr,
+                                  double* vrows = nullptr);
+
+// ---- close-encounter hand-off
+// Move the working set's handed-off entries (status >= HANDOFF_BASE, set by
+// the particle kernel of the chunk that starts at step0) to the end of the
+// encounter list, marking them handed in the working set; snap receives the
+// list's new length.
+hipError_t launch_handoff_gather(Work w, const int32_t* d_nactive, int n_upper, EncList L,
+                                 int64_t step0, int32_t* snap, hipStream_t st);
+// Advance the first *snap list entries through the chunk's steps [step0,
+// step0 + nsteps) with the encounter reading (plain map steps outside the
+// hand-off radius S.rcrit2, M substeps with interpolated planets inside it,
+// removal within rrem2); rows and vrows as the planet map wrote them.
+hipError_t launch_encounter_chunk(const SysConst& S, const double* rrem2, EncList L,
+                                  const int32_t* snap, int n_upper, const double* rows,
+                                  const double* vrows, int nsteps, double dt, int64_t step0,
+                                  int M, Out out, hipStream_t st);
+// Append the list's active entries to the working set (after its active
+// entries, *d_nactive grows) and empty the list.
+hipError_t launch_handoff_merge(EncList L, int n_upper, Work w, int32_t* d_nactive,
+                                hipStream_t st);
 
 // Stable partition of the working set: active entries of src (in order) go to
 // dst; d_nactive is updated in place.  scratch holds >= 2 * nblocks + 1 ints.

@@ -27,6 +27,7 @@ struct ChunkArgs {
   double rmax2, ftol, dt;
   int kiters, nsteps;
   int64_t step0;
+  int handoff;   // within rcrit: hand off to the encounter integrator, not removal
 };
 
 // Advance particle i of the working set through steps [s_begin, s_end) of a
@@ -53,10 +54,20 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
   }
   // A lane's removal record (the state it keeps, step, reason, planet) is
   // written out in the step that removes it, so the state registers can be
-  // overwritten unconditionally; a removed lane takes no further part.
+  // overwritten unconditionally; a removed lane takes no further part.  With
+  // the hand-off on, a lane within a planet's radius is handed off instead:
+  // its state stays in the working set, marked with its local step, for the
+  // encounter integrator.
   int32_t reason = valid ? ST_ACTIVE : -1;
   auto record = [&](int32_t why, int64_t st, int32_t pl, double rx, double ry, double rz,
                     double ux, double uy, double uz) {
+    if (A.handoff && why == ST_ENCOUNTER) {
+      w.x[i] = rx; w.y[i] = ry; w.z[i] = rz;
+      w.vx[i] = ux; w.vy[i] = uy; w.vz[i] = uz;
+      reason = HANDOFF_BASE + (int32_t)(st - A.step0);
+      w.status[i] = reason;
+      return;
+    }
     const int k = w.slot[i];
     out.r[3 * k + 0] = rx; out.r[3 * k + 1] = ry; out.r[3 * k + 2] = rz;
     out.v[3 * k + 0] = ux; out.v[3 * k + 1] = uy; out.v[3 * k + 2] = uz;
@@ -230,6 +241,7 @@ TPM_DEV void batch_item(const SysDev& S, Work w, Out out, const double* __restri
   A.kiters = S.kiters;
   A.nsteps = Q.nsteps;
   A.step0 = Q.step0;
+  A.handoff = 0;
   const double* rows = ring + S.ring_off + (int64_t)Q.slot * Q.slot_rows * (3 * NP + 3);
   const int i = T.first + lane;
   const bool valid = lane < T.count;
@@ -396,6 +408,7 @@ static hipError_t launch_np(const SysConst& S, Work w, const int32_t* d_nactive,
   A.kiters = S.kiters;
   A.nsteps = nsteps;
   A.step0 = step0;
+  A.handoff = S.handoff;
   QueueArgs Q;
   Q.ctr = QL.ctr;
   Q.base = QL.base;
@@ -684,11 +697,12 @@ TPM_DEV void write_helio_velocities(const EphConst& E, const EphW<NP>& W, bool b
 // key ordered in time (see ephemeris_body); the fast form returns instead
 // whether the lane would have taken another path than its own (the general
 // drift's branches), or, with events on, met an event at all.
-template <int NP, bool ROWB, bool FAST>
+template <int NP, bool ROWB, bool FAST, bool VEL>
 TPM_DEV bool eph_step(const EphConst& E, const EphLane& L, const EphW<NP>& W, double h, double dt,
                       double& jx, double& jy, double& jz, double& wx, double& wy, double& wz,
                       double& ax, double& ay, double& az, bool writer, double rsign,
-                      double* __restrict__ row, uint32_t key1, bool events, uint32_t& first_ev) {
+                      double* __restrict__ row, double* __restrict__ vrow, uint32_t key1,
+                      bool events, uint32_t& first_ev) {
   double hx[NP + 1], hy[NP + 1], hz[NP + 1];
   double ox, oy, oz;
   wx = fma_(h, ax, wx); wy = fma_(h, ay, wy); wz = fma_(h, az, wz);
@@ -709,6 +723,7 @@ TPM_DEV bool eph_step(const EphConst& E, const EphLane& L, const EphW<NP>& W, do
     if (FAST) bad = bad | (events & close);
     else first_ev = __builtin_elementwise_min(first_ev, close ? key1 + 1u : UINT32_MAX);
   }
+  if (VEL) write_helio_velocities<NP, ROWB>(E, W, L.body, L.lane, wx, wy, wz, vrow);
   return bad;
 }
 
@@ -717,10 +732,13 @@ constexpr int EPH_BLOCK = 64;
 
 // vside (may be null): receives the planets' heliocentric velocities at the
 // chunk's first and last rows, [2][NP][3] (for the sampled diagnostics).
-template <int NP, bool ROWB>
+// VEL: vrows receives them at every row, [nsteps+1][NP][3] (for the
+// encounter integrator).
+template <int NP, bool ROWB, bool VEL = false>
 TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* __restrict__ vj,
                             double* __restrict__ rows, int nsteps, double dt, int64_t step0,
-                            int64_t* __restrict__ flag, double* __restrict__ vside = nullptr) {
+                            int64_t* __restrict__ flag, double* __restrict__ vside = nullptr,
+                            double* __restrict__ vrows = nullptr) {
   constexpr int ROW = 3 * NP + 3;
   // This wave is a serial chain that shares its SIMD with particle waves:
   // let it issue first.
@@ -774,6 +792,7 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
   uint32_t first_ev = UINT32_MAX;
   if (NP > 1 && hill_violation<NP>(W, ox, oy, oz, hx, hy, hz)) first_ev = 1u;
   if (vside) write_helio_velocities<NP, ROWB>(E, W, L.body, L.lane, wx, wy, wz, vside);
+  if (VEL) write_helio_velocities<NP, ROWB>(E, W, L.body, L.lane, wx, wy, wz, vrows);
   // Blocks of EPH_BLOCK steps.  Giant planets on near-circular orbits take
   // the general drift's short sin/cos path and leave its Newton loop after
   // two steps every time, and meet no event; the fast form runs exactly that,
@@ -795,9 +814,11 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
       bool bad = false;
       for (int t = 0; t < nb; ++t) {
         const int s = s0 + t;
-        bad = bad | eph_step<NP, ROWB, true>(E, L, W, h, dt, jx, jy, jz, wx, wy, wz, ax, ay, az,
-                                             writer, rsign, rows + (size_t)(s + 1) * ROW + roff,
-                                             2u * (uint32_t)(s + 1), events, first_ev);
+        bad = bad | eph_step<NP, ROWB, true, VEL>(
+                        E, L, W, h, dt, jx, jy, jz, wx, wy, wz, ax, ay, az, writer, rsign,
+                        rows + (size_t)(s + 1) * ROW + roff,
+                        VEL ? vrows + (size_t)(s + 1) * 3 * NP : nullptr, 2u * (uint32_t)(s + 1),
+                        events, first_ev);
       }
       if (wave_all(!bad)) continue;
       jx = sjx; jy = sjy; jz = sjz; wx = swx; wy = swy; wz = swz;
@@ -806,9 +827,10 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
     }
     for (int t = 0; t < nb; ++t) {
       const int s = s0 + t;
-      eph_step<NP, ROWB, false>(E, L, W, h, dt, jx, jy, jz, wx, wy, wz, ax, ay, az, writer, rsign,
-                                rows + (size_t)(s + 1) * ROW + roff, 2u * (uint32_t)(s + 1), events,
-                                first_ev);
+      eph_step<NP, ROWB, false, VEL>(E, L, W, h, dt, jx, jy, jz, wx, wy, wz, ax, ay, az, writer,
+                                     rsign, rows + (size_t)(s + 1) * ROW + roff,
+                                     VEL ? vrows + (size_t)(s + 1) * 3 * NP : nullptr,
+                                     2u * (uint32_t)(s + 1), events, first_ev);
     }
   }
   if (vside) write_helio_velocities<NP, ROWB>(E, W, L.body, L.lane, wx, wy, wz, vside + 3 * NP);
@@ -827,12 +849,12 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
     *flag = (ev & 1u) ? step0 + (int64_t)(ev >> 1) : -2;
 }
 
-template <int NP>
+template <int NP, bool VEL>
 __global__ void __launch_bounds__(64) TPM_PLANET_KERNEL
 ephemeris_chunk(EphConst E, double* __restrict__ rj, double* __restrict__ vj,
                 double* __restrict__ rows, int nsteps, double dt, int64_t step0,
-                int64_t* __restrict__ flag, double* __restrict__ vside) {
-  ephemeris_body<NP, false>(E, rj, vj, rows, nsteps, dt, step0, flag, vside);
+                int64_t* __restrict__ flag, double* __restrict__ vside, double* __restrict__ vrows) {
+  ephemeris_body<NP, false, VEL>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, vrows);
 }
 
 // Many systems at once: workgroup b runs system b (its constants, Jacobi
@@ -876,26 +898,27 @@ hipError_t launch_ephemeris_batch(const EphConst* E, double* rj, double* vj, dou
 
 template <int NP>
 static hipError_t eph_np(const EphConst& E, double* rj, double* vj, double* rows, int nsteps,
-                         double dt, int64_t step0, int64_t* flag, double* vside, hipStream_t st) {
-  hipLaunchKernelGGL(ephemeris_chunk<NP>, dim3(1), dim3(64), 0, st, E, rj, vj, rows, nsteps, dt,
-                     step0, flag, vside);
+                         double dt, int64_t step0, int64_t* flag, double* vside, double* vrows,
+                         hipStream_t st) {
+  if (vrows)
+    hipLaunchKernelGGL((ephemeris_chunk<NP, true>), dim3(1), dim3(64), 0, st, E, rj, vj, rows,
+                       nsteps, dt, step0, flag, vside, vrows);
+  else
+    hipLaunchKernelGGL((ephemeris_chunk<NP, false>), dim3(1), dim3(64), 0, st, E, rj, vj, rows,
+                       nsteps, dt, step0, flag, vside, vrows);
   return hipGetLastError();
 }
 
 hipError_t launch_ephemeris_chunk(const EphConst& E, double* rj, double* vj, double* rows,
                                   int nsteps, double dt, int64_t step0, int64_t* flag,
-                                  hipStream_t st, double* vside) {
+                                  hipStream_t st, double* vside, double* vrows) {
   if (nsteps < 0 || nsteps > MAX_EPH_STEPS) return hipErrorInvalidValue;
   switch (E.np) {
-    case 0: return eph_np<0>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
-    case 1: return eph_np<1>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
-    case 2: return eph_np<2>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
-    case 3: return eph_np<3>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
-    case 4: return eph_np<4>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
-    case 5: return eph_np<5>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
-    case 6: return eph_np<6>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
-    case 7: return eph_np<7>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
-    case 8: return eph_np<8>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, st);
+#define TPM_EPH(N) \
+    case N: return eph_np<N>(E, rj, vj, rows, nsteps, dt, step0, flag, vside, vrows, st);
+    TPM_EPH(0) TPM_EPH(1) TPM_EPH(2) TPM_EPH(3) TPM_EPH(4) TPM_EPH(5) TPM_EPH(6) TPM_EPH(7)
+    TPM_EPH(8)
+#undef TPM_EPH
     default: return hipErrorInvalidValue;
   }
 }

@@ -5,6 +5,11 @@
 namespace tpm {
 
 enum : int32_t { ST_ACTIVE = 0, ST_ENCOUNTER = 1, ST_ESCAPE = 2, ST_KEPLER = 3 };
+// Working-set states of the close-encounter hand-off (never in results):
+// HANDOFF_BASE + t, handed off at local step t of the current chunk; ST_HANDED,
+// moved to the encounter list.
+constexpr int32_t ST_HANDED = 4;
+constexpr int32_t HANDOFF_BASE = 16;
 
 // Planet constants of one system, passed by value so they land in SGPRs.
 template <int NP>

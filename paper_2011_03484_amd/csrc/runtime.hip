@@ -59,6 +59,7 @@ int fail(int code, const std::string& msg) {
 struct DeviceStreams {
   std::mutex lock;
   hipStream_t sP = nullptr, sE = nullptr;
+  hipStream_t sH = nullptr;   // encounter integrator (close-encounter hand-off), on first use
 };
 
 DeviceStreams& device_streams(int dev) {
@@ -247,8 +248,23 @@ struct tpm_sim {
     int64_t last_step = -1;                // last sampled global step
   } diag;
   double* d_vside = nullptr;             // [NSLOT][2][np][3] planet velocities at chunk ends
+  // close-encounter hand-off: removal radii (internal order), the encounter
+  // list (capacity n), per-slot list lengths, the planets' velocities per row
+  // of every ring slot, and the events ordering the encounter stream
+  std::vector<double> rrem_s;
+  bool rrem_set = false;
+  EncList enc{};
+  int32_t* d_snap = nullptr;             // [NSLOT]
+  double* d_vring = nullptr;             // [NSLOT][ring_rows][np][3]
+  int64_t vring_rows = 0;
+  hipEvent_t ev_gath[NSLOT]{}, ev_hdone[NSLOT]{};
 
   ~tpm_sim() {
+    release_handoff();
+    for (int k = 0; k < NSLOT; ++k) {
+      if (ev_gath[k]) (void)hipEventDestroy(ev_gath[k]);
+      if (ev_hdone[k]) (void)hipEventDestroy(ev_hdone[k]);
+    }
     release_ad();
     release_diag();
     release_particles();
@@ -280,7 +296,16 @@ struct tpm_sim {
     diag = Diag{};
   }
 
+  void release_handoff() {
+    dfree(enc.x); dfree(enc.y); dfree(enc.z); dfree(enc.vx); dfree(enc.vy); dfree(enc.vz);
+    dfree(enc.slot); dfree(enc.status); dfree(enc.step); dfree(enc.count);
+    enc = EncList{};
+    dfree(d_snap);
+    dfree(d_vring);
+    vring_rows = 0;
+  }
   void release_particles() {
+    release_handoff();
     release_diag();
     for (auto& w : work) {
       dfree(w.x); dfree(w.y); dfree(w.z); dfree(w.vx); dfree(w.vy); dfree(w.vz);
@@ -354,6 +379,7 @@ struct tpm_sim {
     S.kiters = opt.kepler_iters;
     S.ftol = opt.kepler_ftol;
     S.universal = opt.universal_drift ? 1 : 0;
+    S.handoff = opt.handoff_substeps > 0 ? 1 : 0;
     return S;
   }
 
@@ -361,6 +387,41 @@ struct tpm_sim {
 };
 
 namespace {
+
+// Buffers of the close-encounter hand-off for a run whose ring slots hold
+// `rows` rows: the encounter list (capacity n, empty), per-slot list lengths,
+// the planets' velocities per row of every slot, the ordering events and the
+// device's encounter stream.
+int ensure_handoff(tpm_sim* s, int64_t rows) {
+  DeviceStreams& D = device_streams(s->opt.device);
+  if (!D.sH) TPM_HIP(hipStreamCreateWithFlags(&D.sH, hipStreamNonBlocking));
+  if (!s->ev_gath[0])
+    for (int k = 0; k < NSLOT; ++k) {
+      TPM_HIP(hipEventCreateWithFlags(&s->ev_gath[k], hipEventDisableTiming));
+      TPM_HIP(hipEventCreateWithFlags(&s->ev_hdone[k], hipEventDisableTiming));
+    }
+  const size_t n = std::max<int64_t>(s->n, 1);
+  if (!s->enc.count) {
+    EncList& L = s->enc;
+    for (double** p : {&L.x, &L.y, &L.z, &L.vx, &L.vy, &L.vz})
+      TPM_HIP(hipMalloc(p, sizeof(double) * n));
+    TPM_HIP(hipMalloc(&L.slot, sizeof(int32_t) * n));
+    TPM_HIP(hipMalloc(&L.status, sizeof(int32_t) * n));
+    TPM_HIP(hipMalloc(&L.step, sizeof(int64_t) * n));
+    TPM_HIP(hipMalloc(&L.count, sizeof(int32_t)));
+    TPM_HIP(hipMemset(L.count, 0, sizeof(int32_t)));
+    TPM_HIP(hipMalloc(&s->d_snap, sizeof(int32_t) * NSLOT));
+    TPM_HIP(hipMemset(s->d_snap, 0, sizeof(int32_t) * NSLOT));
+  }
+  if (s->vring_rows < rows || !s->d_vring) {
+    TPM_HIP(hipStreamSynchronize(s->sE));
+    TPM_HIP(hipStreamSynchronize(D.sH));
+    dfree(s->d_vring);
+    TPM_HIP(hipMalloc(&s->d_vring, sizeof(double) * NSLOT * rows * 3 * std::max(s->np, 1)));
+    s->vring_rows = rows;
+  }
+  return TPM_OK;
+}
 
 int ensure_ring(tpm_sim* s, int64_t rows) {
   if (s->ring_rows >= rows && s->d_ring) return TPM_OK;
@@ -502,6 +563,7 @@ void tpm_default_options(tpm_options* o) {
   o->time_kernels = 0;
   o->universal_drift = 0;
   o->sort_by_e = 0;
+  o->handoff_substeps = 0;
 }
 
 const char* tpm_last_error(void) { return g_err.c_str(); }
@@ -532,6 +594,8 @@ int tpm_create(const tpm_options* opt, tpm_sim** out) {
     return fail(TPM_EINVAL, "block_threads must be 64, 128, 192 or 256");
   if (!(o.kepler_ftol > 0.0)) o.kepler_ftol = 1e-13;
   if (!std::isfinite(o.r_escape)) return fail(TPM_EINVAL, "r_escape not finite");
+  if (o.handoff_substeps < 0 || o.handoff_substeps > 4096)
+    return fail(TPM_EINVAL, "handoff_substeps must be 0..4096");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
     return fail(TPM_EDEVICE, "no HIP device");
@@ -659,6 +723,22 @@ int tpm_set_planets(tpm_sim* s, int32_t np, const double* mu, const double* r, c
   TPM_HIP(hipMemcpy(s->d_flag, &m1, sizeof(m1), hipMemcpyHostToDevice));
   s->step = 0;
   s->planets_set = true;
+  s->rrem_set = false;
+  return TPM_OK;
+}
+
+int tpm_set_removal_radii(tpm_sim* s, const double* r_rem) {
+  if (!s) return fail(TPM_EINVAL, "sim is NULL");
+  if (!s->planets_set) return fail(TPM_ESTATE, "tpm_set_planets must come first");
+  if (s->np > 0 && !r_rem) return fail(TPM_EINVAL, "r_rem is NULL");
+  std::vector<double> r(s->np);
+  for (int j = 0; j < s->np; ++j) {
+    const double v = r_rem[s->perm[j]];
+    if (!(std::isfinite(v) && v > 0.0)) return fail(TPM_EINVAL, "removal radius must be > 0");
+    r[j] = v;
+  }
+  s->rrem_s = r;
+  s->rrem_set = true;
   return TPM_OK;
 }
 
@@ -763,6 +843,13 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   if (D.on && D.nres > 0 && s->d_table)
     return fail(TPM_ESTATE, "resonant angles need planet velocities, which a supplied planet "
                             "table does not carry");
+  const bool ho = s->opt.handoff_substeps > 0;
+  if (ho) {
+    if (!s->rrem_set) return fail(TPM_ESTATE, "the hand-off needs removal radii (tpm_set_removal_radii)");
+    if (s->d_table || s->d_hist)
+      return fail(TPM_ESTATE, "the hand-off needs the on-device planet map (its planet velocities)");
+    if (D.on) return fail(TPM_ESTATE, "diagnostics and the hand-off do not run together");
+  }
   // Chunk c covers steps [cb[c], cb[c + 1]) of this call: the first K0 steps
   // long, the others K, each also ending at every sample boundary (global
   // steps that are multiples of the diagnostics interval).
@@ -779,6 +866,14 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   if (!s->d_table) {
     int rc = ensure_ring(s, (int64_t)K + 1);
     if (rc) return rc;
+  }
+  hipStream_t sH = nullptr;
+  double rrem2[MAX_NP] = {};
+  if (ho) {
+    int rc = ensure_handoff(s, s->ring_rows);
+    if (rc) return rc;
+    sH = device_streams(s->opt.device).sH;
+    for (int j = 0; j < s->np; ++j) rrem2[j] = s->rrem_s[j] * s->rrem_s[j];
   }
   const SysConst S = s->sys();
   const EphConst E = s->eph();
@@ -806,11 +901,17 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
       double* srow = s->d_ring + (size_t)slot * s->ring_rows * rl;
       TPM_HIP(hipStreamWaitEvent(s->sE, s->ev_done[slot], 0));
       double* vs = s->d_vside ? s->d_vside + (size_t)slot * 6 * s->np : nullptr;
+      double* vr = nullptr;
+      if (ho) {
+        // the encounter integrator is done with this slot's rows too
+        TPM_HIP(hipStreamWaitEvent(s->sE, s->ev_hdone[slot], 0));
+        vr = s->d_vring + (size_t)slot * s->vring_rows * 3 * s->np;
+      }
       if (s->d_hist)
         TPM_HIP(launch_history_rows(s->hist(), srow, ks + 1, s->step + begin(c), dt, vs, s->sE));
       else
         TPM_HIP(launch_ephemeris_chunk(E, s->d_rj, s->d_vj, srow, ks, dt, s->step + begin(c),
-                                       s->d_flag, s->sE, vs));
+                                       s->d_flag, s->sE, vs, vr));
       TPM_HIP(hipEventRecord(s->ev_eph[slot], s->sE));
     }
     return TPM_OK;
@@ -944,6 +1045,19 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
       rc = fire(false, SIZE_MAX);
       if (rc) return rc;
     }
+    if (ho) {
+      // particles handed off in this chunk join the encounter list, which the
+      // encounter stream advances through the chunk's steps while the particle
+      // stream goes on with the next chunk
+      TPM_HIP(launch_handoff_gather(s->work[s->cur], s->d_nactive, n_grid, s->enc, step0,
+                                    s->d_snap + slot, s->sP));
+      TPM_HIP(hipEventRecord(s->ev_gath[slot], s->sP));
+      TPM_HIP(hipStreamWaitEvent(sH, s->ev_gath[slot], 0));
+      TPM_HIP(launch_encounter_chunk(S, rrem2, s->enc, s->d_snap + slot, (int)s->n, rows,
+                                     s->d_vring + (size_t)slot * s->vring_rows * 3 * s->np, ks,
+                                     dt, step0, s->opt.handoff_substeps, s->out, sH));
+      TPM_HIP(hipEventRecord(s->ev_hdone[slot], sH));
+    }
     TPM_HIP(hipEventRecord(s->ev_done[slot], s->sP));
     const bool last = (c == nchunks - 1);
     if (n_grid > 0 && (((c + 1) % R == 0) || last)) {
@@ -963,6 +1077,16 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
       s->cnt_issued++;
     }
   }
+  if (ho && nchunks > 0) {
+    // the encounter list's survivors rejoin the working set (every entry is
+    // now at the run's last step); the list ends the call empty
+    TPM_HIP(hipStreamWaitEvent(s->sP, s->ev_hdone[(nchunks - 1) % NSLOT], 0));
+    TPM_HIP(hipMemcpyAsync(s->h_pin + 18, s->enc.count, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           s->sP));
+    TPM_HIP(launch_handoff_merge(s->enc, (int)s->n, s->work[s->cur], s->d_nactive, s->sP));
+    TPM_HIP(hipMemcpyAsync(s->h_pin + 19, s->d_nactive, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           s->sP));
+  }
   TPM_HIP(hipEventRecord(s->t1P, s->sP));
   TPM_HIP(hipEventRecord(s->t1E, s->sE));
   TPM_HIP(hipStreamSynchronize(s->sE));
@@ -972,6 +1096,11 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
     if (rc) return rc;
     rc = fire(true, SIZE_MAX);
     if (rc) return rc;
+  }
+  s->stats.handoffs = 0;
+  if (ho && nchunks > 0) {
+    s->stats.handoffs = s->h_pin[18];
+    s->n_active = s->h_pin[19];
   }
   {
     int32_t qerr = 0;
@@ -1281,6 +1410,7 @@ int tpm_set_state(tpm_sim* s, const void* buf, int64_t size) {
   TPM_HIP(hipMemcpy(s->d_flag, &h.flag, sizeof(int64_t), hipMemcpyHostToDevice));
   s->step = h.step;
   s->planets_set = true;
+  s->rrem_set = false;
   return load_particles(s, n, r.data(), v.data(), step.data(), reason.data(), planet.data());
 }
 
@@ -1467,6 +1597,8 @@ int tpm_ad_forward(tpm_sim* s, int64_t n, const double* d_r0, const double* d_v0
     return fail(TPM_EINVAL, "bad sizes");
   if (n > 0 && (!d_r0 || !d_v0 || !d_rT || !d_vT)) return fail(TPM_EINVAL, "NULL array");
   if (!std::isfinite(dt) || dt == 0.0) return fail(TPM_EINVAL, "dt must be finite and non-zero");
+  if (s->opt.handoff_substeps > 0)
+    return fail(TPM_ESTATE, "derivatives of the close-encounter hand-off are not available");
   TPM_HIP(hipSetDevice(s->opt.device));
   std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   hipStream_t st = (hipStream_t)stream;
@@ -1735,6 +1867,8 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
   tpm_options o;
   tpm_default_options(&o);
   if (opt_in) o = *opt_in;
+  if (o.handoff_substeps != 0)
+    return fail(TPM_EINVAL, "the close-encounter hand-off does not run in the many-system call");
   if (o.kepler_iters <= 0) o.kepler_iters = 5;
   if (o.chunk_steps < 0 || o.chunk_steps > (1 << 30)) return fail(TPM_EINVAL, "chunk_steps out of range");
   if (o.block_threads < 0 || o.block_threads % 64 || o.block_threads > 256)

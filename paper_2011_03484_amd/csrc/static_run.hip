@@ -169,6 +169,8 @@ extern "C" int tpm_integrate_static(const tpm_options* opt_in, double mu0, int32
   if (opt_in) o = *opt_in;
   if (o.kepler_iters <= 0) o.kepler_iters = 5;
   if (o.kepler_iters > 64) return sfail(TPM_EINVAL, "kepler_iters > 64");
+  if (o.handoff_substeps != 0)
+    return sfail(TPM_EINVAL, "the close-encounter hand-off does not run without allocation");
   if (o.chunk_steps < 0 || o.resync_chunks < 0 || o.block_threads < 0 || o.sub_chunks < 0 ||
       o.waves_per_simd < 0)
     return sfail(TPM_EINVAL, "negative option");
