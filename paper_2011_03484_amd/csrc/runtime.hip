@@ -2157,23 +2157,53 @@ extern "C" int tpm_batch_integrate(int32_t nsys, const double* mu0, const int32_
         for (auto& c : cands) c.block = o.block_threads;
       if (cands.empty()) cands.push_back(TuneChoice{choice.block, choice.chunk, choice.sub_chunks,
                                                     choice.waves_per_simd, 0});
-      double best = 1e300, best_chunk_ms = 0.0;
-      for (const auto& cand : cands) {
+      // time per step of `chunks` chunks of a candidate from the initial
+      // state (the planet maps of the first chunk included)
+      auto trial = [&](const TuneChoice& cand, int64_t chunks, double& per_step,
+                       double& chunk_ms) -> int {
         int rc = reset_run();
         if (rc) return rc;
         TPM_HIP(hipEventRecord(ctx->t0P, ctx->sP));
-        rc = enqueue_run(1, cand, cur);
+        rc = enqueue_run(chunks, cand, cur);
         if (rc) return rc;
         TPM_HIP(hipEventRecord(ctx->t1P, ctx->sP));
         TPM_HIP(hipEventSynchronize(ctx->t1P));
         float ms = 0.f;
         TPM_HIP(hipEventElapsedTime(&ms, ctx->t0P, ctx->t1P));
-        const double per_step = ms / (double)std::min<int64_t>(cand.chunk, nsteps);
-        if (per_step < best) {
-          best = per_step;
-          best_chunk_ms = ms;
+        const int64_t steps = std::min<int64_t>(chunks * cand.chunk, nsteps);
+        per_step = ms / (double)steps;
+        chunk_ms = ms / (double)((steps + cand.chunk - 1) / cand.chunk);
+        return TPM_OK;
+      };
+      // a screen of one chunk per candidate, then the best four again over
+      // up to three chunks with a compaction after each (single-chunk times
+      // differ by a few percent between neighbouring shapes, about the noise
+      // of one launch)
+      std::vector<std::pair<double, size_t>> screen;
+      std::vector<double> chunk_ms_of(cands.size(), 0.0);
+      for (size_t k = 0; k < cands.size(); ++k) {
+        double ps = 0.0;
+        int rc = trial(cands[k], 1, ps, chunk_ms_of[k]);
+        if (rc) return rc;
+        screen.emplace_back(ps, k);
+      }
+      std::sort(screen.begin(), screen.end());
+      double best = 1e300, best_chunk_ms = 0.0;
+      const size_t nfinal = std::min<size_t>(screen.size(), 4);
+      for (size_t f = 0; f < nfinal; ++f) {
+        TuneChoice cand = cands[screen[f].second];
+        double ps = screen[f].first, cms = chunk_ms_of[screen[f].second];
+        const int64_t nch = std::min<int64_t>(3, (nsteps + cand.chunk - 1) / cand.chunk);
+        if (nfinal > 1 && nch > 1) {
+          cand.resync = 1;
+          int rc = trial(cand, nch, ps, cms);
+          if (rc) return rc;
+        }
+        if (ps < best) {
+          best = ps;
+          best_chunk_ms = cms;
           const int keep_r = choice.resync;
-          choice = cand;
+          choice = cands[screen[f].second];
           choice.resync = keep_r;
         }
       }

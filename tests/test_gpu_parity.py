@@ -353,18 +353,34 @@ def test_removal_special_cases(tpm, orc):
 
 
 def test_kepler_failure_removal(tpm, orc):
+    """Kepler failures against the oracle (no planets): an e = 0.99 orbit,
+    whose five-step solve misses the 1e-13 threshold at a step of 0.05
+    radians of mean anomaly, and an unbound orbit are removed as KEPLER at
+    step 0 with their initial states; an e = 0.5 orbit on the same step stays
+    active and matches the oracle's state."""
     mu0 = W.MU_SUN
-    a, e = 10.0, 0.99
-    rr, vv = W.elements_to_cartesian(mu0, np.array([a]), np.array([e]), np.zeros(1), np.zeros(1),
-                                     np.zeros(1), np.array([0.0]))
-    dt = 0.05 / math.sqrt(mu0 / a ** 3)
+    a = np.array([10.0, 10.0, 10.0])
+    e = np.array([0.99, 0.5, 0.0])
+    rr, vv = W.elements_to_cartesian(mu0, a, e, np.zeros(3), np.zeros(3), np.zeros(3),
+                                     np.array([0.0, 0.3, 1.0]))
+    vv[2] *= 1.5                                   # circular speed x 1.5: unbound
+    dt = 0.05 / math.sqrt(mu0 / a[0] ** 3)
+    T = 3
     s = tpm.Simulation()
     s.set_central(mu0)
     s.set_planets(np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0))
     s.set_particles(rr, vv)
-    s.integrate(3, dt)
+    s.integrate(T, dt)
     g = s.particles()
-    assert g["reason"][0] == tpm.KEPLER and g["deact_step"][0] == 0
+    res = orc.particles(mu0, np.zeros(0), np.zeros(0), 0.0, np.zeros((T + 1, 3)), dt, rr, vv, T)
+    assert list(res.reason) == [orc.KEPLER, orc.ACTIVE, orc.KEPLER]
+    assert np.array_equal(g["reason"], res.reason)
+    assert np.array_equal(g["deact_step"], res.deact_step)
+    for k in (0, 2):
+        assert np.array_equal(g["r"][k], rr[k]) and np.array_equal(g["v"][k], vv[k])
+        assert np.array_equal(res.r[k], rr[k]) and np.array_equal(res.v[k], vv[k])
+    err = np.linalg.norm(g["r"][1] - res.r[1]) / np.linalg.norm(res.r[1])
+    assert err <= POS_TOL, err
 
 
 def test_planet_close_pair_reported(tpm, orc):
