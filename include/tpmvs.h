@@ -72,7 +72,7 @@ typedef struct {
   int32_t sub_chunks;     /* work items per tile in a full chunk (dynamic load balance); a
                              shorter chunk gets proportionally fewer items of the same
                              length; 0 = 64 */
-  int32_t waves_per_simd; /* particle wavefronts launched per SIMD (upper bound); 0 = 2 */
+  int32_t waves_per_simd; /* particle wavefronts launched per SIMD (upper bound); 0 = 1 */
   double r_escape;        /* remove when |r| > r_escape; <= 0 disables                */
   double kepler_ftol;     /* Kepler-failure threshold on |F(x_k)|; 0 = 1e-13         */
   int32_t device;         /* HIP device ordinal                                      */
@@ -312,8 +312,9 @@ int tpm_set_planet_history(tpm_sim* sim, int64_t nrec, const double* t, const do
  * replaces it).
  * tpm_ad_backward: vector-Jacobian product (dL/dr_0, dL/dv_0) from
  * (dL/dr_T, dL/dv_T): each segment of ckpt_every steps is recomputed from its
- * checkpoint, its states written to a tape of ckpt_every x 48 n bytes, and swept
- * backwards.
+ * checkpoint into a tape of ckpt_every x 96 n bytes (per particle and step: the
+ * state, the opening kick's acceleration and the drift's Kepler root), and
+ * swept backwards; the library holds two such tapes.
  * tpm_ad_tangent: Jacobian-vector product (d r_T, d v_T) from (d r_0, d v_0)
  * for the run of the last forward.
  * TPM_ESTATE if no forward has been run. */

@@ -4,10 +4,14 @@
 // blocks [6][n] (x, y, z, vx, vy, vz).  The planet table of the whole run is
 // resident in HBM (row k = step k), so every segment can be recomputed.
 //
-//  * ad_segment   - steps [s0, s1) from a checkpoint; optionally writes the
-//                   state at the start of every step to a tape [s1-s0][6][n].
+//  * ad_segment   - steps [s0, s1) from a checkpoint; optionally writes a
+//                   tape [s1-s0][AD_TAPE_FIELDS][n]: per step carried out,
+//                   the state at its start, its opening acceleration and its
+//                   Kepler root (x, sin x, cos x - 1).
 //  * ad_reverse   - walks a segment's tape backwards applying the transposed
-//                   step Jacobian to the adjoint vector kept in registers.
+//                   step Jacobian to the adjoint vector kept in registers; the
+//                   taped values spare it the Kepler solve and the opening
+//                   acceleration, and give the same bits as recomputing them.
 //  * ad_tangent   - carries (state, tangent) forward through [s0, s1).
 #include "ad.hpp"
 #include "ad_internal.h"
@@ -42,19 +46,21 @@ static ADArgs<NP> make_args(const SysConst& S, double dt, int64_t n, int s0, int
 
 // One step of the map from (r, v) at step s (rows s, s+1), with the checks at
 // its end.  Returns the new removal reason (ST_ACTIVE if none).
-template <int NP>
-TPM_DEV int32_t ad_step(const ADArgs<NP>& A, const double* __restrict__ table, int s, double r[3],
-                        double v[3], double acc[3], int32_t& planet) {
-  constexpr int ROW = 3 * NP + 3;
+// row1: row s + 1 (a pointer, or a Row held in registers); xsm receives the
+// drift's Kepler root, its sin and cos - 1.
+template <int NP, typename RowT>
+TPM_DEV int32_t ad_step(const ADArgs<NP>& A, const RowT& row1, double r[3], double v[3],
+                        double acc[3], int32_t& planet, double xsm[3]) {
   const double h = 0.5 * A.dt;
   DriftVals D;
   double nr[3], nv[3];
   drift_vals(A.K, A.dt, A.kiters, A.ftol, r[0], r[1], r[2], fma_(h, acc[0], v[0]),
              fma_(h, acc[1], v[1]), fma_(h, acc[2], v[2]), D, nr[0], nr[1], nr[2], nv[0], nv[1],
              nv[2]);
+  xsm[0] = D.x; xsm[1] = D.s; xsm[2] = D.m;
   if (!D.ok) return ST_KEPLER;
   double b[3];
-  int hit = accel<NP>(table + (size_t)(s + 1) * ROW, A.P, nr[0], nr[1], nr[2], b[0], b[1], b[2]);
+  int hit = accel<NP>(row1, A.P, nr[0], nr[1], nr[2], b[0], b[1], b[2]);
   for (int k = 0; k < 3; ++k) {
     r[k] = nr[k];
     acc[k] = b[k];
@@ -95,17 +101,27 @@ ad_segment(ADArgs<NP> A, const double* __restrict__ table, const double* __restr
     if (hit >= 0) { why = ST_ENCOUNTER; pl = hit; ds = A.s0; }
     else if (fma_(r[0], r[0], fma_(r[1], r[1], r[2] * r[2])) > A.rmax2) { why = ST_ESCAPE; ds = A.s0; }
   }
+  // the row that ends step s is fetched into registers during step s - 1
+  const int zero = opaque_zero_vgpr();
+  Row<NP> R1, Rn;
+  if (A.s0 < A.s1) load_row<NP>(R1, table + (size_t)(A.s0 + 1) * ROW, zero);
   for (int s = A.s0; s < A.s1; ++s) {
-    if (tape) {
-      double* t = tape + (size_t)(s - A.s0) * 6 * n;
-      t[i] = r[0]; t[n + i] = r[1]; t[2 * n + i] = r[2];
-      t[3 * n + i] = v[0]; t[4 * n + i] = v[1]; t[5 * n + i] = v[2];
-    }
+    if (s + 1 < A.s1) load_row<NP>(Rn, table + (size_t)(s + 2) * ROW, zero);
+    const Row<NP> Rs = R1;
+    R1 = Rn;
     if (mode == 2 ? (s >= stop) : (why != ST_ACTIVE)) continue;
     double r1[3] = {r[0], r[1], r[2]}, v1[3] = {v[0], v[1], v[2]}, a1[3] = {acc[0], acc[1], acc[2]};
     int32_t p1 = -1;
-    int32_t w = ad_step<NP>(A, table, s, r1, v1, a1, p1);
+    double xsm[3];
+    int32_t w = ad_step<NP>(A, Rs.v, r1, v1, a1, p1, xsm);
     if (w == ST_KEPLER) { why = w; ds = s; continue; }
+    if (tape) {
+      double* t = tape + (size_t)(s - A.s0) * AD_TAPE_FIELDS * n + i;
+      const double f[AD_TAPE_FIELDS] = {r[0], r[1], r[2], v[0], v[1], v[2], acc[0], acc[1], acc[2],
+                                        xsm[0], xsm[1], xsm[2]};
+#pragma unroll
+      for (int k = 0; k < AD_TAPE_FIELDS; ++k) t[(size_t)k * n] = f[k];
+    }
     for (int k = 0; k < 3; ++k) { r[k] = r1[k]; v[k] = v1[k]; acc[k] = a1[k]; }
     if (w != ST_ACTIVE) { why = w; pl = p1; ds = s + 1; }
   }
@@ -135,19 +151,35 @@ ad_reverse(ADArgs<NP> A, const double* __restrict__ table, const double* __restr
   // steps s with s < ds (or all steps if never removed) were carried out
   int s_top = A.s1;
   if (ds >= 0 && ds < (int64_t)s_top) s_top = (int)(ds > A.s0 ? ds : A.s0);
+  // the tape entry of step s is fetched during step s + 1 (its loads do not
+  // depend on the adjoint)
+  auto fetch = [&](int s, double (&f)[AD_TAPE_FIELDS]) {
+    const double* t = tape + (size_t)(s - A.s0) * AD_TAPE_FIELDS * n + i;
+#pragma unroll
+    for (int k = 0; k < AD_TAPE_FIELDS; ++k) f[k] = t[(size_t)k * n];
+  };
+  // and so is row s - 1 (rows s and s + 1 are in registers already)
+  double cur[AD_TAPE_FIELDS], nxt[AD_TAPE_FIELDS];
+  Row<NP> R0, R1, Rn;
+  if (s_top - 1 >= A.s0) {
+    fetch(s_top - 1, cur);
+    load_row<NP>(R0, table + (size_t)(s_top - 1) * ROW, 0);
+    load_row<NP>(R1, table + (size_t)s_top * ROW, 0);
+  }
   for (int s = s_top - 1; s >= A.s0; --s) {
-    const double* t = tape + (size_t)(s - A.s0) * 6 * n;
-    double r[3] = {t[i], t[n + i], t[2 * n + i]};
-    double v[3] = {t[3 * n + i], t[4 * n + i], t[5 * n + i]};
-    const double* row0 = table + (size_t)s * ROW;
-    const double* row1 = table + (size_t)(s + 1) * ROW;
-    double a0[3];
-    accel<NP>(row0, A.P, r[0], r[1], r[2], a0[0], a0[1], a0[2]);
-    double vh[3] = {fma_(h, a0[0], v[0]), fma_(h, a0[1], v[1]), fma_(h, a0[2], v[2])};
+    if (s - 1 >= A.s0) {
+      fetch(s - 1, nxt);
+      load_row<NP>(Rn, table + (size_t)(s - 1) * ROW, 0);
+    }
+    double r[3] = {cur[0], cur[1], cur[2]};
+    double v[3] = {cur[3], cur[4], cur[5]};
+    const auto& row0 = R0.v;
+    const auto& row1 = R1.v;
+    double vh[3] = {fma_(h, cur[6], v[0]), fma_(h, cur[7], v[1]), fma_(h, cur[8], v[2])};
     DriftVals D;
     double nr[3], nv[3];
-    drift_vals(A.K, A.dt, A.kiters, A.ftol, r[0], r[1], r[2], vh[0], vh[1], vh[2], D, nr[0], nr[1],
-               nr[2], nv[0], nv[1], nv[2]);
+    drift_vals_t<true>(A.K, A.dt, A.kiters, A.ftol, r[0], r[1], r[2], vh[0], vh[1], vh[2], D, nr[0],
+                       nr[1], nr[2], nv[0], nv[1], nv[2], cur[9], cur[10], cur[11]);
     // closing kick: v_{s+1} = v' + h a(r_{s+1})
     double Al[3];
     accel_jac<NP>(row1, A.P, nr, lv, Al);
@@ -161,6 +193,10 @@ ad_reverse(ADArgs<NP> A, const double* __restrict__ table, const double* __restr
       lr[k] = lr0[k] + h * Al[k];
       lv[k] = lvh[k];
     }
+#pragma unroll
+    for (int k = 0; k < AD_TAPE_FIELDS; ++k) cur[k] = nxt[k];
+    R1 = R0;
+    R0 = Rn;
   }
   lam[i] = lr[0]; lam[n + i] = lr[1]; lam[2 * n + i] = lr[2];
   lam[3 * n + i] = lv[0]; lam[4 * n + i] = lv[1]; lam[5 * n + i] = lv[2];

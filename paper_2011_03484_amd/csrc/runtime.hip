@@ -217,7 +217,7 @@ struct tpm_sim {
     double dt = 0.0;
     double* table = nullptr;      // [nsteps+1][3np+3]
     double* ckpts = nullptr;      // [nseg+1][6][n]
-    double* tape = nullptr;       // [2][ckpt][6][n]: two segments' tapes (see tpm_ad_backward)
+    double* tape = nullptr;       // [2][ckpt][AD_TAPE_FIELDS][n]: two segments' tapes (see tpm_ad_backward)
     double* work = nullptr;       // [2][6][n]
     int64_t* dstep = nullptr;
     int32_t* reason = nullptr;
@@ -584,7 +584,7 @@ int tpm_create(const tpm_options* opt, tpm_sim** out) {
       o.waves_per_simd < 0)
     return fail(TPM_EINVAL, "negative option");
   if (o.sub_chunks == 0) o.sub_chunks = 64;
-  if (o.waves_per_simd == 0) o.waves_per_simd = 2;
+  if (o.waves_per_simd == 0) o.waves_per_simd = 1;
   if (o.waves_per_simd > 8) return fail(TPM_EINVAL, "waves_per_simd > 8");
   if (o.chunk_steps == 0) o.chunk_steps = 8192;
   if (o.chunk_steps > (1 << 30)) return fail(TPM_EINVAL, "chunk_steps > 2^30");
@@ -1693,13 +1693,13 @@ int tpm_ad_backward(tpm_sim* s, const double* d_gRT, const double* d_gVT, double
   TPM_HIP(hipSetDevice(s->opt.device));
   hipStream_t st = (hipStream_t)stream;
   {
-    int rc = grow(A.tape, A.cap_tape, (size_t)2 * A.ckpt * 6 * n);
+    int rc = grow(A.tape, A.cap_tape, (size_t)2 * A.ckpt * AD_TAPE_FIELDS * n);
     if (rc) return rc;
   }
   std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   const SysConst S = s->sys();
   double* lam = A.work;
-  double* tape[2] = {A.tape, A.tape + (size_t)A.ckpt * 6 * n};
+  double* tape[2] = {A.tape, A.tape + (size_t)A.ckpt * AD_TAPE_FIELDS * n};
   // Segment k's states are recomputed from its checkpoint into tape k % 2 on
   // the library's particle stream while the caller's stream sweeps segment
   // k + 1 backwards through the other tape: the recomputation does not depend

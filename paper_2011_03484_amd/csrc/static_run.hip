@@ -182,7 +182,7 @@ extern "C" int tpm_integrate_static(const tpm_options* opt_in, double mu0, int32
   if (o.block_threads % 64 || o.block_threads > 256)
     return sfail(TPM_EINVAL, "block_threads must be 64, 128, 192 or 256");
   if (o.sub_chunks == 0) o.sub_chunks = 64;
-  if (o.waves_per_simd == 0) o.waves_per_simd = 2;
+  if (o.waves_per_simd == 0) o.waves_per_simd = 1;
   if (o.waves_per_simd > 8) return sfail(TPM_EINVAL, "waves_per_simd > 8");
   if (!(o.kepler_ftol > 0.0)) o.kepler_ftol = 1e-13;
   if (!std::isfinite(o.r_escape)) return sfail(TPM_EINVAL, "r_escape not finite");
