@@ -192,6 +192,28 @@ def test_handoff_split_calls_are_bitwise(tpm):
     assert a.stats()["step"] == b.stats()["step"] == 3000
 
 
+def test_handoff_does_not_depend_on_tuning(tpm):
+    """The hand-off run is the same bit for bit under other work-queue shapes,
+    chunk lengths and compaction intervals (the chunks decide when the
+    encounter list is advanced, the list's lanes nothing else), with the
+    eccentricity-binned order and with the universal drift."""
+    w = _workload(4096, 86)
+    rrem = np.full(w.np_, 0.05)
+    print(f"[tuning] n={w.n}", flush=True)
+    base = None
+    for opts in ({}, {"chunk_steps": 200, "resync_chunks": 3, "sub_chunks": 4, "waves_per_simd": 2},
+                 {"chunk_steps": 1000, "block_threads": 256, "sub_chunks": 16, "sort_by_e": True}):
+        s = _sim(tpm, w, w.rcrit, rrem, handoff_substeps=8, universal_drift=True, **opts)
+        s.integrate(2500, w.dt)
+        p = s.particles()
+        if base is None:
+            base = p
+            assert s.stats()["handoffs"] > 100
+            continue
+        for k in KEYS:
+            assert np.array_equal(p[k], base[k]), (opts, k)
+
+
 def test_handoff_full_size_sampled(tpm, orc):
     """At the 100,000-particle giant-planet shape with the default chunking,
     16 substeps: every particle the GPU removed within a removal radius plus
