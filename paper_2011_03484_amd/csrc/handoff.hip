@@ -69,9 +69,9 @@ struct EncArgs {
 };
 
 // Lowest planet index with |r - r_j|^2 < rad2_j in a table row, or -1.
-template <int NP>
-TPM_DEV int within(const double* __restrict__ row, const double (&rad2)[NP > 0 ? NP : 1],
-                   double x, double y, double z) {
+template <int NP, typename RowT>
+TPM_DEV int within(const RowT& row, const double (&rad2)[NP > 0 ? NP : 1], double x, double y,
+                   double z) {
   int hit = -1;
 #pragma unroll
   for (int j = NP - 1; j >= 0; --j) {
@@ -84,9 +84,9 @@ TPM_DEV int within(const double* __restrict__ row, const double (&rad2)[NP > 0 ?
 // Acceleration at fraction tau of the step from row a to row b (planet
 // velocities va, vb per row) with the planets on their Hermite interpolants;
 // returns the lowest planet index within its removal radius, or -1.
-template <int NP>
-TPM_DEV int interp_accel(const EncArgs<NP>& A, double tau, const double* __restrict__ ra,
-                         const double* __restrict__ va, const double* __restrict__ rb,
+template <int NP, typename RowT>
+TPM_DEV int interp_accel(const EncArgs<NP>& A, double tau, const RowT& ra,
+                         const double* __restrict__ va, const RowT& rb,
                          const double* __restrict__ vb, double x, double y, double z, double& ax,
                          double& ay, double& az) {
   const double t2 = tau * tau, t3 = t2 * tau;
@@ -131,11 +131,11 @@ TPM_DEV int interp_accel(const EncArgs<NP>& A, double tau, const double* __restr
 // The drift of a step or substep: the fixed-count elliptic solve, retried in
 // universal variables where it is refused and the option is on (the same
 // arithmetic as the particle kernel's step).
-template <int NP>
+template <int NP, int KIT>
 TPM_DEV bool enc_drift(const EncArgs<NP>& A, double dt, double& x, double& y, double& z,
                        double& vx, double& vy, double& vz) {
   double nx = x, ny = y, nz = z, nvx = vx, nvy = vy, nvz = vz;
-  bool ok = drift_fixed(A.K, dt, A.kiters, A.ftol, nx, ny, nz, nvx, nvy, nvz);
+  bool ok = drift_fixed(A.K, dt, KIT > 0 ? KIT : A.kiters, A.ftol, nx, ny, nz, nvx, nvy, nvz);
   if (!ok && A.universal) {
     nx = x; ny = y; nz = z; nvx = vx; nvy = vy; nvz = vz;
     ok = drift_universal(A.K.mu, dt, nx, ny, nz, nvx, nvy, nvz);
@@ -153,8 +153,11 @@ TPM_DEV bool enc_drift(const EncArgs<NP>& A, double dt, double& x, double& y, do
 // iterations, not M per step whenever any lane is in an encounter.  The
 // acceleration at the end of a plain step or of a step's last substep comes
 // from the row itself (exactly the main kernel's arithmetic), inside a step
-// from the interpolated planets.
-template <int NP>
+// from the interpolated planets.  The rows at the two ends of a lane's step
+// stay in registers through its substeps, and the next step's closing row is
+// fetched at the step's start.  KIT > 0 fixes the Newton count at compile
+// time, as in the particle kernel.
+template <int NP, int KIT>
 __global__ void __launch_bounds__(64)
 encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
                 const double* __restrict__ rows, const double* __restrict__ vrows, Out out) {
@@ -177,8 +180,10 @@ encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
   };
   // checks at the first boundary (the particle kernel handed the particle off
   // there before testing the removal radius or escape)
+  Row<NP> Ra, Rb, Rn;       // rows s, s + 1 and (fetched ahead) s + 2
+  load_row<NP>(Ra, rows + (size_t)s * ROW, 0);
   double ax, ay, az;
-  int hit = accel<NP>(rows + (size_t)s * ROW, A.Prem, x, y, z, ax, ay, az);
+  int hit = accel<NP>(Ra.v, A.Prem, x, y, z, ax, ay, az);
   if (hit >= 0) {
     remove(ST_ENCOUNTER, A.step0 + s, hit, x, y, z, vx, vy, vz);
     return;
@@ -187,29 +192,31 @@ encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
     remove(ST_ESCAPE, A.step0 + s, -1, x, y, z, vx, vy, vz);
     return;
   }
+  if (s < A.nsteps) load_row<NP>(Rb, rows + (size_t)(s + 1) * ROW, 0);
   const double hM = A.dt / A.M;
   int m = 0, Ml = 1;        // substep within the current step, substeps of this step
   for (;;) {
     if (s >= A.nsteps) break;
-    const double* ra = rows + (size_t)s * ROW;
-    const double* rb = ra + ROW;
-    // the mode of a step is decided at its first boundary
-    if (m == 0) Ml = within<NP>(ra, A.renc2, x, y, z) >= 0 ? A.M : 1;
+    if (m == 0) {
+      // the mode of a step is decided at its first boundary
+      Ml = within<NP>(Ra.v, A.renc2, x, y, z) >= 0 ? A.M : 1;
+      if (s + 1 < A.nsteps) load_row<NP>(Rn, rows + (size_t)(s + 2) * ROW, 0);
+    }
     const double h = Ml == 1 ? A.dt : hM;
     const double hh = 0.5 * h;
     double nx = x, ny = y, nz = z;
     double nvx = fma_(hh, ax, vx), nvy = fma_(hh, ay, vy), nvz = fma_(hh, az, vz);
-    if (!enc_drift<NP>(A, h, nx, ny, nz, nvx, nvy, nvz)) {
+    if (!enc_drift<NP, KIT>(A, h, nx, ny, nz, nvx, nvy, nvz)) {
       // the state at the start of the failing (sub)step
       remove(ST_KEPLER, A.step0 + s, -1, x, y, z, vx, vy, vz);
       return;
     }
     if (m + 1 == Ml) {
-      hit = accel<NP>(rb, A.Prem, nx, ny, nz, ax, ay, az);
+      hit = accel<NP>(Rb.v, A.Prem, nx, ny, nz, ax, ay, az);
     } else {
       const double* va = vrows + (size_t)s * 3 * NP;
-      hit = interp_accel<NP>(A, (double)(m + 1) / Ml, ra, va, rb, va + 3 * NP, nx, ny, nz, ax, ay,
-                             az);
+      hit = interp_accel<NP>(A, (double)(m + 1) / Ml, Ra.v, va, Rb.v, va + 3 * NP, nx, ny, nz, ax,
+                             ay, az);
     }
     x = nx; y = ny; z = nz;
     vx = fma_(hh, ax, nvx); vy = fma_(hh, ay, nvy); vz = fma_(hh, az, nvz);
@@ -221,6 +228,8 @@ encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
     if (++m == Ml) {
       m = 0;
       ++s;
+      Ra = Rb;
+      Rb = Rn;
       if (fma_(x, x, fma_(y, y, z * z)) > A.rmax2) {
         remove(ST_ESCAPE, A.step0 + s, -1, x, y, z, vx, vy, vz);
         return;
@@ -251,8 +260,12 @@ static hipError_t enc_np(const SysConst& S, const double* rrem2, EncList L, cons
   A.M = M;
   A.universal = S.universal;
   A.step0 = step0;
-  hipLaunchKernelGGL(encounter_chunk<NP>, dim3((n_upper + 63) / 64), dim3(64), 0, st, A, L, snap,
-                     rows, vrows, out);
+  if (S.kiters == 5)
+    hipLaunchKernelGGL((encounter_chunk<NP, 5>), dim3((n_upper + 63) / 64), dim3(64), 0, st, A, L,
+                       snap, rows, vrows, out);
+  else
+    hipLaunchKernelGGL((encounter_chunk<NP, 0>), dim3((n_upper + 63) / 64), dim3(64), 0, st, A, L,
+                       snap, rows, vrows, out);
   return hipGetLastError();
 }
 
