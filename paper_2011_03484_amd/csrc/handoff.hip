@@ -154,9 +154,9 @@ TPM_DEV bool enc_drift(const EncArgs<NP>& A, double dt, double& x, double& y, do
 // acceleration at the end of a plain step or of a step's last substep comes
 // from the row itself (exactly the main kernel's arithmetic), inside a step
 // from the interpolated planets.  The rows at the two ends of a lane's step
-// stay in registers through its substeps, and the next step's closing row is
-// fetched at the step's start.  KIT > 0 fixes the Newton count at compile
-// time, as in the particle kernel.
+// stay in registers through its substeps, and each micro-step fetches the
+// next one's closing row.  KIT > 0 fixes the Newton count at compile time, as
+// in the particle kernel.
 template <int NP, int KIT>
 __global__ void __launch_bounds__(64)
 encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
@@ -180,7 +180,7 @@ encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
   };
   // checks at the first boundary (the particle kernel handed the particle off
   // there before testing the removal radius or escape)
-  Row<NP> Ra, Rb, Rn;       // rows s, s + 1 and (fetched ahead) s + 2
+  Row<NP> Ra, Rb, Rn;       // rows s, s + 1, and the next micro-step's closing row
   load_row<NP>(Ra, rows + (size_t)s * ROW, 0);
   double ax, ay, az;
   int hit = accel<NP>(Ra.v, A.Prem, x, y, z, ax, ay, az);
@@ -197,11 +197,13 @@ encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
   int m = 0, Ml = 1;        // substep within the current step, substeps of this step
   for (;;) {
     if (s >= A.nsteps) break;
-    if (m == 0) {
-      // the mode of a step is decided at its first boundary
-      Ml = within<NP>(Ra.v, A.renc2, x, y, z) >= 0 ? A.M : 1;
-      if (s + 1 < A.nsteps) load_row<NP>(Rn, rows + (size_t)(s + 2) * ROW, 0);
-    }
+    // the mode of a step is decided at its first boundary
+    if (m == 0) Ml = within<NP>(Ra.v, A.renc2, x, y, z) >= 0 ? A.M : 1;
+    // the closing row of the next micro-step, fetched by every lane (row
+    // s + 2 if this micro-step ends the step, else row s + 1 again) so that
+    // the loads are not conditional and their latency hides behind the drift
+    const bool ends = m + 1 == Ml;
+    load_row<NP>(Rn, rows + (size_t)min(s + (ends ? 2 : 1), A.nsteps) * ROW, 0);
     const double h = Ml == 1 ? A.dt : hM;
     const double hh = 0.5 * h;
     double nx = x, ny = y, nz = z;
@@ -211,7 +213,7 @@ encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
       remove(ST_KEPLER, A.step0 + s, -1, x, y, z, vx, vy, vz);
       return;
     }
-    if (m + 1 == Ml) {
+    if (ends) {
       hit = accel<NP>(Rb.v, A.Prem, nx, ny, nz, ax, ay, az);
     } else {
       const double* va = vrows + (size_t)s * 3 * NP;
@@ -225,11 +227,14 @@ encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
       remove(ST_ENCOUNTER, A.step0 + s + 1, hit, x, y, z, vx, vy, vz);
       return;
     }
+#pragma unroll
+    for (int k = 0; k < 3 * NP + 3; ++k) {
+      Ra.v[k] = ends ? Rb.v[k] : Ra.v[k];
+      Rb.v[k] = Rn.v[k];
+    }
     if (++m == Ml) {
       m = 0;
       ++s;
-      Ra = Rb;
-      Rb = Rn;
       if (fma_(x, x, fma_(y, y, z * z)) > A.rmax2) {
         remove(ST_ESCAPE, A.step0 + s, -1, x, y, z, vx, vy, vz);
         return;
