@@ -72,7 +72,9 @@ typedef struct {
   int32_t sub_chunks;     /* work items per tile in a full chunk (dynamic load balance); a
                              shorter chunk gets proportionally fewer items of the same
                              length; 0 = 64 */
-  int32_t waves_per_simd; /* particle wavefronts launched per SIMD (upper bound); 0 = 1 */
+  int32_t waves_per_simd; /* particle wavefronts launched per SIMD (upper bound); 0 = as many
+                             as the working set's tiles fill on every SIMD alike, 1..4,
+                             chosen per launch */
   double r_escape;        /* remove when |r| > r_escape; <= 0 disables                */
   double kepler_ftol;     /* Kepler-failure threshold on |F(x_k)|; 0 = 1e-13         */
   int32_t device;         /* HIP device ordinal                                      */

@@ -5,6 +5,16 @@
 
 namespace tpm {
 
+// Wavefronts per SIMD for a particle launch when the caller leaves it to the
+// library: as many as the working set's tiles fill on every SIMD alike (at
+// least one, at most four).  An uneven split, some SIMDs holding one more
+// wavefront than others, lets the tiles on the shared SIMDs fall behind.
+inline int auto_waves_per_simd(int ntiles, int ncu) {
+  const int per = ntiles / (4 * (ncu > 0 ? ncu : 1));
+  return per < 1 ? 1 : (per > 4 ? 4 : per);
+}
+
+
 constexpr int MAX_NP = 8;
 
 // Records msg as this thread's last error (tpm_last_error) and returns code.

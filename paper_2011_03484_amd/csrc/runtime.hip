@@ -204,6 +204,7 @@ struct tpm_sim {
   double hist_dt = 0.0;                  // dt of the last integrate (the current time)
   int64_t step = 0;
   int ncu = 0;                           // compute units of the device
+  int last_wps = 0;                      // wavefronts per SIMD of the last particle launch
   unsigned long long* d_qctr = nullptr;  // work-queue item counter
   uint32_t* d_progress = nullptr;        // per-tile progress counters
   int32_t* d_qerr = nullptr;             // work-queue error flag
@@ -584,7 +585,6 @@ int tpm_create(const tpm_options* opt, tpm_sim** out) {
       o.waves_per_simd < 0)
     return fail(TPM_EINVAL, "negative option");
   if (o.sub_chunks == 0) o.sub_chunks = 64;
-  if (o.waves_per_simd == 0) o.waves_per_simd = 1;
   if (o.waves_per_simd > 8) return fail(TPM_EINVAL, "waves_per_simd > 8");
   if (o.chunk_steps == 0) o.chunk_steps = 8192;
   if (o.chunk_steps > (1 << 30)) return fail(TPM_EINVAL, "chunk_steps > 2^30");
@@ -1025,7 +1025,10 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
       const int item = std::max(1, K / std::max(1, s->opt.sub_chunks));
       QL.nsub = std::max(1, std::min(s->opt.sub_chunks, (ks + item - 1) / item));
       const int ntiles = (n_grid + 63) / 64;
-      QL.workers = std::max(1, std::min(ntiles * QL.nsub, 4 * s->ncu * s->opt.waves_per_simd));
+      const int wps = s->opt.waves_per_simd > 0 ? s->opt.waves_per_simd
+                                                 : auto_waves_per_simd(ntiles, s->ncu);
+      s->last_wps = wps;
+      QL.workers = std::max(1, std::min(ntiles * QL.nsub, 4 * s->ncu * wps));
       QL.workers = std::min(QL.workers, ntiles);
       QL.block = s->opt.block_threads;
       QL.error = s->d_qerr;
@@ -1418,7 +1421,7 @@ int tpm_get_stats(tpm_sim* s, tpm_stats* o) {
   if (!s || !o) return fail(TPM_EINVAL, "NULL argument");
   tpm_stats st = s->stats;
   st.sub_chunks = s->opt.sub_chunks;
-  st.waves_per_simd = s->opt.waves_per_simd;
+  st.waves_per_simd = s->opt.waves_per_simd > 0 ? s->opt.waves_per_simd : s->last_wps;
   st.block_threads = s->opt.block_threads;
   st.chunk_steps = s->opt.chunk_steps;
   st.resync_chunks = s->opt.resync_chunks;

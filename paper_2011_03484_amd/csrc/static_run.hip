@@ -182,7 +182,6 @@ extern "C" int tpm_integrate_static(const tpm_options* opt_in, double mu0, int32
   if (o.block_threads % 64 || o.block_threads > 256)
     return sfail(TPM_EINVAL, "block_threads must be 64, 128, 192 or 256");
   if (o.sub_chunks == 0) o.sub_chunks = 64;
-  if (o.waves_per_simd == 0) o.waves_per_simd = 1;
   if (o.waves_per_simd > 8) return sfail(TPM_EINVAL, "waves_per_simd > 8");
   if (!(o.kepler_ftol > 0.0)) o.kepler_ftol = 1e-13;
   if (!std::isfinite(o.r_escape)) return sfail(TPM_EINVAL, "r_escape not finite");
@@ -306,7 +305,8 @@ extern "C" int tpm_integrate_static(const tpm_options* opt_in, double mu0, int32
       QL.epoch = q_epoch;
       const int item = std::max(1, K / std::max(1, o.sub_chunks));
       QL.nsub = std::max(1, std::min(o.sub_chunks, (ks + item - 1) / item));
-      QL.workers = std::max(1, std::min(ntiles * QL.nsub, 4 * D.ncu * o.waves_per_simd));
+      const int wps = o.waves_per_simd > 0 ? o.waves_per_simd : auto_waves_per_simd(ntiles, D.ncu);
+      QL.workers = std::max(1, std::min(ntiles * QL.nsub, 4 * D.ncu * wps));
       QL.workers = std::min(QL.workers, ntiles);
       QL.block = o.block_threads;
       QL.error = &misc->qerr;
