@@ -51,7 +51,7 @@ def _workload(n, seed, permute=False):
     return w
 
 
-def _ephemeris(orc, w, T, rp):
+def _ephemeris(orc, w, T, rp, dt=None):
     """The oracle's planet table and velocities in the caller's planet order:
     the oracle's planet map takes the planets sorted by semi-major axis (its
     Jacobi order, as the library sorts them), so they are sorted for it and
@@ -59,7 +59,8 @@ def _ephemeris(orc, w, T, rp):
     rn = np.linalg.norm(rp, axis=1)
     a = 1.0 / (2.0 / rn - np.sum(w.vp ** 2, axis=1) / (w.mu0 + w.mu))
     order = np.argsort(a, kind="stable")
-    e = orc.ephemeris(w.mu0, w.mu[order], rp[order], w.vp[order], T, w.dt, keep_velocities=True)
+    e = orc.ephemeris(w.mu0, w.mu[order], rp[order], w.vp[order], T, w.dt if dt is None else dt,
+                      keep_velocities=True)
     table, vtable = e.table.copy(), e.vtable.copy()
     for k, c in enumerate(order):
         table[:, 3 * c:3 * c + 3] = e.table[:, 3 * k:3 * k + 3]
@@ -67,7 +68,7 @@ def _ephemeris(orc, w, T, rp):
     return table, vtable
 
 
-def _handoff_reference(orc, w, T, rrem, M, universal, idx=None):
+def _handoff_reference(orc, w, T, rrem, M, universal, idx=None, dt=None):
     """Oracle result of the hand-off run on the oracle's own planet table, and
     each particle's near-threshold flag and spread.  A particle is
     near-threshold when its removal record changes as the hand-off, removal
@@ -77,13 +78,14 @@ def _handoff_reference(orc, w, T, rrem, M, universal, idx=None):
     idx: the particles to run (all by default)."""
     sel = slice(None) if idx is None else idx
     r0, v0 = w.r[sel], w.v[sel]
+    dt = w.dt if dt is None else dt
 
     def run(table, vtable, rr=r0, f=1.0):
         return orc.particles_handoff(w.mu0, w.mu, w.rcrit * f, rrem * f, w.rmax * f, table,
-                                     vtable, w.dt, rr, v0, T, substeps=M,
+                                     vtable, dt, rr, v0, T, substeps=M,
                                      kepler_iters=w.kepler_iters, universal=universal)
 
-    table, vtable = _ephemeris(orc, w, T, w.rp)
+    table, vtable = _ephemeris(orc, w, T, w.rp, dt)
     res = run(table, vtable)
     near = np.zeros(len(r0), bool)
     for f in (1 - 1e-9, 1 + 1e-9):
@@ -100,9 +102,9 @@ def _handoff_reference(orc, w, T, rrem, M, universal, idx=None):
     sp1, f1 = response(run(table, vtable, rr=r0 * (1 + np.finfo(float).eps)))
     rp1 = w.rp.copy()
     rp1[0, 0] *= 1 + np.finfo(float).eps
-    sp2, f2 = response(run(*_ephemeris(orc, w, T, rp1)))
+    sp2, f2 = response(run(*_ephemeris(orc, w, T, rp1, dt)))
     with orc.rounding_probe():
-        sp3, f3 = response(run(*_ephemeris(orc, w, T, w.rp)))
+        sp3, f3 = response(run(*_ephemeris(orc, w, T, w.rp, dt)))
     near |= f1 | f2 | f3
     return res, near, np.maximum(np.maximum(sp1, sp2), sp3), table
 
@@ -168,6 +170,47 @@ def test_handoff_matches_oracle(tpm, orc, M, universal, permute):
     assert reached.sum() > 100
     _compare(got, res, near, spread, f"handoff M={M}")
     assert abs(st["handoffs"] - reached.sum()) <= near.sum(), (st["handoffs"], reached.sum())
+
+
+def test_handoff_backwards_matches_oracle(tpm, orc):
+    """The hand-off integrating backwards in time (dt < 0: the interpolants'
+    velocity terms change sign with the step) against the oracle, to the
+    parity bar."""
+    w = _workload(4096, 87)
+    T = 2500
+    rrem = np.full(w.np_, 0.05)
+    print(f"[backwards] n={w.n} T={T}", flush=True)
+    s = _sim(tpm, w, w.rcrit, rrem, handoff_substeps=8, universal_drift=True, chunk_steps=700)
+    s.integrate(T, -w.dt)
+    got, st = s.particles(), s.stats()
+    res, near, spread, _ = _handoff_reference(orc, w, T, rrem, 8, True, dt=-w.dt)
+    print(f"handoffs {st['handoffs']} encounter steps {res.encounter_steps.sum()}", flush=True)
+    assert st["handoffs"] > 100
+    _compare(got, res, near, spread, "handoff backwards")
+
+
+def test_handoff_without_planets_or_particles(tpm):
+    """No planets: nothing is handed off and the run equals the plain one bit
+    for bit; no particles: the call runs and leaves nothing behind."""
+    w = _workload(512, 88)
+    empty = np.zeros(0)
+    a = tpm.Simulation(r_escape=w.rmax, handoff_substeps=8)
+    b = tpm.Simulation(r_escape=w.rmax)
+    for s in (a, b):
+        s.set_central(w.mu0)
+        s.set_planets(empty, np.zeros((0, 3)), np.zeros((0, 3)), empty)
+        s.set_particles(w.r, w.v)
+    a.set_removal_radii(empty)
+    a.integrate(1500, w.dt)
+    b.integrate(1500, w.dt)
+    pa, pb = a.particles(), b.particles()
+    assert a.stats()["handoffs"] == 0
+    for k in KEYS:
+        assert np.array_equal(pa[k], pb[k]), k
+    c = _sim(tpm, w, w.rcrit, np.full(w.np_, 0.05), handoff_substeps=8)
+    c.set_particles(np.zeros((0, 3)), np.zeros((0, 3)))
+    c.integrate(100, w.dt)
+    assert c.stats()["handoffs"] == 0 and c.stats()["step"] == 100
 
 
 def test_handoff_split_calls_are_bitwise(tpm):
