@@ -68,15 +68,35 @@ struct EncArgs {
   int64_t step0;
 };
 
-// Lowest planet index with |r - r_j|^2 < rad2_j in a table row, or -1.
+// The kick acceleration from a table row with the particle kernel's
+// arithmetic (accel in particle.hpp), returning the lowest planet index within
+// its removal radius (or -1) and setting enc when the particle lies within a
+// hand-off radius: the two tests share the squared distances.
 template <int NP, typename RowT>
-TPM_DEV int within(const RowT& row, const double (&rad2)[NP > 0 ? NP : 1], double x, double y,
-                   double z) {
+TPM_DEV int accel_enc(const RowT& row, const EncArgs<NP>& A, double x, double y, double z,
+                      double& ax, double& ay, double& az, bool& enc) {
+  ax = row[3 * NP + 0];
+  ay = row[3 * NP + 1];
+  az = row[3 * NP + 2];
+  double d2s[NP > 0 ? NP : 1];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    double dx = x - row[3 * j + 0];
+    double dy = y - row[3 * j + 1];
+    double dz = z - row[3 * j + 2];
+    double d2 = fma_(dx, dx, fma_(dy, dy, dz * dz));
+    d2s[j] = d2;
+    double k = mul_rsqrt3(A.Prem.mu[j], d2);
+    ax = fma_(-k, dx, ax);
+    ay = fma_(-k, dy, ay);
+    az = fma_(-k, dz, az);
+  }
   int hit = -1;
+  enc = false;
 #pragma unroll
   for (int j = NP - 1; j >= 0; --j) {
-    const double dx = x - row[3 * j], dy = y - row[3 * j + 1], dz = z - row[3 * j + 2];
-    hit = fma_(dx, dx, fma_(dy, dy, dz * dz)) < rad2[j] ? j : hit;
+    hit = d2s[j] < A.Prem.rcrit2[j] ? j : hit;
+    enc = enc | (d2s[j] < A.renc2[j]);
   }
   return hit;
 }
@@ -84,9 +104,9 @@ TPM_DEV int within(const RowT& row, const double (&rad2)[NP > 0 ? NP : 1], doubl
 // Acceleration at fraction tau of the step from row a to row b (planet
 // velocities va, vb per row) with the planets on their Hermite interpolants;
 // returns the lowest planet index within its removal radius, or -1.
-template <int NP, typename RowT>
-TPM_DEV int interp_accel(const EncArgs<NP>& A, double tau, const RowT& ra,
-                         const double* __restrict__ va, const RowT& rb,
+template <int NP, typename RowA, typename RowB>
+TPM_DEV int interp_accel(const EncArgs<NP>& A, double tau, const RowA& ra,
+                         const double* __restrict__ va, const RowB& rb,
                          const double* __restrict__ vb, double x, double y, double z, double& ax,
                          double& ay, double& az) {
   const double t2 = tau * tau, t3 = t2 * tau;
@@ -153,10 +173,11 @@ TPM_DEV bool enc_drift(const EncArgs<NP>& A, double dt, double& x, double& y, do
 // iterations, not M per step whenever any lane is in an encounter.  The
 // acceleration at the end of a plain step or of a step's last substep comes
 // from the row itself (exactly the main kernel's arithmetic), inside a step
-// from the interpolated planets.  The rows at the two ends of a lane's step
-// stay in registers through its substeps, and each micro-step fetches the
-// next one's closing row.  KIT > 0 fixes the Newton count at compile time, as
-// in the particle kernel.
+// from the interpolated planets.  The closing row of a lane's step stays in
+// registers through its substeps, each micro-step fetches the next one's, and
+// the hand-off radius test of a step boundary comes with the acceleration
+// there.  KIT > 0 fixes the Newton count at compile time, as in the particle
+// kernel.
 template <int NP, int KIT>
 __global__ void __launch_bounds__(64)
 encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
@@ -180,10 +201,11 @@ encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
   };
   // checks at the first boundary (the particle kernel handed the particle off
   // there before testing the removal radius or escape)
-  Row<NP> Ra, Rb, Rn;       // rows s, s + 1, and the next micro-step's closing row
-  load_row<NP>(Ra, rows + (size_t)s * ROW, 0);
+  Row<NP> Rn;               // with Rb below: closing rows of the next and this micro-step
+  load_row<NP>(Rn, rows + (size_t)s * ROW, 0);
   double ax, ay, az;
-  int hit = accel<NP>(Ra.v, A.Prem, x, y, z, ax, ay, az);
+  bool enc;                 // within a hand-off radius at the current step boundary
+  int hit = accel_enc<NP>(Rn.v, A, x, y, z, ax, ay, az, enc);
   if (hit >= 0) {
     remove(ST_ENCOUNTER, A.step0 + s, hit, x, y, z, vx, vy, vz);
     return;
@@ -192,13 +214,14 @@ encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
     remove(ST_ESCAPE, A.step0 + s, -1, x, y, z, vx, vy, vz);
     return;
   }
+  Row<NP> Rb;
   if (s < A.nsteps) load_row<NP>(Rb, rows + (size_t)(s + 1) * ROW, 0);
   const double hM = A.dt / A.M;
   int m = 0, Ml = 1;        // substep within the current step, substeps of this step
   for (;;) {
     if (s >= A.nsteps) break;
     // the mode of a step is decided at its first boundary
-    if (m == 0) Ml = within<NP>(Ra.v, A.renc2, x, y, z) >= 0 ? A.M : 1;
+    if (m == 0) Ml = enc ? A.M : 1;
     // the closing row of the next micro-step, fetched by every lane (row
     // s + 2 if this micro-step ends the step, else row s + 1 again) so that
     // the loads are not conditional and their latency hides behind the drift
@@ -214,11 +237,11 @@ encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
       return;
     }
     if (ends) {
-      hit = accel<NP>(Rb.v, A.Prem, nx, ny, nz, ax, ay, az);
+      hit = accel_enc<NP>(Rb.v, A, nx, ny, nz, ax, ay, az, enc);
     } else {
       const double* va = vrows + (size_t)s * 3 * NP;
-      hit = interp_accel<NP>(A, (double)(m + 1) / Ml, Ra.v, va, Rb.v, va + 3 * NP, nx, ny, nz, ax,
-                             ay, az);
+      hit = interp_accel<NP>(A, (double)(m + 1) / Ml, rows + (size_t)s * ROW, va, Rb.v,
+                             va + 3 * NP, nx, ny, nz, ax, ay, az);
     }
     x = nx; y = ny; z = nz;
     vx = fma_(hh, ax, nvx); vy = fma_(hh, ay, nvy); vz = fma_(hh, az, nvz);
@@ -227,11 +250,7 @@ encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
       remove(ST_ENCOUNTER, A.step0 + s + 1, hit, x, y, z, vx, vy, vz);
       return;
     }
-#pragma unroll
-    for (int k = 0; k < 3 * NP + 3; ++k) {
-      Ra.v[k] = ends ? Rb.v[k] : Ra.v[k];
-      Rb.v[k] = Rn.v[k];
-    }
+    Rb = Rn;
     if (++m == Ml) {
       m = 0;
       ++s;
