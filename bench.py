@@ -281,8 +281,8 @@ TRACE_RUNS = {
             "particle_queue / ephemeris_chunk -- resonant_200k, 200,000 particles x 1,000,000 steps",
             "--nsteps 1000 --n 1024 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched "
             "--no-handoff"),
-    "ho": ("encounter_chunk_giants_100k_handoff_kernel_trace.md",
-           "particle_queue / encounter_chunk -- giants_100k with the close-encounter hand-off, "
+    "ho": ("encounter_run_giants_100k_handoff_kernel_trace.md",
+           "particle_queue / encounter_run -- giants_100k with the close-encounter hand-off, "
            "100,000 particles x 1,000,000 steps, 16 substeps",
            "--nsteps 1000 --n 1024 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched "
            "--no-resonant"),
@@ -407,7 +407,7 @@ def _trace_details(key, rows, line):
                     f"sweep; span {span:.1f} ms.", ""]
     if key == "ho":
         h = line.get("handoff", {})
-        enc = [(t0, t1) for k, t0, t1 in rows if "encounter_chunk" in k]
+        enc = [(t0, t1) for k, t0, t1 in rows if "encounter_run" in k]
         ov = 0
         for t0, t1 in enc:          # overlap of each encounter launch with the particle launches
             ov += sum(max(0, min(t1, u1) - max(t0, u0)) for u0, u1 in pq)
@@ -415,10 +415,10 @@ def _trace_details(key, rows, line):
                 f"{h.get('run_ms', 0):.1f} ms, {h.get('handoffs')} hand-offs, removed by reason "
                 f"{h.get('removed_by_reason')}, survivors {h.get('survivors')}.", ""]
         if enc:
-            out += [f"encounter_chunk: {len(enc)} launches, {sum(t1 - t0 for t0, t1 in enc) * 1e-6:.1f} ms "
+            out += [f"encounter_run: {len(enc)} launches, {sum(t1 - t0 for t0, t1 in enc) * 1e-6:.1f} ms "
                     f"busy, {ov * 1e-6:.1f} ms of it beside a particle_queue launch; particle_queue "
                     f"{sum(t1 - t0 for t0, t1 in pq) * 1e-6:.1f} ms busy.", "",
-                    "encounter_chunk durations in launch order, ms:", "",
+                    "encounter_run durations in launch order, ms:", "",
                     "    " + " ".join(f"{(t1 - t0) * 1e-6:.0f}" for t0, t1 in enc), ""]
     if key == "batched":
         b = line.get("batched", {})
@@ -569,7 +569,7 @@ def handoff_run(P, W, torch, nsteps: int, substeps: int = 16, r_rem: float = 0.0
     """The headline workload with the close-encounter hand-off: a particle
     within 0.5 au of a planet moves to the encounter integrator (substeps
     substeps per step, planets on their Hermite interpolants) and is removed
-    within r_rem; the encounter stream runs one chunk behind the main one."""
+    within r_rem; the encounter stream runs behind the main one."""
     w = W.giants_100k()
     s = P.Simulation(r_escape=w.rmax, kepler_iters=w.kepler_iters, time_kernels=True,
                      handoff_substeps=substeps, universal_drift=True)

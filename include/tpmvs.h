@@ -95,7 +95,9 @@ typedef struct {
    * reading follows).  With handoff_substeps = M > 0, a particle that comes
    * within a planet's r_crit (tpm_set_planets; the hand-off radius) is not
    * removed but handed off to a secondary kernel that integrates the list of
-   * such particles one chunk behind the main kernel, on a stream of its own:
+   * such particles behind the main kernel, on a stream of its own (the call
+   * keeps all its planet rows for it: (chunk_steps + 1) x (6 Np + 3) x 8
+   * bytes per chunk, a call needing more than 4 GiB runs as several):
    * at every step boundary a particle within the hand-off radius of any
    * planet takes its next step as M equal substeps of the same kick - drift -
    * kick, with the planets between the two table rows on the cubic Hermite

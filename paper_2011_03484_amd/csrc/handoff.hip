@@ -19,9 +19,13 @@
 // The particle kernel hands a lane off where it would otherwise record an
 // encounter removal (hand-off radius = its rcrit) and leaves its state in the
 // working set; handoff_gather moves such entries to the encounter list;
-// encounter_chunk advances the list through a chunk, one lane per entry (the
-// lanes diverge, which is why they left the main kernel); handoff_merge puts
-// the survivors back into the working set at the end of an integrate call.
+// encounter_run advances the list towards the end of a chunk, one lane per
+// entry (the lanes diverge, which is why they left the main kernel);
+// handoff_merge puts the survivors back into the working set at the end of
+// an integrate call.  A lane may lag behind the main kernel: every launch
+// gives it a budget of micro-steps, and where it stops (at a step or substep
+// boundary) the next launch resumes it, with the planet rows of every chunk
+// of the call still in place; the last launch of a call has no budget.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -42,6 +46,7 @@ handoff_gather(Work w, const int32_t* __restrict__ d_nactive, EncList L, int64_t
   L.slot[k] = w.slot[i];
   L.status[k] = ST_ACTIVE;
   L.step[k] = step0 + (st - HANDOFF_BASE);
+  L.m[k] = -1;                            // not yet checked at its hand-off boundary
   w.status[i] = ST_HANDED;
 }
 
@@ -64,8 +69,9 @@ struct EncArgs {
   double renc2[NP > 0 ? NP : 1];
   KepConst K;
   double rmax2, ftol, dt;
-  int kiters, nsteps, M, universal;
-  int64_t step0;
+  int kiters, M, universal;
+  int64_t target;         // step (from the call's start) the lanes advance to
+  int64_t budget;         // micro-steps per lane in this launch; 0 = no limit
 };
 
 // The kick acceleration from a table row with the particle kernel's
@@ -176,17 +182,39 @@ TPM_DEV bool enc_drift(const EncArgs<NP>& A, double dt, double& x, double& y, do
 // from the interpolated planets.  The closing row of a lane's step stays in
 // registers through its substeps, each micro-step fetches the next one's, and
 // the hand-off radius test of a step boundary comes with the acceleration
-// there.  KIT > 0 fixes the Newton count at compile time, as in the particle
-// kernel.
+// there.  A lane enters at a step boundary (its hand-off boundary, a chunk's
+// first step, or where a budget stopped it) as the particle kernel enters a
+// chunk: acceleration, removal-radius and escape checks from the row there;
+// inside a step (a budget stopped it after a substep) with the acceleration of
+// the interpolated planets there.  Either gives the values the lane had when
+// it stopped, bit for bit.  KIT > 0 fixes the Newton count at compile time,
+// as in the particle kernel.
 template <int NP, int KIT>
 __global__ void __launch_bounds__(64)
-encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
-                const double* __restrict__ rows, const double* __restrict__ vrows, Out out) {
+encounter_run(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap, EncRing R, Out out) {
   constexpr int ROW = 3 * NP + 3;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= *snap || L.status[i] != ST_ACTIVE) return;
-  int s = (int)(L.step[i] - A.step0);
-  if (s < 0 || s > A.nsteps) return;     // not in this chunk (never the case)
+  // chunk c covers steps [cb(c), cb(c + 1)) of the call, cut at its end
+  auto cb = [&](int c) -> int64_t {
+    const int64_t b = c == 0 ? 0 : R.k0 + (int64_t)(c - 1) * R.k;
+    return b < R.nsteps ? b : R.nsteps;
+  };
+  const int64_t g0 = L.step[i] - R.step0;
+  if (g0 < 0 || g0 > R.nsteps) return;   // not in this call (never the case)
+  int m = L.m[i], Ml = L.Ml[i];
+  if (m > 0 && g0 >= R.nsteps) return;   // inside a step past the call's end (never the case)
+  auto chunk_of = [&](int64_t g) -> int { return g < R.k0 ? 0 : 1 + (int)((g - R.k0) / R.k); };
+  // a lane inside step g0 (a budget stopped it after a substep) is in the
+  // chunk that holds that step; a lane at the boundary g0 in the chunk that
+  // ends at or holds it: at a chunk's end it enters with that chunk's last
+  // row (the next chunk's rows may not exist yet when g0 is the launch's
+  // start)
+  int c = m > 0 ? chunk_of(g0) : (g0 == 0 ? 0 : chunk_of(g0 - 1));
+  int s = (int)(g0 - cb(c));
+  int ks = (int)(cb(c + 1) - cb(c));
+  const double* rc = R.rows + (size_t)c * R.ring_rows * ROW;
+  const double* vc = R.vrows + (size_t)c * R.vring_rows * 3 * NP;
   double x = L.x[i], y = L.y[i], z = L.z[i];
   double vx = L.vx[i], vy = L.vy[i], vz = L.vz[i];
   auto remove = [&](int32_t why, int64_t st, int32_t pl, double rx, double ry, double rz,
@@ -199,76 +227,109 @@ encounter_chunk(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap,
     out.planet[k] = pl;
     L.status[i] = why;
   };
-  // checks at the first boundary (the particle kernel handed the particle off
-  // there before testing the removal radius or escape)
-  Row<NP> Rn;               // with Rb below: closing rows of the next and this micro-step
-  load_row<NP>(Rn, rows + (size_t)s * ROW, 0);
   double ax, ay, az;
-  bool enc;                 // within a hand-off radius at the current step boundary
-  int hit = accel_enc<NP>(Rn.v, A, x, y, z, ax, ay, az, enc);
-  if (hit >= 0) {
-    remove(ST_ENCOUNTER, A.step0 + s, hit, x, y, z, vx, vy, vz);
-    return;
-  }
-  if (fma_(x, x, fma_(y, y, z * z)) > A.rmax2) {
-    remove(ST_ESCAPE, A.step0 + s, -1, x, y, z, vx, vy, vz);
-    return;
-  }
-  Row<NP> Rb;
-  if (s < A.nsteps) load_row<NP>(Rb, rows + (size_t)(s + 1) * ROW, 0);
-  const double hM = A.dt / A.M;
-  int m = 0, Ml = 1;        // substep within the current step, substeps of this step
-  for (;;) {
-    if (s >= A.nsteps) break;
-    // the mode of a step is decided at its first boundary
-    if (m == 0) Ml = enc ? A.M : 1;
-    // the closing row of the next micro-step, fetched by every lane (row
-    // s + 2 if this micro-step ends the step, else row s + 1 again) so that
-    // the loads are not conditional and their latency hides behind the drift
-    const bool ends = m + 1 == Ml;
-    load_row<NP>(Rn, rows + (size_t)min(s + (ends ? 2 : 1), A.nsteps) * ROW, 0);
-    const double h = Ml == 1 ? A.dt : hM;
-    const double hh = 0.5 * h;
-    double nx = x, ny = y, nz = z;
-    double nvx = fma_(hh, ax, vx), nvy = fma_(hh, ay, vy), nvz = fma_(hh, az, vz);
-    if (!enc_drift<NP, KIT>(A, h, nx, ny, nz, nvx, nvy, nvz)) {
-      // the state at the start of the failing (sub)step
-      remove(ST_KEPLER, A.step0 + s, -1, x, y, z, vx, vy, vz);
-      return;
-    }
-    if (ends) {
-      hit = accel_enc<NP>(Rb.v, A, nx, ny, nz, ax, ay, az, enc);
-    } else {
-      const double* va = vrows + (size_t)s * 3 * NP;
-      hit = interp_accel<NP>(A, (double)(m + 1) / Ml, rows + (size_t)s * ROW, va, Rb.v,
-                             va + 3 * NP, nx, ny, nz, ax, ay, az);
-    }
-    x = nx; y = ny; z = nz;
-    vx = fma_(hh, ax, nvx); vy = fma_(hh, ay, nvy); vz = fma_(hh, az, nvz);
+  bool enc = false;         // within a hand-off radius at the current step boundary
+  // entry at step boundary s of chunk c: acceleration, removal radius, escape
+  auto enter = [&]() -> bool {
+    Row<NP> R0;
+    load_row<NP>(R0, rc + (size_t)s * ROW, 0);
+    const int hit = accel_enc<NP>(R0.v, A, x, y, z, ax, ay, az, enc);
     if (hit >= 0) {
-      // step n + 1 at the step's end or at a substep inside it
-      remove(ST_ENCOUNTER, A.step0 + s + 1, hit, x, y, z, vx, vy, vz);
-      return;
+      remove(ST_ENCOUNTER, R.step0 + cb(c) + s, hit, x, y, z, vx, vy, vz);
+      return false;
     }
-    Rb = Rn;
-    if (++m == Ml) {
-      m = 0;
-      ++s;
-      if (fma_(x, x, fma_(y, y, z * z)) > A.rmax2) {
-        remove(ST_ESCAPE, A.step0 + s, -1, x, y, z, vx, vy, vz);
+    if (fma_(x, x, fma_(y, y, z * z)) > A.rmax2) {
+      remove(ST_ESCAPE, R.step0 + cb(c) + s, -1, x, y, z, vx, vy, vz);
+      return false;
+    }
+    return true;
+  };
+  if (m <= 0) {
+    m = 0;
+    if (!enter()) return;
+  } else {
+    const double* va = vc + (size_t)s * 3 * NP;
+    interp_accel<NP>(A, (double)m / Ml, rc + (size_t)s * ROW, va, rc + (size_t)(s + 1) * ROW,
+                     va + 3 * NP, x, y, z, ax, ay, az);
+  }
+  // into the next chunk at chunk c's end, entered as the particle kernel
+  // enters a chunk
+  auto next_chunk = [&]() -> bool {
+    ++c;
+    s = 0;
+    ks = (int)(cb(c + 1) - cb(c));
+    rc = R.rows + (size_t)c * R.ring_rows * ROW;
+    vc = R.vrows + (size_t)c * R.vring_rows * 3 * NP;
+    return enter();
+  };
+  const double hM = A.dt / A.M;
+  int64_t used = 0;
+  if (cb(c) + s < A.target) {
+    if (s == ks && !next_chunk()) return;
+    Row<NP> Rb, Rn;         // the closing row of this and of the next micro-step
+    load_row<NP>(Rb, rc + (size_t)(s + 1) * ROW, 0);
+    for (;;) {
+      if (A.budget > 0 && used >= A.budget) break;
+      // the mode of a step is decided at its first boundary
+      if (m == 0) Ml = enc ? A.M : 1;
+      // the closing row of the next micro-step, fetched by every lane (row
+      // s + 2 if this micro-step ends the step, else row s + 1 again) so
+      // that the loads are not conditional and their latency hides behind
+      // the drift
+      const bool ends = m + 1 == Ml;
+      load_row<NP>(Rn, rc + (size_t)min(s + (ends ? 2 : 1), ks) * ROW, 0);
+      const double h = Ml == 1 ? A.dt : hM;
+      const double hh = 0.5 * h;
+      double nx = x, ny = y, nz = z;
+      double nvx = fma_(hh, ax, vx), nvy = fma_(hh, ay, vy), nvz = fma_(hh, az, vz);
+      if (!enc_drift<NP, KIT>(A, h, nx, ny, nz, nvx, nvy, nvz)) {
+        // the state at the start of the failing (sub)step
+        remove(ST_KEPLER, R.step0 + cb(c) + s, -1, x, y, z, vx, vy, vz);
         return;
+      }
+      int hit;
+      if (ends) {
+        hit = accel_enc<NP>(Rb.v, A, nx, ny, nz, ax, ay, az, enc);
+      } else {
+        const double* va = vc + (size_t)s * 3 * NP;
+        hit = interp_accel<NP>(A, (double)(m + 1) / Ml, rc + (size_t)s * ROW, va, Rb.v,
+                               va + 3 * NP, nx, ny, nz, ax, ay, az);
+      }
+      x = nx; y = ny; z = nz;
+      vx = fma_(hh, ax, nvx); vy = fma_(hh, ay, nvy); vz = fma_(hh, az, nvz);
+      if (hit >= 0) {
+        // step n + 1 at the step's end or at a substep inside it
+        remove(ST_ENCOUNTER, R.step0 + cb(c) + s + 1, hit, x, y, z, vx, vy, vz);
+        return;
+      }
+      Rb = Rn;
+      ++used;
+      if (++m == Ml) {
+        m = 0;
+        ++s;
+        if (fma_(x, x, fma_(y, y, z * z)) > A.rmax2) {
+          remove(ST_ESCAPE, R.step0 + cb(c) + s, -1, x, y, z, vx, vy, vz);
+          return;
+        }
+        if (cb(c) + s >= A.target) break;
+        if (s == ks) {
+          if (!next_chunk()) return;
+          load_row<NP>(Rb, rc + ROW, 0);
+        }
       }
     }
   }
   L.x[i] = x; L.y[i] = y; L.z[i] = z;
   L.vx[i] = vx; L.vy[i] = vy; L.vz[i] = vz;
-  L.step[i] = A.step0 + A.nsteps;
+  L.step[i] = R.step0 + cb(c) + s;
+  L.m[i] = m;
+  L.Ml[i] = Ml;
 }
 
 template <int NP>
 static hipError_t enc_np(const SysConst& S, const double* rrem2, EncList L, const int32_t* snap,
-                         int n_upper, const double* rows, const double* vrows, int nsteps,
-                         double dt, int64_t step0, int M, Out out, hipStream_t st) {
+                         int n_upper, const EncRing& R, int64_t target, int64_t budget, double dt,
+                         int M, Out out, hipStream_t st) {
   EncArgs<NP> A;
   for (int j = 0; j < (NP > 0 ? NP : 1); ++j) {
     A.Prem.mu[j] = NP > 0 ? S.mu[j] : 0.0;
@@ -280,28 +341,29 @@ static hipError_t enc_np(const SysConst& S, const double* rrem2, EncList L, cons
   A.ftol = S.ftol;
   A.dt = dt;
   A.kiters = S.kiters;
-  A.nsteps = nsteps;
   A.M = M;
   A.universal = S.universal;
-  A.step0 = step0;
+  A.target = target;
+  A.budget = budget;
   if (S.kiters == 5)
-    hipLaunchKernelGGL((encounter_chunk<NP, 5>), dim3((n_upper + 63) / 64), dim3(64), 0, st, A, L,
-                       snap, rows, vrows, out);
+    hipLaunchKernelGGL((encounter_run<NP, 5>), dim3((n_upper + 63) / 64), dim3(64), 0, st, A, L,
+                       snap, R, out);
   else
-    hipLaunchKernelGGL((encounter_chunk<NP, 0>), dim3((n_upper + 63) / 64), dim3(64), 0, st, A, L,
-                       snap, rows, vrows, out);
+    hipLaunchKernelGGL((encounter_run<NP, 0>), dim3((n_upper + 63) / 64), dim3(64), 0, st, A, L,
+                       snap, R, out);
   return hipGetLastError();
 }
 
-hipError_t launch_encounter_chunk(const SysConst& S, const double* rrem2, EncList L,
-                                  const int32_t* snap, int n_upper, const double* rows,
-                                  const double* vrows, int nsteps, double dt, int64_t step0,
-                                  int M, Out out, hipStream_t st) {
+hipError_t launch_encounter_run(const SysConst& S, const double* rrem2, EncList L,
+                                const int32_t* snap, int n_upper, const EncRing& R,
+                                int64_t target, int64_t budget, double dt, int M, Out out,
+                                hipStream_t st) {
   if (n_upper <= 0) return hipSuccess;
-  if (M < 1) return hipErrorInvalidValue;
+  if (M < 1 || R.k0 < 1 || R.k < 1 || target < 0 || target > R.nsteps)
+    return hipErrorInvalidValue;
   switch (S.np) {
 #define TPM_ENC(N) \
-    case N: return enc_np<N>(S, rrem2, L, snap, n_upper, rows, vrows, nsteps, dt, step0, M, out, st);
+    case N: return enc_np<N>(S, rrem2, L, snap, n_upper, R, target, budget, dt, M, out, st);
     TPM_ENC(0) TPM_ENC(1) TPM_ENC(2) TPM_ENC(3) TPM_ENC(4) TPM_ENC(5) TPM_ENC(6) TPM_ENC(7)
     TPM_ENC(8)
 #undef TPM_ENC

@@ -70,7 +70,22 @@ struct EncList {
   int32_t* slot;
   int32_t* status;
   int64_t* step;
+  int32_t* m;            // substeps done in the current step; -1: not yet entered
+  int32_t* Ml;           // substeps of the current step
   int32_t* count;        // entries in use
+};
+
+// The planet rows of an integrate call for the encounter integrator: chunk c
+// covers steps [cb(c), cb(c + 1)) from the call's start, cb(0) = 0,
+// cb(1) = k0, cb(c) = k0 + (c - 1) k, cut at nsteps; its rows and its planets'
+// velocities are slot c.
+struct EncRing {
+  const double* rows;    // [slots][ring_rows][3 np + 3]
+  const double* vrows;   // [slots][vring_rows][np][3]
+  int64_t ring_rows, vring_rows;
+  int k0, k;
+  int64_t nsteps;
+  int64_t step0;         // global step of the call's start
 };
 
 // Ephemeris constants (bodies 0..np, body 0 = central mass).
@@ -123,14 +138,15 @@ hipError_t launch_ephemeris_chunk(const EphConst& E, double* rj, double* vj, dou
 // list's new length.
 hipError_t launch_handoff_gather(Work w, const int32_t* d_nactive, int n_upper, EncList L,
                                  int64_t step0, int32_t* snap, hipStream_t st);
-// Advance the first *snap list entries through the chunk's steps [step0,
-// step0 + nsteps) with the encounter reading (plain map steps outside the
-// hand-off radius S.rcrit2, M substeps with interpolated planets inside it,
-// removal within rrem2); rows and vrows as the planet map wrote them.
-hipError_t launch_encounter_chunk(const SysConst& S, const double* rrem2, EncList L,
-                                  const int32_t* snap, int n_upper, const double* rows,
-                                  const double* vrows, int nsteps, double dt, int64_t step0,
-                                  int M, Out out, hipStream_t st);
+// Advance the first *snap list entries towards step `target` of the call
+// with the encounter reading (plain map steps outside the hand-off radius
+// S.rcrit2, M substeps with interpolated planets inside it, removal within
+// rrem2, beyond S.rmax2, on a refused drift), at most `budget` micro-steps
+// per entry (0: no limit); removals go to `out`.
+hipError_t launch_encounter_run(const SysConst& S, const double* rrem2, EncList L,
+                                const int32_t* snap, int n_upper, const EncRing& R,
+                                int64_t target, int64_t budget, double dt, int M, Out out,
+                                hipStream_t st);
 // Append the list's active entries to the working set (after its active
 // entries, *d_nactive grows) and empty the list.
 hipError_t launch_handoff_merge(EncList L, int n_upper, Work w, int32_t* d_nactive,

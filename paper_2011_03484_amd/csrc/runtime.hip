@@ -88,6 +88,11 @@ hipError_t ensure_device_streams(DeviceStreams& D) {
 
 constexpr int NSLOT = 8;   // planet-table ring slots
 constexpr int FIRST_CHUNK_STEPS = 1024;   // longest first chunk of an on-the-fly run
+// With the close-encounter hand-off an integrate call keeps all its planet
+// rows (and planet velocities); a call that would need more than this is run
+// as several calls (survivors of the encounter list rejoin the working set at
+// each one's end, which changes no result).
+constexpr int64_t HANDOFF_RING_BYTES = int64_t(4) << 30;
 constexpr int NCNT = 8;    // in-flight active-count readbacks
 
 template <class T>
@@ -194,6 +199,7 @@ struct tpm_sim {
   int n_active = 0;                      // host copy (upper bound between compactions)
   double* d_ring = nullptr;
   int64_t ring_rows = 0;                 // rows per slot allocated
+  int64_t ring_slots = 0;                // slots allocated (NSLOT; with the hand-off, a call's chunks)
   double* d_table = nullptr;             // caller-supplied table (optional)
   int64_t table_rows = 0;
   // planet history (tpm_set_planet_history): t[nrec], r, v [nrec][np][3]
@@ -256,8 +262,10 @@ struct tpm_sim {
   bool rrem_set = false;
   EncList enc{};
   int32_t* d_snap = nullptr;             // [NSLOT]
-  double* d_vring = nullptr;             // [NSLOT][ring_rows][np][3]
-  int64_t vring_rows = 0;
+  double* d_vring = nullptr;             // [slots][ring_rows][np][3]
+  int64_t vring_rows = 0, vring_slots = 0;
+  int vring_np = -1;                     // planets the velocity ring was sized for
+  int64_t snap_slots = 0;                // entries of d_snap
   hipEvent_t ev_gath[NSLOT]{}, ev_hdone[NSLOT]{};
 
   ~tpm_sim() {
@@ -299,11 +307,15 @@ struct tpm_sim {
 
   void release_handoff() {
     dfree(enc.x); dfree(enc.y); dfree(enc.z); dfree(enc.vx); dfree(enc.vy); dfree(enc.vz);
-    dfree(enc.slot); dfree(enc.status); dfree(enc.step); dfree(enc.count);
+    dfree(enc.slot); dfree(enc.status); dfree(enc.step); dfree(enc.m); dfree(enc.Ml);
+    dfree(enc.count);
     enc = EncList{};
     dfree(d_snap);
     dfree(d_vring);
     vring_rows = 0;
+    vring_slots = 0;
+    vring_np = -1;
+    snap_slots = 0;
   }
   void release_particles() {
     release_handoff();
@@ -349,7 +361,7 @@ struct tpm_sim {
     const double a = hist_t0 + (double)step * dt, b = hist_t0 + (double)(step + nsteps) * dt;
     return std::min(a, b) >= hist_tmin && std::max(a, b) <= hist_tmax;
   }
-  void release_ring() { dfree(d_ring); d_ring = nullptr; ring_rows = 0; }
+  void release_ring() { dfree(d_ring); d_ring = nullptr; ring_rows = 0; ring_slots = 0; }
   void release_base() {
     // the streams belong to the device (shared); only wait for them
     if (sP) (void)hipStreamSynchronize(sP);
@@ -389,11 +401,11 @@ struct tpm_sim {
 
 namespace {
 
-// Buffers of the close-encounter hand-off for a run whose ring slots hold
-// `rows` rows: the encounter list (capacity n, empty), per-slot list lengths,
-// the planets' velocities per row of every slot, the ordering events and the
-// device's encounter stream.
-int ensure_handoff(tpm_sim* s, int64_t rows) {
+// Buffers of the close-encounter hand-off for a call of `slots` chunks whose
+// ring slots hold `rows` rows: the encounter list (capacity n, empty), the
+// list length after each chunk's hand-offs, the planets' velocities per row of
+// every slot, the ordering events and the device's encounter stream.
+int ensure_handoff(tpm_sim* s, int64_t rows, int64_t slots) {
   DeviceStreams& D = device_streams(s->opt.device);
   if (!D.sH) TPM_HIP(hipStreamCreateWithFlags(&D.sH, hipStreamNonBlocking));
   if (!s->ev_gath[0])
@@ -409,29 +421,37 @@ int ensure_handoff(tpm_sim* s, int64_t rows) {
     TPM_HIP(hipMalloc(&L.slot, sizeof(int32_t) * n));
     TPM_HIP(hipMalloc(&L.status, sizeof(int32_t) * n));
     TPM_HIP(hipMalloc(&L.step, sizeof(int64_t) * n));
+    TPM_HIP(hipMalloc(&L.m, sizeof(int32_t) * n));
+    TPM_HIP(hipMalloc(&L.Ml, sizeof(int32_t) * n));
     TPM_HIP(hipMalloc(&L.count, sizeof(int32_t)));
     TPM_HIP(hipMemset(L.count, 0, sizeof(int32_t)));
-    TPM_HIP(hipMalloc(&s->d_snap, sizeof(int32_t) * NSLOT));
-    TPM_HIP(hipMemset(s->d_snap, 0, sizeof(int32_t) * NSLOT));
   }
-  if (s->vring_rows < rows || !s->d_vring) {
+  if (s->vring_rows < rows || s->vring_slots < slots || s->vring_np != s->np || !s->d_vring ||
+      s->snap_slots < slots) {
     TPM_HIP(hipStreamSynchronize(s->sE));
+    TPM_HIP(hipStreamSynchronize(s->sP));
     TPM_HIP(hipStreamSynchronize(D.sH));
     dfree(s->d_vring);
-    TPM_HIP(hipMalloc(&s->d_vring, sizeof(double) * NSLOT * rows * 3 * std::max(s->np, 1)));
+    dfree(s->d_snap);
+    TPM_HIP(hipMalloc(&s->d_vring, sizeof(double) * slots * rows * 3 * std::max(s->np, 1)));
+    TPM_HIP(hipMalloc(&s->d_snap, sizeof(int32_t) * slots));
     s->vring_rows = rows;
+    s->vring_slots = slots;
+    s->vring_np = s->np;
+    s->snap_slots = slots;
   }
   return TPM_OK;
 }
 
-int ensure_ring(tpm_sim* s, int64_t rows) {
-  if (s->ring_rows >= rows && s->d_ring) return TPM_OK;
+int ensure_ring(tpm_sim* s, int64_t rows, int64_t slots = NSLOT) {
+  if (s->ring_rows >= rows && s->ring_slots >= slots && s->d_ring) return TPM_OK;
   TPM_HIP(hipStreamSynchronize(s->sE));
   TPM_HIP(hipStreamSynchronize(s->sP));
   s->release_ring();
-  size_t bytes = sizeof(double) * (size_t)NSLOT * rows * (3 * s->np + 3);
+  size_t bytes = sizeof(double) * (size_t)slots * rows * (3 * s->np + 3);
   TPM_HIP(hipMalloc(&s->d_ring, bytes));
   s->ring_rows = rows;
+  s->ring_slots = slots;
   return TPM_OK;
 }
 
@@ -829,6 +849,35 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
     return fail(TPM_EINVAL, "supplied planet table too short");
   if (s->d_hist && !s->hist_covers(s->step, nsteps, dt))
     return fail(TPM_EINVAL, "the run's row times leave the planet history");
+  if (s->opt.handoff_substeps > 0 && !s->d_table && !s->d_hist) {
+    const int64_t K = s->opt.chunk_steps;
+    const int64_t per_slot = (K + 1) * (3 * s->np + 3 + 3 * std::max(s->np, 1)) * 8;
+    const int64_t max_slots = std::max<int64_t>(2, HANDOFF_RING_BYTES / per_slot);
+    const int64_t seg = std::min<int64_t>(K, FIRST_CHUNK_STEPS) + (max_slots - 1) * K;
+    if (nsteps > seg) {
+      tpm_stats agg = s->stats;
+      agg.chunks = agg.compactions = agg.handoffs = agg.active_particle_steps = 0;
+      agg.particle_kernel_ms = agg.particle_ms = agg.ephemeris_ms = agg.wall_ms = 0.0;
+      int ret = TPM_OK;
+      for (int64_t done = 0; done < nsteps;) {
+        const int64_t piece = std::min(seg, nsteps - done);
+        const int rc = tpm_integrate(s, piece, dt);
+        if (rc != TPM_OK && rc != TPM_EPLANET) return rc;
+        if (rc == TPM_EPLANET) ret = rc;
+        agg.chunks += s->stats.chunks;
+        agg.compactions += s->stats.compactions;
+        agg.handoffs += s->stats.handoffs;
+        agg.active_particle_steps += s->stats.active_particle_steps;
+        agg.particle_kernel_ms += s->stats.particle_kernel_ms;
+        agg.particle_ms += s->stats.particle_ms;
+        agg.ephemeris_ms += s->stats.ephemeris_ms;
+        agg.wall_ms += s->stats.wall_ms;
+        done += piece;
+      }
+      s->stats = agg;
+      return ret;
+    }
+  }
   TPM_HIP(hipSetDevice(s->opt.device));
   std::lock_guard<std::mutex> dev_lock(device_streams(s->opt.device).lock);
   auto w0 = std::chrono::steady_clock::now();
@@ -863,14 +912,18 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   auto begin = [&](int64_t c) -> int64_t { return cb[c]; };
   auto length = [&](int64_t c) -> int { return (int)(cb[c + 1] - cb[c]); };
   const int64_t nchunks = (int64_t)cb.size() - 1;
+  // With the hand-off the ring keeps every chunk of the call (slot c for chunk
+  // c), so that the encounter stream may lag behind the particle stream.
+  const int64_t ring_slots = ho ? std::max<int64_t>(nchunks, 1) : NSLOT;
+  auto row_slot = [&](int64_t c) -> int64_t { return ho ? c : c % NSLOT; };
   if (!s->d_table) {
-    int rc = ensure_ring(s, (int64_t)K + 1);
+    int rc = ensure_ring(s, (int64_t)K + 1, ring_slots);
     if (rc) return rc;
   }
   hipStream_t sH = nullptr;
   double rrem2[MAX_NP] = {};
   if (ho) {
-    int rc = ensure_handoff(s, s->ring_rows);
+    int rc = ensure_handoff(s, s->ring_rows, ring_slots);
     if (rc) return rc;
     sH = device_streams(s->opt.device).sH;
     for (int j = 0; j < s->np; ++j) rrem2[j] = s->rrem_s[j] * s->rrem_s[j];
@@ -898,15 +951,12 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
       const int64_t c = eph_next;
       const int ks = length(c);
       const int slot = (int)(c % NSLOT);
-      double* srow = s->d_ring + (size_t)slot * s->ring_rows * rl;
+      double* srow = s->d_ring + (size_t)row_slot(c) * s->ring_rows * rl;
       TPM_HIP(hipStreamWaitEvent(s->sE, s->ev_done[slot], 0));
       double* vs = s->d_vside ? s->d_vside + (size_t)slot * 6 * s->np : nullptr;
-      double* vr = nullptr;
-      if (ho) {
-        // the encounter integrator is done with this slot's rows too
-        TPM_HIP(hipStreamWaitEvent(s->sE, s->ev_hdone[slot], 0));
-        vr = s->d_vring + (size_t)slot * s->vring_rows * 3 * s->np;
-      }
+      // with the hand-off, the planets' velocities at every row too (for the
+      // encounter integrator's interpolation; the slot is this chunk's alone)
+      double* vr = ho ? s->d_vring + (size_t)c * s->vring_rows * 3 * s->np : nullptr;
       if (s->d_hist)
         TPM_HIP(launch_history_rows(s->hist(), srow, ks + 1, s->step + begin(c), dt, vs, s->sE));
       else
@@ -1000,7 +1050,7 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
       int rc = enqueue_eph(c + NSLOT - 1);
       if (rc) return rc;
       TPM_HIP(hipStreamWaitEvent(s->sP, s->ev_eph[slot], 0));
-      rows = s->d_ring + (size_t)slot * s->ring_rows * rl;
+      rows = s->d_ring + (size_t)row_slot(c) * s->ring_rows * rl;
     }
     {
       int rc = poll_counts();
@@ -1050,15 +1100,27 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
     }
     if (ho) {
       // particles handed off in this chunk join the encounter list, which the
-      // encounter stream advances through the chunk's steps while the particle
-      // stream goes on with the next chunk
+      // encounter stream advances towards the chunk's end while the particle
+      // stream goes on: a budget of micro-steps per entry (the chunk's length)
+      // keeps each launch about as long as a particle launch, and an entry
+      // left behind is resumed by the next launch; the call's last launch
+      // takes every entry to the end
       TPM_HIP(launch_handoff_gather(s->work[s->cur], s->d_nactive, n_grid, s->enc, step0,
-                                    s->d_snap + slot, s->sP));
+                                    s->d_snap + c, s->sP));
       TPM_HIP(hipEventRecord(s->ev_gath[slot], s->sP));
       TPM_HIP(hipStreamWaitEvent(sH, s->ev_gath[slot], 0));
-      TPM_HIP(launch_encounter_chunk(S, rrem2, s->enc, s->d_snap + slot, (int)s->n, rows,
-                                     s->d_vring + (size_t)slot * s->vring_rows * 3 * s->np, ks,
-                                     dt, step0, s->opt.handoff_substeps, s->out, sH));
+      EncRing ER;
+      ER.rows = s->d_ring;
+      ER.vrows = s->d_vring;
+      ER.ring_rows = s->ring_rows;
+      ER.vring_rows = s->vring_rows;
+      ER.k0 = K0;
+      ER.k = K;
+      ER.nsteps = nsteps;
+      ER.step0 = s->step;
+      const int64_t budget = (c == nchunks - 1) ? 0 : (int64_t)K;
+      TPM_HIP(launch_encounter_run(S, rrem2, s->enc, s->d_snap + c, (int)s->n, ER, begin(c + 1),
+                                   budget, dt, s->opt.handoff_substeps, s->out, sH));
       TPM_HIP(hipEventRecord(s->ev_hdone[slot], sH));
     }
     TPM_HIP(hipEventRecord(s->ev_done[slot], s->sP));
