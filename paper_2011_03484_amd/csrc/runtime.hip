@@ -256,13 +256,14 @@ struct tpm_sim {
   } diag;
   double* d_vside = nullptr;             // [NSLOT][2][np][3] planet velocities at chunk ends
   // close-encounter hand-off: removal radii (internal order), the encounter
-  // list (capacity n), per-slot list lengths, the planets' velocities per row
-  // of every ring slot, and the events ordering the encounter stream
+  // list (capacity n), the list's length after each chunk's hand-offs, the
+  // planets' velocities per row of every ring slot, and the events ordering
+  // the encounter stream
   std::vector<double> rrem_s;
   bool rrem_set = false;
   EncList enc{};
-  int32_t* d_snap = nullptr;             // [NSLOT]
-  double* d_vring = nullptr;             // [slots][ring_rows][np][3]
+  int32_t* d_snap = nullptr;             // [chunks of the call]
+  double* d_vring = nullptr;             // [slots][vring_rows][np][3]
   int64_t vring_rows = 0, vring_slots = 0;
   int vring_np = -1;                     // planets the velocity ring was sized for
   int64_t snap_slots = 0;                // entries of d_snap
