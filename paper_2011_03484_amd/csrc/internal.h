@@ -111,6 +111,8 @@ struct QueueLaunch {
   int workers;                 // wavefronts launched
   int block;                   // threads per workgroup (multiple of 64)
   int32_t* error;              // device flag set on an over-long wait
+  bool deep = false;           // planet rows fetched two steps ahead, not one (for
+                               // launches of one wavefront per SIMD)
 };
 
 // Particle chunk: nsteps steps through rows[0..nsteps] (row 0 = step0) over

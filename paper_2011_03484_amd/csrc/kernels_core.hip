@@ -35,13 +35,14 @@ struct ChunkArgs {
 // chunk are written before the launch).  The step loop is uniform across the
 // wavefront (s_begin, s_end are wave-uniform); removed lanes are masked off
 // and the wavefront leaves early once none is active.  KIT > 0 fixes the
-// Newton count at compile time; PREFETCH fetches each planet row a step
-// ahead into VGPRs (for launches with about one wavefront per SIMD).
+// Newton count at compile time; DEPTH > 0 fetches each planet row DEPTH
+// steps ahead into VGPRs (for launches with a few wavefronts per SIMD; 0:
+// scalar loads at the point of use, for many).
 //
 // UNIV: a drift the fixed-iteration solve refuses is taken in universal
 // variables instead (drift_universal); the particle is removed as KEPLER only
 // if that gives no finite result either.
-template <int NP, int KIT, bool PREFETCH, bool UNIV = false>
+template <int NP, int KIT, int DEPTH, bool UNIV = false>
 TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const ChunkArgs<NP>& A,
                      int i, bool valid, int s_begin, int s_end) {
   constexpr int ROW = 3 * NP + 3;
@@ -118,11 +119,10 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
   auto all_removed = [&](int s) {
     return ((s - s_begin) & 7) == 0 && wave_all(reason != ST_ACTIVE);
   };
-  if (PREFETCH) {
+  if (DEPTH == 1) {
     // The row that ends step s is fetched during step s - 1, into the one of
-    // two alternating VGPR buffers that step s - 1 does not use: with one
-    // wavefront per SIMD (the usual case once removals have thinned the
-    // working set) nothing else hides that load's latency.
+    // two alternating VGPR buffers that step s - 1 does not use: with few
+    // wavefronts per SIMD nothing else hides that load's latency.
     const int zero = opaque_zero_vgpr();
     Row<NP> ra, rb;
     load_row<NP>(ra, rows + (size_t)(s_begin + 1) * ROW, zero);
@@ -133,6 +133,25 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
       if (s + 1 >= s_end) break;
       load_row<NP>(ra, rows + (size_t)min(s + 3, s_end) * ROW, zero);
       step(s + 1, rb.v);
+    }
+  } else if (DEPTH == 2) {
+    // Two steps ahead, three buffers in turn: with one wavefront per SIMD
+    // the particles run right behind the planet map, and a row just written
+    // on another die can take longer than one step to arrive.
+    const int zero = opaque_zero_vgpr();
+    Row<NP> ra, rb, rc;
+    load_row<NP>(ra, rows + (size_t)(s_begin + 1) * ROW, zero);
+    load_row<NP>(rb, rows + (size_t)min(s_begin + 2, s_end) * ROW, zero);
+    for (int s = s_begin; s < s_end; s += 3) {
+      if (all_removed(s)) break;
+      load_row<NP>(rc, rows + (size_t)min(s + 3, s_end) * ROW, zero);
+      step(s, ra.v);
+      if (s + 1 >= s_end) break;
+      load_row<NP>(ra, rows + (size_t)min(s + 4, s_end) * ROW, zero);
+      step(s + 1, rb.v);
+      if (s + 2 >= s_end) break;
+      load_row<NP>(rb, rows + (size_t)min(s + 5, s_end) * ROW, zero);
+      step(s + 2, rc.v);
     }
   } else {
     // many wavefronts per SIMD: rows by scalar loads at their use
@@ -175,7 +194,7 @@ TPM_DEV unsigned long long wave_uniform(unsigned long long v) {
 // and the publish are executed by the whole wavefront (lane 0 alone adds 1 to
 // the counter), so the readfirstlane that makes their results wave-uniform
 // always sees the full wavefront and the loop's branches stay scalar.
-template <int NP, int KIT, bool UNIV>
+template <int NP, int KIT, bool UNIV, int DEPTH>
 __global__ void __launch_bounds__(256)
 particle_queue(Work w, const int32_t* __restrict__ d_nactive, Out out,
                const double* __restrict__ rows, ChunkArgs<NP> A, QueueArgs Q) {
@@ -212,7 +231,7 @@ particle_queue(Work w, const int32_t* __restrict__ d_nactive, Out out,
     const int s_end = min(Q.nsteps, s_begin + Q.sub_steps);
     if (go && s_begin < s_end) {       // the last sub-chunks of a short chunk may be empty
       const int i = t * 64 + lane;
-      advance<NP, KIT, true, UNIV>(w, out, rows, A, i, i < n, s_begin, s_end);
+      advance<NP, KIT, DEPTH, UNIV>(w, out, rows, A, i, i < n, s_begin, s_end);
     }
     // publish completion; the release orders every store of this item
     __hip_atomic_store(Q.progress + t, Q.epoch + (uint32_t)s + 1u, __ATOMIC_RELEASE,
@@ -246,9 +265,9 @@ TPM_DEV void batch_item(const SysDev& S, Work w, Out out, const double* __restri
   const int i = T.first + lane;
   const bool valid = lane < T.count;
   if (S.kiters == 5)
-    advance<NP, 5, false>(w, out, rows, A, i, valid, s_begin, s_end);
+    advance<NP, 5, 0>(w, out, rows, A, i, valid, s_begin, s_end);
   else
-    advance<NP, 0, false>(w, out, rows, A, i, valid, s_begin, s_end);
+    advance<NP, 0, 0>(w, out, rows, A, i, valid, s_begin, s_end);
 }
 
 __global__ void __launch_bounds__(256)
@@ -422,15 +441,19 @@ static hipError_t launch_np(const SysConst& S, Work w, const int32_t* d_nactive,
   if (Q.ntiles <= 0) return hipSuccess;
   const int waves_per_block = QL.block / 64;
   const int nblocks = (QL.workers + waves_per_block - 1) / waves_per_block;
-  if (S.universal)
-    hipLaunchKernelGGL((particle_queue<NP, 0, true>), dim3(nblocks), dim3(QL.block), 0, st, w,
-                       d_nactive, out, rows, A, Q);
-  else if (S.kiters == 5)
-    hipLaunchKernelGGL((particle_queue<NP, 5, false>), dim3(nblocks), dim3(QL.block), 0, st, w,
-                       d_nactive, out, rows, A, Q);
-  else
-    hipLaunchKernelGGL((particle_queue<NP, 0, false>), dim3(nblocks), dim3(QL.block), 0, st, w,
-                       d_nactive, out, rows, A, Q);
+#define TPM_PQ(KIT, UNIV, DEPTH)                                                              \
+  hipLaunchKernelGGL((particle_queue<NP, KIT, UNIV, DEPTH>), dim3(nblocks), dim3(QL.block), 0, st, \
+                     w, d_nactive, out, rows, A, Q)
+  if (QL.deep) {
+    if (S.universal) TPM_PQ(0, true, 2);
+    else if (S.kiters == 5) TPM_PQ(5, false, 2);
+    else TPM_PQ(0, false, 2);
+  } else {
+    if (S.universal) TPM_PQ(0, true, 1);
+    else if (S.kiters == 5) TPM_PQ(5, false, 1);
+    else TPM_PQ(0, false, 1);
+  }
+#undef TPM_PQ
   return hipGetLastError();
 }
 

@@ -307,6 +307,7 @@ extern "C" int tpm_integrate_static(const tpm_options* opt_in, double mu0, int32
       QL.nsub = std::max(1, std::min(o.sub_chunks, (ks + item - 1) / item));
       const int wps = o.waves_per_simd > 0 ? o.waves_per_simd : auto_waves_per_simd(ntiles, D.ncu);
       QL.workers = std::max(1, std::min(ntiles * QL.nsub, 4 * D.ncu * wps));
+      QL.deep = wps == 1;
       QL.workers = std::min(QL.workers, ntiles);
       QL.block = o.block_threads;
       QL.error = &misc->qerr;
