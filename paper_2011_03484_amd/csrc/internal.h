@@ -111,7 +111,7 @@ struct QueueLaunch {
   int workers;                 // wavefronts launched
   int block;                   // threads per workgroup (multiple of 64)
   int32_t* error;              // device flag set on an over-long wait
-  bool deep = false;           // planet rows fetched two steps ahead, not one (for
+  bool deep = false;           // planet rows fetched three steps ahead, not one (for
                                // launches of one wavefront per SIMD)
 };
 

@@ -134,24 +134,28 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
       load_row<NP>(ra, rows + (size_t)min(s + 3, s_end) * ROW, zero);
       step(s + 1, rb.v);
     }
-  } else if (DEPTH == 2) {
-    // Two steps ahead, three buffers in turn: with one wavefront per SIMD
+  } else if (DEPTH == 3) {
+    // Three steps ahead, four buffers in turn: with one wavefront per SIMD
     // the particles run right behind the planet map, and a row just written
-    // on another die can take longer than one step to arrive.
+    // on another die can take longer than a step to arrive.
     const int zero = opaque_zero_vgpr();
-    Row<NP> ra, rb, rc;
+    Row<NP> ra, rb, rc, rd;
     load_row<NP>(ra, rows + (size_t)(s_begin + 1) * ROW, zero);
     load_row<NP>(rb, rows + (size_t)min(s_begin + 2, s_end) * ROW, zero);
-    for (int s = s_begin; s < s_end; s += 3) {
+    load_row<NP>(rc, rows + (size_t)min(s_begin + 3, s_end) * ROW, zero);
+    for (int s = s_begin; s < s_end; s += 4) {
       if (all_removed(s)) break;
-      load_row<NP>(rc, rows + (size_t)min(s + 3, s_end) * ROW, zero);
+      load_row<NP>(rd, rows + (size_t)min(s + 4, s_end) * ROW, zero);
       step(s, ra.v);
       if (s + 1 >= s_end) break;
-      load_row<NP>(ra, rows + (size_t)min(s + 4, s_end) * ROW, zero);
+      load_row<NP>(ra, rows + (size_t)min(s + 5, s_end) * ROW, zero);
       step(s + 1, rb.v);
       if (s + 2 >= s_end) break;
-      load_row<NP>(rb, rows + (size_t)min(s + 5, s_end) * ROW, zero);
+      load_row<NP>(rb, rows + (size_t)min(s + 6, s_end) * ROW, zero);
       step(s + 2, rc.v);
+      if (s + 3 >= s_end) break;
+      load_row<NP>(rc, rows + (size_t)min(s + 7, s_end) * ROW, zero);
+      step(s + 3, rd.v);
     }
   } else {
     // many wavefronts per SIMD: rows by scalar loads at their use
@@ -445,9 +449,9 @@ static hipError_t launch_np(const SysConst& S, Work w, const int32_t* d_nactive,
   hipLaunchKernelGGL((particle_queue<NP, KIT, UNIV, DEPTH>), dim3(nblocks), dim3(QL.block), 0, st, \
                      w, d_nactive, out, rows, A, Q)
   if (QL.deep) {
-    if (S.universal) TPM_PQ(0, true, 2);
-    else if (S.kiters == 5) TPM_PQ(5, false, 2);
-    else TPM_PQ(0, false, 2);
+    if (S.universal) TPM_PQ(0, true, 3);
+    else if (S.kiters == 5) TPM_PQ(5, false, 3);
+    else TPM_PQ(0, false, 3);
   } else {
     if (S.universal) TPM_PQ(0, true, 1);
     else if (S.kiters == 5) TPM_PQ(5, false, 1);
