@@ -97,7 +97,9 @@ typedef struct {
    * removed but handed off to a secondary kernel that integrates the list of
    * such particles behind the main kernel, on a stream of its own (the call
    * keeps all its planet rows for it: (chunk_steps + 1) x (6 Np + 3) x 8
-   * bytes per chunk, a call needing more than 4 GiB runs as several):
+   * bytes per chunk; a call needing more than 4 GiB, or than the environment
+   * variable TPM_HANDOFF_RING_BYTES says, runs as several, with no change of
+   * result):
    * at every step boundary a particle within the hand-off radius of any
    * planet takes its next step as M equal substeps of the same kick - drift -
    * kick, with the planets between the two table rows on the cubic Hermite

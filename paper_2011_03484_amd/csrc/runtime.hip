@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <deque>
 #include <map>
 #include <memory>
@@ -89,10 +90,21 @@ hipError_t ensure_device_streams(DeviceStreams& D) {
 constexpr int NSLOT = 8;   // planet-table ring slots
 constexpr int FIRST_CHUNK_STEPS = 1024;   // longest first chunk of an on-the-fly run
 // With the close-encounter hand-off an integrate call keeps all its planet
-// rows (and planet velocities); a call that would need more than this is run
-// as several calls (survivors of the encounter list rejoin the working set at
-// each one's end, which changes no result).
+// rows (and planet velocities); a call that would need more than this (the
+// environment variable TPM_HANDOFF_RING_BYTES may set it) is run as several
+// calls (survivors of the encounter list rejoin the working set at each one's
+// end, which changes no result).
 constexpr int64_t HANDOFF_RING_BYTES = int64_t(4) << 30;
+
+int64_t handoff_ring_bytes() {
+  const char* e = std::getenv("TPM_HANDOFF_RING_BYTES");
+  if (e && *e) {
+    char* end = nullptr;
+    const long long v = std::strtoll(e, &end, 10);
+    if (end && *end == '\0' && v > 0) return (int64_t)v;
+  }
+  return HANDOFF_RING_BYTES;
+}
 constexpr int NCNT = 8;    // in-flight active-count readbacks
 
 template <class T>
@@ -853,7 +865,7 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
   if (s->opt.handoff_substeps > 0 && !s->d_table && !s->d_hist) {
     const int64_t K = s->opt.chunk_steps;
     const int64_t per_slot = (K + 1) * (3 * s->np + 3 + 3 * std::max(s->np, 1)) * 8;
-    const int64_t max_slots = std::max<int64_t>(2, HANDOFF_RING_BYTES / per_slot);
+    const int64_t max_slots = std::max<int64_t>(2, handoff_ring_bytes() / per_slot);
     const int64_t seg = std::min<int64_t>(K, FIRST_CHUNK_STEPS) + (max_slots - 1) * K;
     if (nsteps > seg) {
       tpm_stats agg = s->stats;

@@ -235,6 +235,31 @@ def test_handoff_split_calls_are_bitwise(tpm):
     assert a.stats()["step"] == b.stats()["step"] == 3000
 
 
+def test_handoff_long_call_runs_in_pieces(tpm, monkeypatch):
+    """A call whose planet rows exceed the hand-off ring's budget (set low
+    through TPM_HANDOFF_RING_BYTES: 18 chunks of 256 steps) runs as several
+    calls: the same particles, planets and step count, bit for bit, as with
+    the default budget, and the statistics add up over the pieces."""
+    w = _workload(2048, 89)
+    rrem = np.full(w.np_, 0.05)
+    T = 10_000
+    print(f"[pieces] n={w.n} T={T}", flush=True)
+    a = _sim(tpm, w, w.rcrit, rrem, handoff_substeps=8, chunk_steps=256)
+    a.integrate(T, w.dt)
+    monkeypatch.setenv("TPM_HANDOFF_RING_BYTES", str(1 << 20))
+    b = _sim(tpm, w, w.rcrit, rrem, handoff_substeps=8, chunk_steps=256)
+    b.integrate(T, w.dt)
+    pa, pb = a.particles(), b.particles()
+    sa, sb = a.stats(), b.stats()
+    print(f"handoffs {sa['handoffs']} / in pieces {sb['handoffs']}, chunks {sa['chunks']} / "
+          f"{sb['chunks']}", flush=True)
+    for k in KEYS:
+        assert np.array_equal(pa[k], pb[k]), k
+    assert np.array_equal(a.planets()[0], b.planets()[0])
+    assert sb["step"] == T and sb["handoffs"] >= sa["handoffs"] > 50
+    assert sb["active_particle_steps"] == sa["active_particle_steps"]
+
+
 def test_handoff_does_not_depend_on_tuning(tpm):
     """The hand-off run is the same bit for bit under other work-queue shapes,
     chunk lengths and compaction intervals (the chunks decide when the
