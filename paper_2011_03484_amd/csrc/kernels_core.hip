@@ -449,13 +449,21 @@ static hipError_t launch_np(const SysConst& S, Work w, const int32_t* d_nactive,
   hipLaunchKernelGGL((particle_queue<NP, KIT, UNIV, DEPTH>), dim3(nblocks), dim3(QL.block), 0, st, \
                      w, d_nactive, out, rows, A, Q)
   if (QL.deep) {
-    if (S.universal) TPM_PQ(0, true, 3);
-    else if (S.kiters == 5) TPM_PQ(5, false, 3);
-    else TPM_PQ(0, false, 3);
+    if (S.kiters == 5) {
+      if (S.universal) TPM_PQ(5, true, 3);
+      else TPM_PQ(5, false, 3);
+    } else {
+      if (S.universal) TPM_PQ(0, true, 3);
+      else TPM_PQ(0, false, 3);
+    }
   } else {
-    if (S.universal) TPM_PQ(0, true, 1);
-    else if (S.kiters == 5) TPM_PQ(5, false, 1);
-    else TPM_PQ(0, false, 1);
+    if (S.kiters == 5) {
+      if (S.universal) TPM_PQ(5, true, 1);
+      else TPM_PQ(5, false, 1);
+    } else {
+      if (S.universal) TPM_PQ(0, true, 1);
+      else TPM_PQ(0, false, 1);
+    }
   }
 #undef TPM_PQ
   return hipGetLastError();

@@ -1092,7 +1092,7 @@ int tpm_integrate(tpm_sim* s, int64_t nsteps, double dt) {
                                                  : auto_waves_per_simd(ntiles, s->ncu);
       s->last_wps = wps;
       QL.workers = std::max(1, std::min(ntiles * QL.nsub, 4 * s->ncu * wps));
-      QL.deep = wps == 1;
+      QL.deep = wps == 1 && !ho;
       QL.workers = std::min(QL.workers, ntiles);
       QL.block = s->opt.block_threads;
       QL.error = s->d_qerr;
