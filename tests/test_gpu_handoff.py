@@ -235,6 +235,35 @@ def test_handoff_split_calls_are_bitwise(tpm):
     assert a.stats()["step"] == b.stats()["step"] == 3000
 
 
+def test_handoff_continues_from_a_state_blob(tpm):
+    """A hand-off run continued in a new simulation from tpm_get_state /
+    tpm_set_state (removal radii set again, as set_state clears them) equals
+    the uninterrupted run bit for bit."""
+    w = _workload(2048, 90)
+    rrem = np.full(w.np_, 0.05)
+    print(f"[state] n={w.n}", flush=True)
+    a = _sim(tpm, w, w.rcrit, rrem, handoff_substeps=8, chunk_steps=512)
+    a.integrate(2600, w.dt)
+    b = _sim(tpm, w, w.rcrit, rrem, handoff_substeps=8, chunk_steps=512)
+    b.integrate(1100, w.dt)
+    blob = b.get_state()
+    b.close()
+    c = tpm.Simulation(r_escape=w.rmax, kepler_iters=w.kepler_iters, handoff_substeps=8,
+                       chunk_steps=512)
+    c.set_state(blob)
+    with pytest.raises(tpm.TpmError) as e:
+        c.integrate(10, w.dt)                       # the removal radii went with set_state
+    assert e.value.code == tpm.TPM_ESTATE
+    c.set_removal_radii(rrem)
+    c.integrate(1500, w.dt)
+    pa, pc = a.particles(), c.particles()
+    assert a.stats()["handoffs"] > 20
+    for k in KEYS:
+        assert np.array_equal(pa[k], pc[k]), k
+    assert np.array_equal(a.planets()[0], c.planets()[0])
+    assert c.stats()["step"] == 2600
+
+
 def test_handoff_long_call_runs_in_pieces(tpm, monkeypatch):
     """A call whose planet rows exceed the hand-off ring's budget (set low
     through TPM_HANDOFF_RING_BYTES: 18 chunks of 256 steps) runs as several
