@@ -763,25 +763,36 @@ def test_ragged_and_empty_particle_sets(tpm, orc, n):
     _compare(g, res, near, spread, f"ragged/{n}")
 
 
-def test_eight_planets_single_system(tpm, orc):
-    """The largest planet count (8) on the single-system path: planet table and
-    particles against the oracle."""
-    rng = np.random.default_rng(88)
+# An eight-planet system (semi-major axes and masses of the Sun's planets,
+# e < 0.05, i < 0.03 rad); the planet-count cases below take subsets of it.
+EIGHT_A = np.array([0.4, 0.7, 1.0, 1.5, 5.2, 9.5, 19.2, 30.1])
+EIGHT_MU = np.array([1.7e-7, 2.4e-6, 3.0e-6, 3.2e-7, 9.5e-4, 2.9e-4, 4.4e-5, 5.2e-5])
+
+
+def _planet_subset_run(tpm, orc, idx, label, seed=88):
+    """Planets EIGHT_*[idx] and 700 particles at 2-4.5 au (e, i < 0.1) for 800
+    steps of about 1/30 of the innermost period of the eight: planet table and
+    particles of the single-system path against the oracle."""
+    rng = np.random.default_rng(seed)
     mu0 = W.MU_SUN
-    a = np.array([0.4, 0.7, 1.0, 1.5, 5.2, 9.5, 19.2, 30.1])
-    mu = np.array([1.7e-7, 2.4e-6, 3.0e-6, 3.2e-7, 9.5e-4, 2.9e-4, 4.4e-5, 5.2e-5]) * mu0
-    rp, vp = W.elements_to_cartesian(mu0 + mu, a, rng.uniform(0, 0.05, 8), rng.uniform(0, 0.03, 8),
-                                     rng.uniform(0, 2 * math.pi, 8), rng.uniform(0, 2 * math.pi, 8),
-                                     rng.uniform(0, 2 * math.pi, 8))
+    a8 = EIGHT_A
+    mu8 = EIGHT_MU * mu0
+    rp8, vp8 = W.elements_to_cartesian(mu0 + mu8, a8, rng.uniform(0, 0.05, 8),
+                                       rng.uniform(0, 0.03, 8), rng.uniform(0, 2 * math.pi, 8),
+                                       rng.uniform(0, 2 * math.pi, 8),
+                                       rng.uniform(0, 2 * math.pi, 8))
+    idx = np.asarray(idx)
+    mu, rp, vp, a = mu8[idx], rp8[idx], vp8[idx], a8[idx]
     n = 700
     ar = rng.uniform(2.0, 4.5, n)
     r, v = W.elements_to_cartesian(np.full(n, mu0), ar, rng.uniform(0, 0.1, n),
                                    rng.uniform(0, 0.1, n), rng.uniform(0, 2 * math.pi, n),
                                    rng.uniform(0, 2 * math.pi, n), rng.uniform(0, 2 * math.pi, n))
     rcrit = W.hill_radius(mu0, mu, a)
-    dt = 0.4 / 365.25 * 20          # 1/30 of the innermost period, roughly
+    dt = 0.4 / 365.25 * 20
     T = 800
-    w = W.Workload("eight", mu0, mu, rp, vp, rcrit, 100.0, r, v, dt, T)
+    w = W.Workload(label, mu0, mu, rp, vp, rcrit, 100.0, r, v, dt, T)
+    print(f"[{label}] planets {idx.tolist()}", flush=True)
     s = _sim(tpm, w)
     table = s.planet_table(T, dt)
     eph = orc.ephemeris(mu0, mu, rp, vp, T, dt)
@@ -791,7 +802,22 @@ def test_eight_planets_single_system(tpm, orc):
     s.integrate(T, dt)
     g = s.particles()
     res, near, spread = _oracle_reference(orc, w, T, eph.table)
-    _compare(g, res, near, spread, "eight_planets")
+    _compare(g, res, near, spread, label)
+
+
+def test_eight_planets_single_system(tpm, orc):
+    """The largest planet count (8) on the single-system path: planet table and
+    particles against the oracle."""
+    _planet_subset_run(tpm, orc, range(8), "eight_planets")
+
+
+@pytest.mark.parametrize("idx", [(4, 5), (4, 5, 6), (0, 1, 2, 4, 5), (0, 1, 2, 3, 4, 5),
+                                 (0, 1, 2, 3, 4, 5, 6)])
+def test_planet_counts_single_system(tpm, orc, idx):
+    """Every other planet count from 2 to 7 on the single-system path (its
+    planet map and particle kernel are compiled per count): planet table and
+    particles against the oracle."""
+    _planet_subset_run(tpm, orc, idx, f"planets_{len(idx)}")
 
 
 def test_planet_order_is_the_callers(tpm):
