@@ -51,6 +51,14 @@ PMC_PASSES = {
 }
 PMC_BENCH_ARGS = ("--nsteps 20000 --steps 1 --warmup 0 --no-cpu --no-adjoint --no-batched "
                   "--no-resonant --no-handoff --copy-calibration-mb 256")
+# The resonant workload's counter pass: a 1,024-particle headline run (another
+# kernel variant, left out) and 20,000 steps of the resonant workload.
+RES_COUNTERS_JSON = os.path.join(ROOT, "profiles", "particle_queue_resonant_200k_counters.json")
+RES_COUNTERS_MD = os.path.join(ROOT, "profiles", "particle_queue_resonant_200k_counters.md")
+RES_PMC = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 "
+           "SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU_FLOPS_FP64")
+RES_PMC_BENCH_ARGS = ("--nsteps 1024 --n 1024 --steps 1 --warmup 0 --no-cpu --no-adjoint "
+                      "--no-batched --no-handoff --resonant-steps 20000")
 
 
 def kernel_source_hash() -> str:
@@ -70,12 +78,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def counter_figures():
+def counter_figures(path: str = COUNTERS_JSON):
     """Per active particle-step figures of the committed counter runs (executed
     FP64 flops; calibrated HBM bytes), or None unless they were taken on the
     current kernel sources."""
     try:
-        d = json.load(open(COUNTERS_JSON))
+        d = json.load(open(path))
     except (OSError, ValueError):
         return None
     return d if d.get("source_hash") == kernel_source_hash() else None
@@ -200,6 +208,61 @@ def summarize_counters(pmc_dir: str) -> None:
               open(COUNTERS_JSON, "w"), indent=1)
     print("\n".join(out[-6:]))
     summarize_ephemeris(pmc_dir, tot, cnt, steps, src)
+
+
+def summarize_resonant_counters(pmc_dir: str) -> None:
+    """Write the resonant workload's counter summary (markdown) and its executed
+    FP64 flops per active particle-step (json) from the rocprofv3 pass in
+    pmc_dir/r1, made by `rocprofv3 --pmc <RES_PMC> --kernel-trace -f csv -d
+    <pmc_dir>/r1 -o run -- python3 bench.py <RES_PMC_BENCH_ARGS>` with its
+    output in <pmc_dir>/r1.log.  The resonant run's particle launches are the
+    kernel variant with a one-step row prefetch (several wavefronts per SIMD);
+    the small headline run before it uses the three-step one."""
+    import collections
+    import csv
+    res_kernel = "particle_queue<4, 5, false, 1>"
+    tot = collections.Counter()
+    launches = 0
+    for r in csv.DictReader(open(os.path.join(pmc_dir, "r1", "run_counter_collection.csv"))):
+        if res_kernel in r["Kernel_Name"]:
+            tot[r["Counter_Name"]] += float(r["Counter_Value"])
+            if r["Counter_Name"] == "SQ_WAVES":
+                launches += 1
+    kt = 0.0
+    for r in csv.DictReader(open(os.path.join(pmc_dir, "r1", "run_kernel_trace.csv"))):
+        if res_kernel in r["Kernel_Name"]:
+            kt += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    run = json.loads([x for x in open(os.path.join(pmc_dir, "r1.log")) if x.startswith("{")][-1])
+    src = run["kernel_sources"]
+    aps = run["resonant"]["active_particle_steps"]
+    steps = int(RES_PMC_BENCH_ARGS.split()[-1])
+    per = lambda c: 64 * tot[c] / aps
+    fpps = per("SQ_INSTS_VALU_FLOPS_FP64")
+    rate = fpps * aps / kt / 1e12
+    out = [f"# particle_queue<4,5> counters -- resonant_200k, 200,000 particles x {steps:,} steps "
+           f"({launches} launches)", "",
+           "Command (`cd /tmp && export TMPDIR=/tmp` first), then `python3 bench.py "
+           "--summarize-resonant-counters <out>` for this summary:", "",
+           f"    timeout -s KILL 120 rocprofv3 --pmc {RES_PMC} --kernel-trace -f csv -d <out>/r1 "
+           f"-o run -- python3 <repo>/bench.py {RES_PMC_BENCH_ARGS} > <out>/r1.log", "",
+           f"Kernel sources of the counted run: `bench.kernel_source_hash()` = `{src}`.", "",
+           f"Sums over the resonant run's {launches} particle launches ({res_kernel}; the "
+           "1,024-particle headline run before it uses another variant and is left out), from "
+           "`run_counter_collection.csv`:", "", "| counter | value |", "|---|---|"]
+    for c, v in tot.items():
+        out.append(f"| {c} | {v:.6g} |")
+    out += ["", f"Derived ({aps:,} active particle-steps; kernel-trace time {kt * 1e3:.1f} ms):", "",
+            f"* Executed FP64 per active particle-step (64 x instructions / particle-steps): "
+            f"{per('SQ_INSTS_VALU_FMA_F64'):.1f} FMA, {per('SQ_INSTS_VALU_MUL_F64'):.1f} mul, "
+            f"{per('SQ_INSTS_VALU_ADD_F64'):.1f} add, {per('SQ_INSTS_VALU_TRANS_F64'):.1f} "
+            f"transcendental; flops (FMA = 2) {fpps:.1f}.",
+            f"* FP64 rate under the profiler: {fpps:.1f} x {aps:.4g} / {kt * 1e3:.1f} ms = "
+            f"{rate:.1f} TFLOP/s = {rate / FP64_PEAK_TFLOPS * 100:.0f}% of {FP64_PEAK_TFLOPS}."]
+    open(RES_COUNTERS_MD, "w").write("\n".join(out) + "\n")
+    json.dump({"kernel": "particle_queue<4,5>", "workload": f"resonant_200k, {steps} steps",
+               "source_hash": src, "flops_per_particle_step": fpps,
+               "summary": os.path.basename(RES_COUNTERS_MD)}, open(RES_COUNTERS_JSON, "w"), indent=1)
+    print("\n".join(out[-3:]))
 
 
 def summarize_ephemeris(pmc_dir: str, tot, cnt, steps: int, src: str) -> None:
@@ -555,14 +618,24 @@ def resonant_run(P, W, torch, nsteps: int):
     secs = time.perf_counter() - t0
     st = s.stats()
     s.close()
+    kernel_rate = st["active_particle_steps"] / (st["particle_kernel_ms"] / 1e3)
+    cf = counter_figures(RES_COUNTERS_JSON)
+    executed = None
+    if cf:
+        tf = cf["flops_per_particle_step"] * kernel_rate / 1e12
+        executed = {"flops_per_particle_step": cf["flops_per_particle_step"], "tflops": tf,
+                    "frac": tf / FP64_PEAK_TFLOPS,
+                    "source": "SQ_INSTS_VALU_FLOPS_FP64 of the committed counter run of this "
+                              "workload on the same kernel sources, per active particle-step, over "
+                              "this run's particle-kernel time"}
     return {"workload": f"resonant_200k: 200,000 particles, 4 planets, dt = 120 d, {nsteps} steps "
                         f"(the first {nsteps / 1e7:.0%} of its 1e7-step length)",
             "value": st["active_particle_steps"] / secs, "unit": "particle-steps/s",
             "run_ms": secs * 1e3,
-            "particle_steps_per_s_kernels_only": st["active_particle_steps"] / (st["particle_kernel_ms"] / 1e3),
+            "particle_steps_per_s_kernels_only": kernel_rate,
             "active_particle_steps": st["active_particle_steps"],
             "removed_by_reason": st["count_by_reason"][1:], "survivors": st["count_by_reason"][0],
-            "compactions": st["compactions"]}
+            "compactions": st["compactions"], "executed_fp64": executed}
 
 
 def handoff_run(P, W, torch, nsteps: int, substeps: int = 16, r_rem: float = 0.05):
@@ -631,9 +704,15 @@ def main():
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="write the counter summary under profiles/ from rocprofv3 --pmc passes "
                          "p1..p4 in DIR, then exit (no GPU use)")
+    ap.add_argument("--summarize-resonant-counters", metavar="DIR",
+                    help="write the resonant workload's counter summary under profiles/ from the "
+                         "rocprofv3 --pmc pass r1 in DIR, then exit (no GPU use)")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(args.summarize_counters)
+        return
+    if args.summarize_resonant_counters:
+        summarize_resonant_counters(args.summarize_resonant_counters)
         return
     if args.summarize_traces:
         summarize_traces(args.summarize_traces)
