@@ -84,7 +84,11 @@ typedef struct {
   int32_t universal_drift;/* 1: a drift the fixed-iteration solve refuses (unbound or
                              near-parabolic orbit, |F(x_k)| > kepler_ftol) is taken in
                              universal variables instead, and the particle is removed
-                             as TPM_KEPLER only if that gives no finite result; 0 = off */
+                             as TPM_KEPLER only if that gives no finite result; 0 = off.
+                             It applies to tpm_integrate and the hand-off's encounter
+                             integrator; tpm_integrate_static, tpm_batch_integrate and
+                             the derivative calls (tpm_ad_*) take the fixed-iteration
+                             drift alone, whatever this says.                       */
   int32_t sort_by_e;      /* 1: order the working set by decreasing osculating
                              eccentricity bin (bins of 0.1; unbound orbits first), so
                              wavefronts hold particles of similar Newton counts and the
