@@ -352,6 +352,71 @@ def test_removal_special_cases(tpm, orc):
     assert list(g["deact_step"]) == list(ref.deact_step)
 
 
+def _two_body(mu, r0, v0, t):
+    """Exact two-body state at time t from (r0, v0) (elliptic orbits, e > 0),
+    written out from the orbital elements: E - e sin E = M0 + n t, solved by
+    Newton from M, then the perifocal position and velocity; in x87 extended
+    precision (np.longdouble), so that its own rounding stays far below the
+    float64 map's."""
+    L = np.longdouble
+    mu, t = L(mu), L(t)
+    r0, v0 = r0.astype(L), v0.astype(L)
+    rn = np.sqrt(np.sum(r0 * r0, axis=1))
+    h = np.cross(r0, v0)
+    ev = np.cross(v0, h) / mu - r0 / rn[:, None]
+    e = np.sqrt(np.sum(ev * ev, axis=1))
+    a = 1.0 / (2.0 / rn - np.sum(v0 * v0, axis=1) / mu)
+    n = np.sqrt(mu / a ** 3)
+    cosE0 = (1.0 - rn / a) / e
+    sinE0 = np.sum(r0 * v0, axis=1) / (e * np.sqrt(mu * a))
+    E0 = np.arctan2(sinE0, cosE0)
+    twopi = 2 * np.arccos(L(-1))
+    M = np.mod(E0 - e * np.sin(E0) + n * t, twopi)
+    E = M.copy()
+    for _ in range(60):
+        E = E - (E - e * np.sin(E) - M) / (1 - e * np.cos(E))
+    P = ev / e[:, None]
+    Q = np.cross(h, P) / np.sqrt(np.sum(h * h, axis=1))[:, None]
+    b = a * np.sqrt(1.0 - e * e)
+    r = (a * (np.cos(E) - e))[:, None] * P + (b * np.sin(E))[:, None] * Q
+    rr = a * (1.0 - e * np.cos(E))
+    fac = np.sqrt(mu * a) / rr
+    v = (-fac * np.sin(E))[:, None] * P + (fac * np.sqrt(1 - e * e) * np.cos(E))[:, None] * Q
+    return r.astype(np.float64), v.astype(np.float64)
+
+
+def test_no_planets_is_exact_two_body(tpm):
+    """With no planets the map is the Kepler drift alone (zero kicks): after
+    1,000 steps every particle sits on its exact two-body orbit, the closed
+    form evaluated from its orbital elements in extended precision, to 5e-11
+    relative in position and velocity.  That is the rounding of 1,000 float64
+    drifts: the oracle's own run of this case reaches 7.4e-12, and a wrong term
+    of the drift or a wrong sign would be off by orders of magnitude more.
+    Orbits a in [1, 30] au, e in [0.01, 0.5], from 12 to 400 steps per orbit
+    (up to 83 orbits)."""
+    rng = np.random.default_rng(97)
+    mu0 = W.MU_SUN
+    n = 3000
+    r0, v0 = W.elements_to_cartesian(np.full(n, mu0), rng.uniform(1.0, 30.0, n),
+                                     rng.uniform(0.01, 0.5, n), rng.uniform(0, 0.5, n),
+                                     rng.uniform(0, 2 * math.pi, n), rng.uniform(0, 2 * math.pi, n),
+                                     rng.uniform(0, 2 * math.pi, n))
+    dt, T = 0.083, 1000
+    print(f"[two-body] n={n} T={T}", flush=True)
+    s = tpm.Simulation(r_escape=1000.0, kepler_iters=5)
+    s.set_central(mu0)
+    s.set_planets(np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0))
+    s.set_particles(r0, v0)
+    s.integrate(T, dt)
+    g = s.particles()
+    assert np.all(g["reason"] == tpm.ACTIVE)
+    r, v = _two_body(mu0, r0, v0, T * dt)
+    er = np.linalg.norm(g["r"] - r, axis=1) / np.linalg.norm(r, axis=1)
+    ev = np.linalg.norm(g["v"] - v, axis=1) / np.linalg.norm(v, axis=1)
+    print(f"max rel position error {er.max():.3g}, velocity {ev.max():.3g}", flush=True)
+    assert er.max() <= 5e-11 and ev.max() <= 5e-11
+
+
 def test_kepler_failure_removal(tpm, orc):
     """Kepler failures against the oracle (no planets): an e = 0.99 orbit,
     whose five-step solve misses the 1e-13 threshold at a step of 0.05
