@@ -469,6 +469,33 @@ def test_cr3bp_jacobi_constant_bounded_on_gpu(tpm):
     assert np.median(late / early) < 1.5
 
 
+def test_gpu_map_converges_to_direct_nbody_as_dt_squared(tpm):
+    """The GPU path is a second-order map of the Newtonian problem: against an
+    independent direct N-body integration (scipy DOP853 of the barycentric
+    equations, the same one the oracle is pinned to) the position error of
+    planets and particles shrinks about 4x each time dt halves (120 yr at
+    dt = 0.4, 0.2, 0.1 yr)."""
+    from test_oracle_pins import _direct_nbody
+    w = W.giants_100k(n=6, seed=5)
+    t_end = 120.0
+    rx, rpx = _direct_nbody(w.mu0, w.mu, w.rp, w.vp, w.r, w.v, t_end)
+    errs = []
+    for dt in (0.4, 0.2, 0.1):
+        T = int(round(t_end / dt))
+        s = _sim(tpm, w)
+        s.integrate(T, dt)
+        g = s.particles()
+        assert np.all(g["reason"] == tpm.ACTIVE)
+        errs.append((np.max(np.linalg.norm(g["r"] - rx, axis=1)),
+                     np.max(np.linalg.norm(s.planets()[0] - rpx, axis=1))))
+    errs = np.array(errs)
+    print(f"errors (particles, planets) at dt 0.4, 0.2, 0.1: {errs.tolist()}", flush=True)
+    for col in range(2):
+        ratios = errs[:-1, col] / errs[1:, col]
+        assert np.all((ratios > 3.0) & (ratios < 5.5)), (col, errs)
+    assert errs[-1, 0] < 1e-3 and errs[-1, 1] < 1e-3
+
+
 def test_kepler_failure_removal(tpm, orc):
     """Kepler failures against the oracle (no planets): an e = 0.99 orbit,
     whose five-step solve misses the 1e-13 threshold at a step of 0.05
