@@ -134,17 +134,22 @@ def test_one_substep_equals_plain_map(tpm, universal):
     assert np.array_equal(s.planets()[0], ref.planets()[0])
 
 
-@pytest.mark.parametrize("M,universal,permute", [(16, True, False), (4, False, True)])
-def test_handoff_matches_oracle(tpm, orc, M, universal, permute):
+@pytest.mark.parametrize("M,universal,permute,kiters", [(16, True, False, 5), (4, False, True, 5),
+                                                         (8, True, False, 8)])
+def test_handoff_matches_oracle(tpm, orc, M, universal, permute, kiters):
     """M substeps per encounter step against the oracle (hand-off radius
     0.5 au, removal radii 0.03..0.06 au per planet, given in caller order;
-    planets permuted in one case): identical removal records outside the
-    near-threshold set, states within the parity bar, and as many hand-offs
-    as the oracle has particles that reached the hand-off radius."""
+    planets permuted in one case; a Newton count other than the method's five,
+    which runs the kernels that read it at run time, in one): identical
+    removal records outside the near-threshold set, states within the parity
+    bar, and as many hand-offs as the oracle has particles that reached the
+    hand-off radius."""
     w = _workload(4096, 82, permute)
+    w.kepler_iters = kiters
     T = 3000
     rrem = np.array([0.03, 0.04, 0.05, 0.06])
-    print(f"[oracle M={M} universal={universal} permute={permute}] n={w.n} T={T}", flush=True)
+    print(f"[oracle M={M} universal={universal} permute={permute} k={kiters}] n={w.n} T={T}",
+          flush=True)
     s = _sim(tpm, w, w.rcrit, rrem, handoff_substeps=M, chunk_steps=512,
              universal_drift=universal)
     s.integrate(T, w.dt)
