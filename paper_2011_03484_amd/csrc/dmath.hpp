@@ -66,13 +66,24 @@ TPM_DEV double rsqrt(double x) {
 
 // m / x^(3/2) for x > 0 (a force factor m/|d|^3 with x = |d|^2), from the same
 // residual: m y^3 (1 + 3e/2 + 15 e^2/8), e = 1 - x y^2 (measured: at most
-// 2.5 * 2^-53 relative; the cube of rsqrt reaches 6.9 * 2^-53).
-TPM_DEV double mul_rsqrt3(double m, double x) {
+// 2.5 * 2^-53 relative; the cube of rsqrt reaches 6.9 * 2^-53).  c15 is the
+// series' 3/2, which a caller may pass from a register it keeps for the
+// purpose (see vgpr_held; the value, and so the result, is the same).
+TPM_DEV double mul_rsqrt3(double m, double x, double c15 = 1.5) {
   double y = __builtin_amdgcn_rsq(x);
   double y2 = y * y;
   double e = fma_(-x, y2, 1.0);
   double mm = m * (y2 * y);
-  return fma_(mm * e, fma_(e, 1.875, 1.5), mm);
+  return fma_(mm * e, fma_(e, 1.875, c15), mm);
+}
+
+// A value held in a VGPR: the compiler cannot turn it back into a constant.
+// An FP64 instruction reads at most one scalar operand, so a constant that
+// meets another scalar operand in one instruction is otherwise copied into a
+// VGPR at every use.
+TPM_DEV double vgpr_held(double v) {
+  asm volatile("" : "+v"(v));
+  return v;
 }
 
 // m / x^(3/2) with the series truncated after e: relative error below

@@ -30,6 +30,42 @@ struct ChunkArgs {
   int handoff;   // within rcrit: hand off to the encounter integrator, not removal
 };
 
+// The work-queue kernel's leading arguments as its argument segment lays them
+// out (particle_queue: w, d_nactive, out, ...).
+struct QueueArgsHead {
+  Work w;
+  const int32_t* n;
+  Out out;
+};
+typedef const __attribute__((address_space(4))) char* KargPtr;
+
+// The argument segment's address, hidden from the compiler where it is used:
+// a load through it then stays at that use, instead of being hoisted to the
+// kernel's start and its result held in scalar registers throughout.
+TPM_DEV KargPtr karg_at_use(KargPtr p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+// (The host pass of this source compiles no device code from them.)
+TPM_DEV Work karg_work(KargPtr p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *reinterpret_cast<const __attribute__((address_space(4))) Work*>(
+      karg_at_use(p) + offsetof(QueueArgsHead, w));
+#else
+  (void)p;
+  return Work{};
+#endif
+}
+TPM_DEV Out karg_out(KargPtr p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *reinterpret_cast<const __attribute__((address_space(4))) Out*>(
+      karg_at_use(p) + offsetof(QueueArgsHead, out));
+#else
+  (void)p;
+  return Out{};
+#endif
+}
+
 // Advance particle i of the working set through steps [s_begin, s_end) of a
 // chunk whose rows start at `rows` (row k = step step0 + k; all rows of the
 // chunk are written before the launch).  The step loop is uniform across the
@@ -42,11 +78,15 @@ struct ChunkArgs {
 // UNIV: a drift the fixed-iteration solve refuses is taken in universal
 // variables instead (drift_universal); the particle is removed as KEPLER only
 // if that gives no finite result either.
-template <int NP, int KIT, int DEPTH, bool UNIV = false>
+// KA: w and out are read from the work-queue kernel's argument segment ka
+// where they are used (the item's start and end, a record), which leaves the
+// step loop's scalar registers to its constants.
+template <int NP, int KIT, int DEPTH, bool UNIV = false, bool KA = false>
 TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const ChunkArgs<NP>& A,
-                     int i, bool valid, int s_begin, int s_end) {
+                     int i, bool valid, int s_begin, int s_end, KargPtr ka = nullptr) {
   constexpr int ROW = 3 * NP + 3;
   const int kiters = KIT > 0 ? KIT : A.kiters;
+  if (KA) w = karg_work(ka);
   valid = valid && w.status[i] == ST_ACTIVE;
   double x = 0, y = 0, z = 0, vx = 0, vy = 0, vz = 0;
   if (valid) {
@@ -62,20 +102,22 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
   int32_t reason = valid ? ST_ACTIVE : -1;
   auto record = [&](int32_t why, int64_t st, int32_t pl, double rx, double ry, double rz,
                     double ux, double uy, double uz) {
+    const Work wr = KA ? karg_work(ka) : w;
     if (A.handoff && why == ST_ENCOUNTER) {
-      w.x[i] = rx; w.y[i] = ry; w.z[i] = rz;
-      w.vx[i] = ux; w.vy[i] = uy; w.vz[i] = uz;
+      wr.x[i] = rx; wr.y[i] = ry; wr.z[i] = rz;
+      wr.vx[i] = ux; wr.vy[i] = uy; wr.vz[i] = uz;
       reason = HANDOFF_BASE + (int32_t)(st - A.step0);
-      w.status[i] = reason;
+      wr.status[i] = reason;
       return;
     }
-    const int k = w.slot[i];
-    out.r[3 * k + 0] = rx; out.r[3 * k + 1] = ry; out.r[3 * k + 2] = rz;
-    out.v[3 * k + 0] = ux; out.v[3 * k + 1] = uy; out.v[3 * k + 2] = uz;
-    out.step[k] = st;
-    out.reason[k] = why;
-    out.planet[k] = pl;
-    w.status[i] = why;
+    const Out o = KA ? karg_out(ka) : out;
+    const int k = wr.slot[i];
+    o.r[3 * k + 0] = rx; o.r[3 * k + 1] = ry; o.r[3 * k + 2] = rz;
+    o.v[3 * k + 0] = ux; o.v[3 * k + 1] = uy; o.v[3 * k + 2] = uz;
+    o.step[k] = st;
+    o.reason[k] = why;
+    o.planet[k] = pl;
+    wr.status[i] = why;
     reason = why;
   };
   double ax, ay, az;
@@ -165,8 +207,9 @@ TPM_DEV void advance(Work w, Out out, const double* __restrict__ rows, const Chu
     }
   }
   if (reason == ST_ACTIVE) {
-    w.x[i] = x; w.y[i] = y; w.z[i] = z;
-    w.vx[i] = vx; w.vy[i] = vy; w.vz[i] = vz;
+    const Work we = KA ? karg_work(ka) : w;
+    we.x[i] = x; we.y[i] = y; we.z[i] = z;
+    we.vx[i] = vx; we.vy[i] = vy; we.vz[i] = vz;
   }
 }
 
@@ -235,7 +278,8 @@ particle_queue(Work w, const int32_t* __restrict__ d_nactive, Out out,
     const int s_end = min(Q.nsteps, s_begin + Q.sub_steps);
     if (go && s_begin < s_end) {       // the last sub-chunks of a short chunk may be empty
       const int i = t * 64 + lane;
-      advance<NP, KIT, DEPTH, UNIV>(w, out, rows, A, i, i < n, s_begin, s_end);
+      advance<NP, KIT, DEPTH, UNIV, true>(w, out, rows, A, i, i < n, s_begin, s_end,
+                                          (KargPtr)__builtin_amdgcn_kernarg_segment_ptr());
     }
     // publish completion; the release orders every store of this item
     __hip_atomic_store(Q.progress + t, Q.epoch + (uint32_t)s + 1u, __ATOMIC_RELEASE,
@@ -567,6 +611,7 @@ struct EphLane {
   double kc;                      // coefficient of the kick's Kepler term (see eph_accel)
   double cw;                      // weight of the central term in the lane's own kick
   double nb;                      // 0 on body lanes, 1 elsewhere (keeps an rsqrt finite)
+  double c15;                     // 1.5, held in a VGPR (see vgpr_held)
   KepConst K;                     // Kepler constant mu'_b for the drift
 };
 
@@ -574,6 +619,7 @@ struct EphLane {
 // FMAs (no selects on the lane index inside the step loop).
 template <int NP>
 struct EphW {
+  double cjv[NP + 1];    // mu_k/eta_k on every lane, held in VGPRs (see vgpr_held)
   double wr[NP + 1];     // mu_k/eta_k for 1 <= k < lane, else 0 (own heliocentric position)
   double wa[NP + 1];     // mu_k for k < lane, else 0 (sum_{k<b} mu_k a_k)
   double mul[NP + 1];    // mu_l, 0 for the lane's own body
@@ -586,6 +632,7 @@ TPM_DEV EphW<NP> eph_weights(const EphConst& E, int lane) {
   EphW<NP> W;
 #pragma unroll
   for (int k = 0; k <= NP; ++k) {
+    W.cjv[k] = vgpr_held(E.cj[k]);
     W.wr[k] = (k >= 1 && k < lane) ? E.cj[k] : 0.0;
     W.wa[k] = (k < lane) ? E.mu[k] : 0.0;
     W.mul[k] = (k == lane) ? 0.0 : E.mu[k];
@@ -631,9 +678,9 @@ TPM_DEV void helio_step(const EphConst& E, const EphW<NP>& W, double jx, double 
   for (int b = 1; b <= NP; ++b) {
     px[b] = eph_bcast<ROWB>(jx, b); py[b] = eph_bcast<ROWB>(jy, b); pz[b] = eph_bcast<ROWB>(jz, b);
     hx[b] = px[b] + Rx; hy[b] = py[b] + Ry; hz[b] = pz[b] + Rz;
-    Rx = fma_(E.cj[b], px[b], Rx);
-    Ry = fma_(E.cj[b], py[b], Ry);
-    Rz = fma_(E.cj[b], pz[b], Rz);
+    Rx = fma_(W.cjv[b], px[b], Rx);
+    Ry = fma_(W.cjv[b], py[b], Ry);
+    Rz = fma_(W.cjv[b], pz[b], Rz);
   }
   own_helio<NP>(W, jx, jy, jz, px, py, pz, ox, oy, oz);
 }
@@ -660,12 +707,12 @@ TPM_DEV void eph_accel(const EphConst& E, const EphLane& L, const EphW<NP>& W, d
   for (int l = 1; l <= NP; ++l) {
     double dx = ox - hx[l], dy = oy - hy[l], dz = oz - hz[l];
     double d2 = fma_(dx, dx, fma_(dy, dy, dz * dz));
-    double k = mul_rsqrt3(W.mul[l], d2 + W.self[l]);
+    double k = mul_rsqrt3(W.mul[l], d2 + W.self[l], L.c15);
     px = fma_(-k, dx, px);
     py = fma_(-k, dy, py);
     pz = fma_(-k, dz, pz);
   }
-  const double k0 = mul_rsqrt3(W.mul[0], fma_(ox, ox, fma_(oy, oy, oz * oz)) + W.self[0]);
+  const double k0 = mul_rsqrt3(W.mul[0], fma_(ox, ox, fma_(oy, oy, oz * oz)) + W.self[0], L.c15);
   const double nx = fma_(-k0, ox, px), ny = fma_(-k0, oy, py), nz = fma_(-k0, oz, pz);
   // sum_{k<b} mu_k a_k from the broadcast Newtonian accelerations
   double sx = 0.0, sy = 0.0, sz = 0.0;
@@ -676,7 +723,7 @@ TPM_DEV void eph_accel(const EphConst& E, const EphLane& L, const EphW<NP>& W, d
     sz = fma_(W.wa[k], eph_bcast<ROWB>(nz, k), sz);
   }
   double r2 = fma_(jx, jx, fma_(jy, jy, jz * jz));
-  double kk = mul_rsqrt3(L.kc, r2 + L.nb);
+  double kk = mul_rsqrt3(L.kc, r2 + L.nb, L.c15);
   const double kw = k0 * L.cw;
   // lane 0: jx = ie_prev = 0, so a = n
   ax = fma_(kk, jx, fma_(-sx, L.ie_prev, fma_(-kw, ox, px)));
@@ -787,6 +834,7 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
     if (L.lane == b) { L.mup = E.mup[b]; L.ie_prev = E.inv_eta[b - 1]; }
   L.kc = L.mup;
   L.cw = 1.0;
+  L.c15 = vgpr_held(1.5);
   if (NP >= 1 && L.lane == 1) {
     L.kc = E.mup[1] - E.mu[0];
     L.cw = 0.0;
