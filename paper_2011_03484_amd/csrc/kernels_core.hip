@@ -611,7 +611,7 @@ struct EphLane {
   double kc;                      // coefficient of the kick's Kepler term (see eph_accel)
   double cw;                      // weight of the central term in the lane's own kick
   double nb;                      // 0 on body lanes, 1 elsewhere (keeps an rsqrt finite)
-  double c15;                     // 1.5, held in a VGPR (see vgpr_held)
+  double c15;                     // 1.5 (held in a VGPR by the single-system map)
   KepConst K;                     // Kepler constant mu'_b for the drift
 };
 
@@ -619,7 +619,7 @@ struct EphLane {
 // FMAs (no selects on the lane index inside the step loop).
 template <int NP>
 struct EphW {
-  double cjv[NP + 1];    // mu_k/eta_k on every lane, held in VGPRs (see vgpr_held)
+  double cjv[NP + 1];    // mu_k/eta_k on every lane (see eph_weights)
   double wr[NP + 1];     // mu_k/eta_k for 1 <= k < lane, else 0 (own heliocentric position)
   double wa[NP + 1];     // mu_k for k < lane, else 0 (sum_{k<b} mu_k a_k)
   double mul[NP + 1];    // mu_l, 0 for the lane's own body
@@ -627,12 +627,15 @@ struct EphW {
   double hill2[NP + 1];  // squared mutual Hill radius with body j > lane, else 0
 };
 
-template <int NP>
+// HOLD: the constants that meet a broadcast in one instruction are held in
+// VGPRs (the single-system map, whose broadcasts are scalar); the many-system
+// map broadcasts into VGPRs and keeps them as they are.
+template <int NP, bool HOLD>
 TPM_DEV EphW<NP> eph_weights(const EphConst& E, int lane) {
   EphW<NP> W;
 #pragma unroll
   for (int k = 0; k <= NP; ++k) {
-    W.cjv[k] = vgpr_held(E.cj[k]);
+    W.cjv[k] = HOLD ? vgpr_held(E.cj[k]) : E.cj[k];
     W.wr[k] = (k >= 1 && k < lane) ? E.cj[k] : 0.0;
     W.wa[k] = (k < lane) ? E.mu[k] : 0.0;
     W.mul[k] = (k == lane) ? 0.0 : E.mu[k];
@@ -834,12 +837,12 @@ TPM_DEV void ephemeris_body(const EphConst& E, double* __restrict__ rj, double* 
     if (L.lane == b) { L.mup = E.mup[b]; L.ie_prev = E.inv_eta[b - 1]; }
   L.kc = L.mup;
   L.cw = 1.0;
-  L.c15 = vgpr_held(1.5);
+  L.c15 = ROWB ? 1.5 : vgpr_held(1.5);
   if (NP >= 1 && L.lane == 1) {
     L.kc = E.mup[1] - E.mu[0];
     L.cw = 0.0;
   }
-  const EphW<NP> W = eph_weights<NP>(E, L.lane);
+  const EphW<NP> W = eph_weights<NP, !ROWB>(E, L.lane);
   {
     double smu, rsmu;
     sqrt_rsqrt(L.mup, smu, rsmu);
