@@ -189,12 +189,33 @@ TPM_DEV bool enc_drift(const EncArgs<NP>& A, double dt, double& x, double& y, do
 // the interpolated planets there.  Either gives the values the lane had when
 // it stopped, bit for bit.  KIT > 0 fixes the Newton count at compile time,
 // as in the particle kernel.
+// encounter_run's parameters in order, for the offsets of the list and the
+// results in its argument segment (see karg_field).
+template <int NP>
+struct EncRunArgs {
+  EncArgs<NP> A;
+  EncList L;
+  const int32_t* snap;
+  EncRing R;
+  Out out;
+};
+
 template <int NP, int KIT>
 __global__ void __launch_bounds__(64)
-encounter_run(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap, EncRing R, Out out) {
+encounter_run(EncArgs<NP> A, EncList L_arg, const int32_t* __restrict__ snap, EncRing R,
+              Out out_arg) {
   constexpr int ROW = 3 * NP + 3;
+  // the list's and the results' pointers are read where they are used (the
+  // entry, a removal, the exit), which leaves the micro-step loop's scalar
+  // registers to its constants
+  (void)L_arg;
+  (void)out_arg;
+  const KargPtr ka = (KargPtr)__builtin_amdgcn_kernarg_segment_ptr();
+  auto list = [&]() { return karg_field<EncList>(ka, offsetof(EncRunArgs<NP>, L)); };
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= *snap || L.status[i] != ST_ACTIVE) return;
+  if (i >= *snap) return;
+  const EncList L = list();
+  if (L.status[i] != ST_ACTIVE) return;
   // chunk c covers steps [cb(c), cb(c + 1)) of the call, cut at its end
   auto cb = [&](int c) -> int64_t {
     const int64_t b = c == 0 ? 0 : R.k0 + (int64_t)(c - 1) * R.k;
@@ -219,13 +240,15 @@ encounter_run(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap, EncRin
   double vx = L.vx[i], vy = L.vy[i], vz = L.vz[i];
   auto remove = [&](int32_t why, int64_t st, int32_t pl, double rx, double ry, double rz,
                     double ux, double uy, double uz) {
-    const int k = L.slot[i];
+    const EncList Lr = list();
+    const Out out = karg_field<Out>(ka, offsetof(EncRunArgs<NP>, out));
+    const int k = Lr.slot[i];
     out.r[3 * k + 0] = rx; out.r[3 * k + 1] = ry; out.r[3 * k + 2] = rz;
     out.v[3 * k + 0] = ux; out.v[3 * k + 1] = uy; out.v[3 * k + 2] = uz;
     out.step[k] = st;
     out.reason[k] = why;
     out.planet[k] = pl;
-    L.status[i] = why;
+    Lr.status[i] = why;
   };
   double ax, ay, az;
   bool enc = false;         // within a hand-off radius at the current step boundary
@@ -319,11 +342,12 @@ encounter_run(EncArgs<NP> A, EncList L, const int32_t* __restrict__ snap, EncRin
       }
     }
   }
-  L.x[i] = x; L.y[i] = y; L.z[i] = z;
-  L.vx[i] = vx; L.vy[i] = vy; L.vz[i] = vz;
-  L.step[i] = R.step0 + cb(c) + s;
-  L.m[i] = m;
-  L.Ml[i] = Ml;
+  const EncList Le = list();
+  Le.x[i] = x; Le.y[i] = y; Le.z[i] = z;
+  Le.vx[i] = vx; Le.vy[i] = vy; Le.vz[i] = vz;
+  Le.step[i] = R.step0 + cb(c) + s;
+  Le.m[i] = m;
+  Le.Ml[i] = Ml;
 }
 
 template <int NP>

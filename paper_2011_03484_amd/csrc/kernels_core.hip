@@ -31,40 +31,14 @@ struct ChunkArgs {
 };
 
 // The work-queue kernel's leading arguments as its argument segment lays them
-// out (particle_queue: w, d_nactive, out, ...).
+// out (particle_queue: w, d_nactive, out, ...); see karg_field.
 struct QueueArgsHead {
   Work w;
   const int32_t* n;
   Out out;
 };
-typedef const __attribute__((address_space(4))) char* KargPtr;
-
-// The argument segment's address, hidden from the compiler where it is used:
-// a load through it then stays at that use, instead of being hoisted to the
-// kernel's start and its result held in scalar registers throughout.
-TPM_DEV KargPtr karg_at_use(KargPtr p) {
-  asm volatile("" : "+s"(p));
-  return p;
-}
-// (The host pass of this source compiles no device code from them.)
-TPM_DEV Work karg_work(KargPtr p) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  return *reinterpret_cast<const __attribute__((address_space(4))) Work*>(
-      karg_at_use(p) + offsetof(QueueArgsHead, w));
-#else
-  (void)p;
-  return Work{};
-#endif
-}
-TPM_DEV Out karg_out(KargPtr p) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  return *reinterpret_cast<const __attribute__((address_space(4))) Out*>(
-      karg_at_use(p) + offsetof(QueueArgsHead, out));
-#else
-  (void)p;
-  return Out{};
-#endif
-}
+TPM_DEV Work karg_work(KargPtr p) { return karg_field<Work>(p, offsetof(QueueArgsHead, w)); }
+TPM_DEV Out karg_out(KargPtr p) { return karg_field<Out>(p, offsetof(QueueArgsHead, out)); }
 
 // Advance particle i of the working set through steps [s_begin, s_end) of a
 // chunk whose rows start at `rows` (row k = step step0 + k; all rows of the

@@ -41,6 +41,32 @@ TPM_DEV void load_row(Row<NP>& R, const double* __restrict__ row, int zero) {
   for (int k = 0; k < 3 * NP + 3; ++k) R.v[k] = row[zero + k];
 }
 
+// A kernel's argument segment, read where a value is used: a kernel that
+// reads rarely used pointer arguments (records, an item's start and end)
+// through karg_field keeps them out of the scalar registers its loops need.
+// The address is hidden from the compiler at each use, so the load stays
+// there instead of being hoisted to the kernel's start.  The offsets come
+// from a struct with the kernel's leading parameters in order, which the
+// argument segment lays out as a C struct.  (The host pass of these sources
+// compiles no device code from them.)
+typedef const __attribute__((address_space(4))) char* KargPtr;
+
+TPM_DEV KargPtr karg_at_use(KargPtr p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+template <typename T>
+TPM_DEV T karg_field(KargPtr p, size_t off) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *reinterpret_cast<const __attribute__((address_space(4))) T*>(karg_at_use(p) + off);
+#else
+  (void)p;
+  (void)off;
+  return T{};
+#endif
+}
+
 // Kick acceleration from one table row (sec. 2.2, kick equation):
 //   a = h0 - sum_j mu_j d_j / |d_j|^3,   d_j = r - r_j,
 // and the encounter test |d_j| < rcrit_j (lowest j wins; -1 if none).
